@@ -1,0 +1,453 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests re-types an oracle formula: each compares the oracle with
+an independent route to the same number (dense integer arithmetic, a library
+routine, brute force over sets, a hand-worked example, a closed form).
+"""
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from synth import CSR, gen_c1, gen_uniform_zipf
+
+
+def rand_csr(rng, m, n, density, integer=False, empty_rows=0.0):
+    D = (rng.random((m, n)) < density).astype(np.float64)
+    if empty_rows:
+        D[rng.random(m) < empty_rows] = 0.0
+    if integer:
+        V = rng.integers(-8, 9, size=(m, n)).astype(np.float64)
+        V[V == 0] = 1.0
+    else:
+        V = rng.uniform(-1, 1, size=(m, n))
+    D = D * V
+    return dense_to_csr(D), D
+
+
+def dense_to_csr(D):
+    m, n = D.shape
+    r, c = np.nonzero(D)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=m), out=rowptr[1:])
+    return CSR(m, n, rowptr, c.astype(np.int32), D[r, c].astype(np.float64))
+
+
+# ---------------------------------------------------------------- products
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 30), st.integers(1, 30), st.floats(0.0, 1.0), st.integers(0, 2**31))
+def test_spmv_integer_exact_vs_dense(orc, m, n, dens, seed):
+    """Small integers make every summation order exact: the CSR row sums must
+    equal the dense integer product bit for bit."""
+    rng = np.random.default_rng(seed)
+    A, D = rand_csr(rng, m, n, dens, integer=True)
+    x = rng.integers(-8, 9, size=n)
+    y = orc.spmv(A, x.astype(np.float64))
+    ref = (D.astype(np.int64) @ x).astype(np.float64)
+    assert np.array_equal(y, ref)
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 40), st.integers(1, 40), st.integers(0, 2**31))
+def test_spmv_float_vs_dense(orc, m, n, seed):
+    rng = np.random.default_rng(seed)
+    A, D = rand_csr(rng, m, n, 0.3)
+    x = rng.uniform(-1, 1, n)
+    y = orc.spmv(A, x)
+    ref = D @ x
+    bound = np.abs(D) @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 1e-14 * bound + 1e-300)
+
+
+def test_spmv_vs_scipy_c1(orc):
+    import scipy.sparse as sp
+    A = gen_c1()
+    x = np.random.default_rng(5).uniform(-1, 1, A.n)
+    S = sp.csr_matrix((A.vals, A.colidx, A.rowptr), shape=(A.m, A.n))
+    y = orc.spmv(A, x)
+    ref = S @ x
+    bound = abs(S) @ np.abs(x)
+    assert np.all(np.abs(y - ref) <= 1e-13 * bound)
+
+
+def test_spmv_special_cases(orc):
+    n = 7
+    I = dense_to_csr(np.eye(n))
+    x = np.arange(n, dtype=np.float64) - 3.5
+    assert np.array_equal(orc.spmv(I, x), x)
+    d = np.array([2.0, -1.0, 0.5, 4.0, 3.0, 1.0, -2.0])
+    assert np.array_equal(orc.spmv(dense_to_csr(np.diag(d)), x), d * x)
+    D = np.zeros((4, 5))
+    D[1, 2] = 3.0
+    y = orc.spmv(dense_to_csr(D), np.ones(5))
+    assert np.array_equal(y, [0.0, 3.0, 0.0, 0.0])
+    # an empty matrix
+    E = CSR(0, 3, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    assert orc.spmv(E, np.ones(3)).size == 0
+
+
+def test_spmv_is_left_to_right(orc):
+    """Rounding reveals the summation order: (1 + 1e16) - 1e16 = 0 in binary64
+    when summed in storage order."""
+    A = CSR(1, 3, np.array([0, 3]), np.array([0, 1, 2], np.int32),
+            np.array([1.0, 1e16, -1e16]))
+    assert orc.spmv(A, np.ones(3))[0] == 0.0
+
+
+def test_spmv_rows_and_abs(orc):
+    rng = np.random.default_rng(3)
+    A, D = rand_csr(rng, 50, 40, 0.2, integer=True)
+    x = rng.integers(-4, 5, size=40).astype(np.float64)
+    rows = np.array([0, 7, 49, 7])
+    y, a = orc.spmv_rows(A, x, rows)
+    assert np.array_equal(y, (D @ x)[rows])
+    assert np.array_equal(a, (np.abs(D) @ np.abs(x))[rows])
+    assert np.array_equal(orc.abs_rowsum(A, x), np.abs(D) @ np.abs(x))
+
+
+def test_spmm_integer(orc):
+    rng = np.random.default_rng(4)
+    A, D = rand_csr(rng, 30, 20, 0.3, integer=True)
+    X = rng.integers(-5, 6, size=(20, 8)).astype(np.float64)
+    assert np.array_equal(orc.spmm(A, X), D @ X)
+
+
+# ------------------------------------------------------------- permutation
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 25), st.integers(1, 25), st.integers(0, 2**31))
+def test_permute_matches_dense(orc, m, n, seed):
+    """A_hat = P_r A P_c with new->old perms is the dense fancy-indexed matrix,
+    and P A Q (Q^T x) = P (A x) exactly on integers (Section 3)."""
+    rng = np.random.default_rng(seed)
+    A, D = rand_csr(rng, m, n, 0.35, integer=True)
+    rp_, cp_ = rng.permutation(m), rng.permutation(n)
+    orp, oci, ov = orc.permute_csr(A, rp_, cp_)
+    H = np.zeros((m, n))
+    for i in range(m):
+        for p in range(orp[i], orp[i + 1]):
+            H[i, oci[p]] = ov[p]
+        assert np.all(np.diff(oci[orp[i]:orp[i + 1]]) > 0)
+    assert np.array_equal(H, D[rp_][:, cp_])
+    x = rng.integers(-8, 9, size=n).astype(np.float64)
+    Ah = CSR(m, n, orp, oci.astype(np.int32), ov)
+    assert np.array_equal(orc.spmv(Ah, x[cp_]), orc.spmv(A, x)[rp_])
+
+
+def test_permute_rejects_non_bijection(orc):
+    A, _ = rand_csr(np.random.default_rng(0), 4, 4, 0.5)
+    with pytest.raises(ValueError):
+        orc.permute_csr(A, np.arange(4), np.array([0, 1, 1, 2]))
+
+
+# ------------------------------------------------------------------- split
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 30), st.integers(1, 30), st.integers(1, 9), st.integers(0, 2**31))
+def test_split_sum_equals_product(orc, m, n, K, seed):
+    """sum_k A^k x = A x for any nonzero-disjoint splitting (Section 4);
+    exact on integers."""
+    rng = np.random.default_rng(seed)
+    A, D = rand_csr(rng, m, n, 0.4, integer=True)
+    part = rng.integers(0, K, size=A.nnz)
+    x = rng.integers(-8, 9, size=n).astype(np.float64)
+    assert np.array_equal(orc.split_spmv(A, part, K, x), D @ x)
+    y0 = rng.integers(-8, 9, size=m).astype(np.float64)
+    assert np.array_equal(orc.split_spmv(A, part, K, x, y0), y0 + D @ x)
+
+
+def test_split_accumulates_part_by_part(orc):
+    """y <- y + A^k x is applied for k = 1..K in turn (Section 4): in binary64
+    (1e16 - 1e16) + 1 = 1 when the two large entries form A^1, while storage
+    order would give (1 + 1e16) - 1e16 = 0."""
+    A = CSR(1, 3, np.array([0, 3]), np.array([0, 1, 2], np.int32),
+            np.array([1.0, 1e16, -1e16]))
+    part = np.array([1, 0, 0])
+    assert orc.split_spmv(A, part, 2, np.ones(3))[0] == 1.0
+    assert orc.split_spmv(A, np.array([0, 0, 0]), 1, np.ones(3))[0] == 0.0
+
+
+def test_split_rejects_bad_part(orc):
+    A, _ = rand_csr(np.random.default_rng(0), 5, 5, 0.6)
+    with pytest.raises(ValueError):
+        orc.split_spmv(A, np.full(A.nnz, 3), 3, np.ones(5))
+
+
+# ---------------------------------------------------------- connectivities
+
+def brute_lambda_cols(D, r2p, K):
+    m, n = D.shape
+    return np.array([len({r2p[i] for i in range(m) if D[i, j] != 0 and 0 <= r2p[i] < K})
+                     for j in range(n)])
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 20), st.integers(1, 20), st.integers(1, 6), st.integers(0, 2**31))
+def test_lambda_cols_brute(orc, m, n, K, seed):
+    rng = np.random.default_rng(seed)
+    A, D = rand_csr(rng, m, n, 0.3)
+    r2p = rng.integers(0, K + 1, size=m)  # value K marks a border row
+    lam = orc.lambda_cols(A, r2p, K)
+    assert np.array_equal(lam, brute_lambda_cols(D, r2p, K))
+    deg = (D != 0).sum(axis=1)
+    assert orc.bound_db(A, r2p, K) == lam.sum() + deg[r2p == K].sum()
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 20), st.integers(1, 20), st.integers(1, 6), st.integers(0, 2**31))
+def test_lambda_split_brute(orc, m, n, K, seed):
+    rng = np.random.default_rng(seed)
+    A, D = rand_csr(rng, m, n, 0.3)
+    part = rng.integers(0, K, size=A.nnz)
+    rows = np.repeat(np.arange(m), np.diff(A.rowptr))
+    lr, lc = orc.lambda_split(A, part, K)
+    for i in range(m):
+        assert lr[i] == len(set(part[rows == i]))
+    for j in range(n):
+        assert lc[j] == len(set(part[A.colidx == j]))
+    assert orc.bound_split(A, part, K) == lr.sum() + lc.sum()
+
+
+def test_lambda_hidden_block_diagonal(orc):
+    """A pure block-diagonal matrix split along its blocks has every column
+    in exactly one row slice: sum_j lambda(c_j) = n (Theorem 1 closed form)."""
+    rng = np.random.default_rng(9)
+    K, bs = 4, 6
+    D = np.zeros((K * bs, K * bs))
+    for k in range(K):
+        blk = rng.uniform(-1, 1, (bs, bs)) * (rng.random((bs, bs)) < 0.5)
+        np.fill_diagonal(blk, 1.0)
+        D[k * bs:(k + 1) * bs, k * bs:(k + 1) * bs] = blk
+    p = rng.permutation(K * bs)
+    Dh = D[p][:, p]
+    A = dense_to_csr(Dh)
+    r2p = (np.arange(K * bs) // bs)[p]
+    assert orc.bound_sb(A, r2p, K) == K * bs
+    # every row in its own part of size one gives the column degrees
+    assert orc.bound_sb(A, np.arange(K * bs), K * bs) == A.nnz
+
+
+def test_bounds_hand_worked():
+    """Hand-worked 4x5 example (Eq. 3, Theorem 1, Theorem 2, Corollary 4).
+
+        row0: c0 c1          part 0
+        row1: c1 c2          part 0
+        row2: c2 c3 c4       part 1
+        row3: c0 c4          part 1 (DB: border row)
+
+    SB (parts {0,1},{2,3}): lambda = c0:2 c1:1 c2:2 c3:1 c4:1 -> sum 7.
+    DB with row 3 in R_B: lambda' = c0:1 c1:1 c2:2 c3:1 c4:1 = 6, plus
+    nnz(row3) = 2 -> 8.
+    Split with parts [0,0 | 0,1 | 1,1,1 | 0,1] (storage order):
+    lambda(r) = 1,2,1,2 -> 6; lambda(c): c0 {0}, c1 {0}, c2 {1}, c3 {1},
+    c4 {1} -> 5; total 11.
+    """
+    import oracle as orc
+    D = np.zeros((4, 5))
+    for i, cs in enumerate([[0, 1], [1, 2], [2, 3, 4], [0, 4]]):
+        D[i, cs] = 1.0
+    A = dense_to_csr(D)
+    assert orc.bound_sb(A, [0, 0, 1, 1], 2) == 7
+    assert orc.bound_db(A, [0, 0, 1, 2], 2) == 8
+    assert orc.bound_split(A, [0, 0, 0, 1, 1, 1, 1, 0, 1], 2) == 11
+
+
+# -------------------------------------------------------- canonical orders
+
+def test_canonical_rowcol_hand_worked(orc):
+    """Same 4x5 matrix, SB with parts {row0,row1}, {row2,row3}, one leaf
+    per part.  Rows keep their order.  Columns: c1 only in part 0 -> C_1;
+    c3, c4 only in part 1 -> C_2; c0, c2 in both -> C_B.  So the new column
+    order is c1 | c3 c4 | c0 c2."""
+    D = np.zeros((4, 5))
+    for i, cs in enumerate([[0, 1], [1, 2], [2, 3, 4], [0, 4]]):
+        D[i, cs] = 1.0
+    A = dense_to_csr(D)
+    c = orc.canonical_rowcol(A, [0, 0, 1, 1], [0, 0, 1, 1], 2)
+    assert list(c["row_perm"]) == [0, 1, 2, 3]
+    assert list(c["col_perm"]) == [1, 3, 4, 0, 2]
+    assert list(c["part_ptr"]) == [0, 2, 4, 4]
+    assert list(c["col_part_ptr"]) == [0, 1, 3, 5]
+    orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
+    assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2) == []
+    # DB with row 3 in the border: c4 is then touched by part 1 only
+    # among part rows, c0 only by part 0 -> c0 c1 | c3 c4 | c2
+    c = orc.canonical_rowcol(A, [0, 0, 1, 2], [0, 0, 1, 0], 2)
+    assert list(c["row_perm"]) == [0, 1, 2, 3]
+    assert list(c["col_perm"]) == [0, 1, 3, 4, 2]
+    orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
+    assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2, db=True) == []
+    assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2, db=False) != []
+
+
+def test_check_sb_flags_violation(orc):
+    """A nonzero of part 0 in part 1's column slice breaks Eq. 1."""
+    D = np.zeros((4, 4))
+    D[0, 0] = D[1, 1] = D[2, 2] = D[3, 3] = 1.0
+    D[0, 2] = 1.0
+    A = dense_to_csr(D)
+    errs = orc.check_sb(A.rowptr, A.colidx, [0, 2, 4, 4], [0, 2, 4, 4], 2)
+    assert errs
+
+
+@settings(max_examples=25, deadline=None)
+@given(st.integers(2, 30), st.integers(2, 30), st.integers(1, 5), st.integers(0, 2**31))
+def test_canonical_rowcol_random_partition(orc, m, n, K, seed):
+    """Any row partition yields a valid SB form after the canonical orders."""
+    rng = np.random.default_rng(seed)
+    A, _ = rand_csr(rng, m, n, 0.25)
+    r2p = rng.integers(0, K, size=m)
+    leaves_per = 2
+    r2leaf = r2p * leaves_per + rng.integers(0, leaves_per, size=m)
+    c = orc.canonical_rowcol(A, r2p, r2leaf, K, nleaves=K * leaves_per)
+    assert sorted(c["row_perm"]) == list(range(m))
+    assert sorted(c["col_perm"]) == list(range(n))
+    orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
+    assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], K) == []
+    # leaf-exclusive column ranges hold only columns of that leaf's rows
+    inv = np.empty(m, np.int64)
+    inv[c["row_perm"]] = np.arange(m)
+    rows = np.repeat(np.arange(m), np.diff(orp))
+    for l in range(K * leaves_per):
+        lo, hi = c["leaf_col_lo"][l], c["leaf_col_hi"][l]
+        sel = (oci >= lo) & (oci < hi)
+        rl, rh = c["leaf_row_ptr"][l], c["leaf_row_ptr"][l + 1]
+        assert np.all((rows[sel] >= rl) & (rows[sel] < rh))
+
+
+def test_canonical_split_and_gcsr(orc):
+    """The per-leaf GCSR of a splitting stores every nonzero once; summing
+    the leaves back gives A_hat (Section 4, nonzero-disjoint parts)."""
+    rng = np.random.default_rng(11)
+    A, D = rand_csr(rng, 25, 30, 0.25)
+    K = 3
+    part = rng.integers(0, K, size=A.nnz)
+    leaf = part * 2 + rng.integers(0, 2, size=A.nnz)
+    c = orc.canonical_split(A, part, leaf, K)
+    assert sorted(c["row_perm"]) == list(range(25))
+    g = orc.split_gcsr(A, leaf, 2 * K, c["row_perm"], c["col_perm"])
+    H = np.zeros_like(D)
+    for s in range(g["slot_row"].size):
+        for p in range(g["slot_ptr"][s], g["slot_ptr"][s + 1]):
+            assert H[g["slot_row"][s], g["colidx"][p]] == 0
+            H[g["slot_row"][s], g["colidx"][p]] = g["vals"][p]
+    assert np.array_equal(H, D[c["row_perm"]][:, c["col_perm"]])
+    # rows spread over several leaves are exactly those from row_shared_begin
+    rows = np.repeat(np.arange(25), np.diff(A.rowptr))
+    nleaf = np.array([len(set(leaf[rows == i])) for i in range(25)])
+    inv = np.empty(25, np.int64)
+    inv[c["row_perm"]] = np.arange(25)
+    rb, re_ = c["row_shared_begin"], c["row_empty_begin"]
+    assert np.all((inv[nleaf > 1] >= rb) & (inv[nleaf > 1] < re_))
+    assert np.all(inv[nleaf == 1] < rb)
+    assert np.all(inv[nleaf == 0] >= re_)
+
+
+# ------------------------------------------------------------ precision
+
+def test_quantization_vs_libraries(orc):
+    import torch
+    rng = np.random.default_rng(2)
+    v = np.concatenate([rng.uniform(-1, 1, 5000), rng.standard_normal(5000) * 1e30,
+                        [0.0, -0.0, 1.0, 3.0e38, 1e-40, 1 + 2.0**-24, 1 + 3 * 2.0**-24]])
+    f = orc.to_f32(v)
+    assert np.array_equal(f.view(np.uint32), v.astype(np.float32).view(np.uint32))
+    h = orc.f32_to_bf16(f)
+    ref = torch.from_numpy(f).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(h, ref)
+    # ties to even: 1 + 2^-8 is halfway between bf16 1.0 and 1 + 2^-7
+    t = np.array([1 + 2.0**-8, 1 + 3 * 2.0**-8], dtype=np.float32)
+    assert list(orc.f32_to_bf16(t)) == [0x3F80, 0x3F82]
+
+
+def test_lowp_spmv_integer_exact(orc):
+    rng = np.random.default_rng(6)
+    A, D = rand_csr(rng, 60, 50, 0.3, integer=True)
+    x = rng.integers(-8, 9, size=50)
+    f = orc.to_f32(A.vals)
+    y32 = orc.spmv_lowp(A, f, x.astype(np.float32))
+    y16 = orc.spmv_lowp(A, None, x.astype(np.float32), vals16=orc.f32_to_bf16(f))
+    ref = (D.astype(np.int64) @ x).astype(np.float32)
+    assert np.array_equal(y32, ref) and np.array_equal(y16, ref)
+
+
+def spd(rng, n, density=0.2):
+    B = rng.uniform(-1, 1, (n, n)) * (rng.random((n, n)) < density)
+    S = B + B.T
+    np.fill_diagonal(S, 0.0)
+    np.fill_diagonal(S, np.abs(S).sum(axis=1) + 1.0)
+    return S
+
+
+def test_cg_and_ir_cg_vs_solve(orc):
+    rng = np.random.default_rng(8)
+    S = spd(rng, 80)
+    A = dense_to_csr(S)
+    xs = np.ones(80)
+    b = S @ xs
+    x, it, rel = orc.cg(lambda v: orc.spmv(A, v), b, 1e-12, 500)
+    ref = np.linalg.solve(S, b)
+    assert np.max(np.abs(x - ref)) < 1e-9
+    f = orc.to_f32(A.vals)
+    x2, outer, inner, rel2 = orc.ir_cg(lambda v: orc.spmv(A, v),
+                                      lambda v: orc.spmv_lowp(A, f, v), b, tol=1e-10)
+    assert rel2 <= 1e-10
+    assert np.linalg.norm(b - S @ x2) / np.linalg.norm(b) <= 1e-10
+    assert np.max(np.abs(x2 - ref)) < 1e-8
+    assert outer >= 2  # binary32 alone cannot reach 1e-10
+
+
+# ------------------------------------------------------------------- MLP
+
+def test_mlp_gradient_finite_differences(orc):
+    rng = np.random.default_rng(12)
+    theta = rng.standard_normal(8344) * 0.2
+    X = rng.standard_normal((7, 40))
+    lab = rng.integers(0, 24, size=7)
+    loss, g = orc.mlp_grad(theta, X, lab)
+    assert abs(loss - orc.mlp_loss(theta, X, lab)) < 1e-12
+    h = 1e-6
+    idx = np.concatenate([rng.choice(8344, 60, replace=False), [0, 2559, 2560, 8343]])
+    for i in idx:
+        e = np.zeros(8344)
+        e[i] = h
+        fd = (orc.mlp_loss(theta + e, X, lab) - orc.mlp_loss(theta - e, X, lab)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), i
+
+
+def test_mlp_forward_and_adam_vs_torch(orc):
+    import torch
+    rng = np.random.default_rng(13)
+    theta = rng.standard_normal(8344) * 0.2
+    X = rng.standard_normal((5, 40))
+    lab = rng.integers(0, 24, size=5)
+    p = orc.mlp_unflatten(theta)
+    net = torch.nn.Sequential(torch.nn.Linear(40, 64), torch.nn.ReLU(),
+                              torch.nn.Linear(64, 64), torch.nn.ReLU(),
+                              torch.nn.Linear(64, 24)).double()
+    with torch.no_grad():
+        for layer, (w, b) in zip([net[0], net[2], net[4]],
+                                 [("W1", "b1"), ("W2", "b2"), ("W3", "b3")]):
+            layer.weight.copy_(torch.from_numpy(p[w]))
+            layer.bias.copy_(torch.from_numpy(p[b]))
+    z = net(torch.from_numpy(X))
+    assert np.allclose(z.detach().numpy(), orc.mlp_forward(theta, X), rtol=0, atol=1e-12)
+    opt = torch.optim.Adam(net.parameters(), lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(8344)
+    v = np.zeros(8344)
+    th = theta.copy()
+    for t in range(1, 4):
+        opt.zero_grad()
+        loss = torch.nn.functional.cross_entropy(net(torch.from_numpy(X)), torch.from_numpy(lab))
+        loss.backward()
+        _, g = orc.mlp_grad(th, X, lab)
+        tg = np.concatenate([net[0].weight.grad.numpy().ravel(), net[0].bias.grad.numpy(),
+                             net[2].weight.grad.numpy().ravel(), net[2].bias.grad.numpy(),
+                             net[4].weight.grad.numpy().ravel(), net[4].bias.grad.numpy()])
+        assert np.allclose(g, tg, rtol=1e-10, atol=1e-13)
+        opt.step()
+        th, m, v = orc.adam_step(th, g, m, v, t)
+    tp = np.concatenate([net[0].weight.detach().numpy().ravel(), net[0].bias.detach().numpy(),
+                         net[2].weight.detach().numpy().ravel(), net[2].bias.detach().numpy(),
+                         net[4].weight.detach().numpy().ravel(), net[4].bias.detach().numpy()])
+    assert np.allclose(th, tp, rtol=0, atol=1e-12)
