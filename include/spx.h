@@ -1,0 +1,255 @@
+/*
+ * spx -- cache-aware sparse matrix-vector products for AMD MI355X (gfx950).
+ *
+ * C interface of the library.  The operations follow Akbudak, Kayaaslan and
+ * Aykanat, "Analyzing and enhancing OSKI for sparse matrix-vector
+ * multiplication" (arXiv 1203.2739):
+ *
+ *   - the CSR product y <- A x (Section 2.1, the CSR scheme);
+ *   - the single-SpMxV framework: the product on A_hat = P_r A P_c in
+ *     singly-bordered form (Section 3.1, Eq. 1-3) or doubly-bordered form
+ *     (Section 3.2, Eq. 5), computed in reordered space, y_hat <- A_hat x_hat;
+ *   - the multiple-SpMxV framework: y <- y + A^k x for k = 1..K over a
+ *     nonzero-disjoint splitting A = A^1 + ... + A^K (Section 4).
+ *
+ * General rules
+ *   - Every function returns SPX_OK (0) or a negative status; no C++
+ *     exception crosses this interface.  spx_last_error() returns a
+ *     thread-local message describing the last failure of the calling thread.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device allocations (for example the data_ptr() of a torch tensor on
+ *     cuda:0).  Host input arrays are copied; the library never keeps them.
+ *   - Index arrays are int32; a matrix may hold at most 2^31 - 64 nonzeros.
+ *   - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *     Products are asynchronous on that stream; a launch failure is reported
+ *     by the call that launches (SPX_EHIP).
+ *   - Handles are immutable after creation apart from spx_plan_retune, so
+ *     products with one plan may run concurrently on different streams as
+ *     long as their output vectors differ.
+ *   - Input and output vectors of one call must not overlap.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spx_status;
+
+#define SPX_OK 0
+#define SPX_EINVAL (-1)       /* invalid argument or malformed matrix        */
+#define SPX_ENOMEM (-2)       /* host or device allocation failed            */
+#define SPX_EHIP (-3)         /* a HIP runtime call failed                   */
+#define SPX_ENOTCONV (-4)     /* iterative solver hit its iteration limit    */
+#define SPX_EUNSUPPORTED (-5) /* the operation does not apply to this handle */
+#define SPX_ENODEVICE (-6)    /* the handle has no device copy               */
+
+typedef struct spx_mat_s *spx_mat;   /* a CSR matrix (host copy, optionally on the device) */
+typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to multiply    */
+
+/* Plan forms. */
+#define SPX_FORM_PLAIN 0 /* CSR in the original order                       */
+#define SPX_FORM_SB 1    /* singly-bordered block-diagonal form, Eq. 1      */
+#define SPX_FORM_DB 2    /* doubly-bordered block-diagonal form, Eq. 5      */
+#define SPX_FORM_SPLIT 3 /* nonzero-disjoint splitting, Section 4           */
+
+/* Kernel schedule.  Any field set to 0 takes the library default.
+ *   wg_size          threads per workgroup: 256, 512 or 1024
+ *   nnz_per_block    nonzeros one workgroup stages per step: 4 or 8 per
+ *                    thread (a multiple of wg_size)
+ *   blocks_per_tile  row blocks one workgroup processes in sequence; the
+ *                    tile's x window is loaded into LDS once per tile
+ *   window_entries   largest LDS x window in binary64 entries (0 = default,
+ *                    -1 = no window); windows are contiguous column ranges
+ *   xcd_remap        1 = map consecutive tiles to the same XCD (default),
+ *                    -1 = hardware dispatch order
+ *   long_row         rows longer than this get a workgroup of their own  */
+typedef struct spx_tune_s {
+    int32_t wg_size;
+    int32_t nnz_per_block;
+    int32_t blocks_per_tile;
+    int32_t window_entries;
+    int32_t xcd_remap;
+    int32_t long_row;
+    int32_t reserved[2];
+} spx_tune;
+
+/* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
+ * (SB: sum_j lambda(c_j)), Theorem 2 (DB: sum_j lambda'(c_j) and
+ * sum over R_B of nnz(r_i)) and Corollary 4 (split: sum_i lambda(r_i) and
+ * sum_j lambda(c_j)), computed for the K top-level parts.                 */
+typedef struct spx_plan_info_s {
+    int32_t form, K, m, n;
+    int64_t nnz;
+    int32_t nleaves, nblocks, ntiles, nslots;
+    int32_t row_border_begin; /* DB: first row of R_B; split: first row shared by leaves */
+    int32_t row_empty_begin;  /* split: first row holding no nonzero (m otherwise) */
+    int32_t col_border_begin; /* SB/DB/split: first column of the column border C_B */
+    int32_t wg_size, nnz_per_block, blocks_per_tile, window_entries;
+    int64_t sum_lambda_col;   /* Thm 1 / Thm 2 first term / Cor 4 column term */
+    int64_t sum_lambda_row;   /* Cor 4 row term (split), 0 otherwise */
+    int64_t border_row_nnz;   /* Thm 2 second term (DB), 0 otherwise */
+    int64_t cut_connectivity; /* sum over nets of cost * (lambda - 1) at the top level */
+    int64_t bytes_matrix;     /* device bytes streamed per product: values, indices, slot tables */
+    int64_t bytes_window;     /* LDS window fill bytes per product (read from x) */
+    int64_t window_nnz;       /* nonzeros whose x entry is read from an LDS window */
+    double partition_seconds; /* host time of the partitioner */
+    double plan_seconds;      /* host time of ordering and table building */
+} spx_plan_info;
+
+const char *spx_last_error(void);
+const char *spx_version(void);
+
+/* Number of host threads the partitioner may use (>= 1).  Results do not
+ * depend on it. */
+spx_status spx_set_num_threads(int32_t nthreads);
+
+/* ----------------------------------------------------------------------
+ * Matrices (Section 2.1: CSR arrays nonzero, colIndex, rowStart).
+ *
+ * rowptr[m+1], colidx[nnz], vals[nnz] are host arrays.  They must satisfy
+ * rowptr[0] = 0, rowptr non-decreasing, rowptr[m] = nnz, 0 <= colidx < n and
+ * column indices strictly increasing inside every row; otherwise SPX_EINVAL.
+ * m, n >= 0.  spx_csr_upload also copies the matrix to the current HIP
+ * device on `stream` and returns after the copy completed;
+ * spx_csr_create_host keeps a host copy only (its plans can be built,
+ * inspected and exported, not multiplied: SPX_ENODEVICE).
+ */
+spx_status spx_csr_upload(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
+                          const int32_t *colidx, const double *vals, void *stream,
+                          spx_mat *out);
+spx_status spx_csr_create_host(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
+                               const int32_t *colidx, const double *vals, spx_mat *out);
+void spx_mat_destroy(spx_mat A);
+
+/* ----------------------------------------------------------------------
+ * Plans.  A plan keeps what it needs of the matrix; destroying the matrix
+ * first is allowed.  `tune` may be NULL.
+ *
+ * spx_plan_plain: the CSR product in the original order (Section 2.1).
+ *
+ * spx_reorder_sb: K-way columnwise SB form (Section 3.1, Eq. 1) found by
+ *   recursive bisection of the column-net hypergraph of A (rows = vertices
+ *   weighted by nnz, columns = unit-cost nets, connectivity cutsize), which
+ *   minimizes the bound of Theorem 1.  K >= 1.
+ * spx_reorder_db: K-way DB form (Section 3.2, Eq. 5) found by recursive
+ *   bisection of the row-column-net hypergraph (nonzeros = vertices; column
+ *   nets of cost 1 under the connectivity metric and split when cut; row nets
+ *   of cost nnz(r_i) under the cut-net metric, removed together with their
+ *   vertices when cut, which sends the row to R_B), minimizing the bound of
+ *   Theorem 2.
+ * spx_split: nonzero-disjoint splitting into K parts (Section 4.1) by
+ *   recursive bisection of the row-column-net hypergraph with the
+ *   connectivity metric on row and column nets, minimizing the bound of
+ *   Corollary 4.  Products then run as y <- y + A^k x.
+ *
+ *   window_bytes > 0 continues the bisection inside each part until every
+ *   leaf's x subvector (split: x and y subvectors) fits window_bytes; leaves
+ *   are the units whose x window is staged in LDS.  0 stops at the K parts.
+ *   seed makes the randomized partitioner reproducible; the result does not
+ *   depend on the thread count.
+ *
+ *   Outputs (caller-allocated host arrays, each may be NULL):
+ *     row_perm[m], col_perm[n]: new -> old, so that
+ *       A_hat[i', j'] = A[row_perm[i'], col_perm[j']],
+ *       x_hat[j'] = x[col_perm[j']], y[row_perm[i']] = y_hat[i'].
+ *     part_ptr: SB [K+1], DB [K+2]: first reordered row of each part; for DB
+ *       part_ptr[K] .. part_ptr[K+1] is the row border R_B.
+ *     nz_part[nnz] (split): part of every nonzero, in A's CSR order.
+ *   Orders (the paper leaves them open): rows by part, then leaf, then
+ *   original index, R_B last; columns of one leaf, then columns shared by
+ *   leaves of one part, then the column border C_B, ties by original index.
+ *   For the split, rows touched by a single leaf come first (by leaf), rows
+ *   shared by leaves follow, empty rows last.
+ */
+spx_status spx_plan_plain(spx_mat A, const spx_tune *tune, spx_plan *out);
+spx_status spx_reorder_sb(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                          int32_t *row_perm, int32_t *col_perm, int32_t *part_ptr,
+                          const spx_tune *tune, spx_plan *out);
+spx_status spx_reorder_db(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                          int32_t *row_perm, int32_t *col_perm, int32_t *part_ptr,
+                          const spx_tune *tune, spx_plan *out);
+spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                     int32_t *row_perm, int32_t *col_perm, int32_t *nz_part,
+                     const spx_tune *tune, spx_plan *out);
+
+/* Rebuild the kernel schedule (row blocks, tiles, windows) of a plan without
+ * repartitioning.  Not thread-safe against products running on the plan. */
+spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
+void spx_plan_destroy(spx_plan P);
+spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info);
+
+/* ----------------------------------------------------------------------
+ * Products (device vectors, binary64).
+ *
+ * spx_spmv: y <- A x for the plain form; y_hat <- A_hat x_hat in reordered
+ *   space for SB/DB (Section 3); for a split plan the same as
+ *   spx_spmv_split with accumulate = 0.  x has n entries, y has m.
+ * spx_spmv_split: y <- y + A^k x for k = 1..K (Section 4) in the split's
+ *   reordered space.  accumulate = 0: y starts at zero (the call zeroes the
+ *   rows shared by several leaves itself and stores the others);
+ *   accumulate = 1: the products are added to the incoming y;
+ *   accumulate = 2: as 0, but the caller has already zeroed the shared rows
+ *   [row_border_begin, m) (spx_split_prepare_y), so only the product kernel
+ *   runs.  Partial results of shared rows are added with binary64 atomics,
+ *   so the rounding of those rows varies from run to run within the error
+ *   bound of reordered summation.
+ * spx_split_prepare_y: y[i] = 0 for the shared rows i >= row_border_begin.
+ * spx_permute_x: x_hat[j'] = x[col_perm[j']] (Section 3).
+ * spx_unpermute_y: y[row_perm[i']] = y_hat[i'].
+ *   Both return SPX_EUNSUPPORTED for the plain form.
+ */
+spx_status spx_spmv(spx_plan P, const double *x, double *y, void *stream);
+spx_status spx_spmv_split(spx_plan P, const double *x, double *y, int32_t accumulate,
+                          void *stream);
+spx_status spx_split_prepare_y(spx_plan P, double *y, void *stream);
+spx_status spx_permute_x(spx_plan P, const double *x, double *x_hat, void *stream);
+spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Inspection (host arrays, caller-allocated; any pointer may be NULL).
+ *
+ * spx_plan_export_csr: the stored matrix of a plain/SB/DB plan in CSR:
+ *   rowptr[m+1], colidx[nnz], vals[nnz] (A itself for plain, A_hat else).
+ * spx_plan_export_split: the per-leaf GCSR storage of a split plan in
+ *   reordered coordinates (GCSR = CSR plus the list of non-empty rows,
+ *   Section 5.2): leaf_slot_ptr[nleaves+1], slot_row[nslots],
+ *   slot_ptr[nslots+1], colidx[nnz], vals[nnz].
+ * spx_plan_export_parts: the partition itself.  SB/DB: r2p[m] (part of each
+ *   original row, K for R_B) and r2leaf[m] (leaf, -1 for R_B).  Split:
+ *   nz_part[nnz] and nz_leaf[nnz] in A's CSR order.
+ * spx_plan_export_perm: row_perm[m], col_perm[n] (identity for plain).
+ * spx_plan_export_sched: blk_slot[nblocks+1] (slot range of each row block)
+ *   and tiles[4*ntiles] = {first block, end block, window first column,
+ *   window length} per tile.
+ */
+spx_status spx_plan_export_csr(spx_plan P, int32_t *rowptr, int32_t *colidx, double *vals);
+spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *slot_row,
+                                 int32_t *slot_ptr, int32_t *colidx, double *vals);
+spx_status spx_plan_export_parts(spx_plan P, int32_t *a, int32_t *b);
+spx_status spx_plan_export_perm(spx_plan P, int32_t *row_perm, int32_t *col_perm);
+spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_slot, int32_t *tiles);
+
+/* ----------------------------------------------------------------------
+ * Measurement helpers.
+ *
+ * spx_stream_read: reads `bytes` bytes of device memory at `src` with 16-byte
+ *   streaming loads and writes one binary64 per workgroup to `sink`
+ *   (sink holds at least spx_stream_sink_len(bytes) entries); the achieved
+ *   bandwidth of this kernel is the read ceiling the SpMV kernels are
+ *   compared with.  bytes must be a multiple of 16.
+ * spx_stream_copy: dst <- src, `bytes` a multiple of 16 (a plain copy of
+ *   known size, used to calibrate memory-traffic counters).
+ */
+int64_t spx_stream_sink_len(int64_t bytes);
+spx_status spx_stream_read(const void *src, int64_t bytes, double *sink, void *stream);
+spx_status spx_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPX_H */

@@ -1,0 +1,404 @@
+"""Python binding of libspx (argument marshalling only).
+
+Every computation runs in the HIP library ``libspx.so`` built from
+``csrc/``; this module converts numpy arrays and torch tensors to pointers and
+raises :class:`SpxError` for a failed call.  Importing works without a GPU;
+loading the library fails loudly if it has not been built.
+
+Function names follow the C interface in ``include/spx.h`` without the
+``spx_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspx.so")
+
+FORM_PLAIN, FORM_SB, FORM_DB, FORM_SPLIT = 0, 1, 2, 3
+FORM_NAMES = {0: "plain", 1: "sb", 2: "db", 3: "split"}
+
+_lib = None
+
+
+class SpxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"spx error {code}: {msg}")
+        self.code = code
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("nnz_per_block", ctypes.c_int32),
+                ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("long_row", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("K", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("nleaves", ctypes.c_int32),
+                ("nblocks", ctypes.c_int32), ("ntiles", ctypes.c_int32), ("nslots", ctypes.c_int32),
+                ("row_border_begin", ctypes.c_int32), ("row_empty_begin", ctypes.c_int32),
+                ("col_border_begin", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("nnz_per_block", ctypes.c_int32), ("blocks_per_tile", ctypes.c_int32),
+                ("window_entries", ctypes.c_int32), ("sum_lambda_col", ctypes.c_int64),
+                ("sum_lambda_row", ctypes.c_int64), ("border_row_nnz", ctypes.c_int64),
+                ("cut_connectivity", ctypes.c_int64), ("bytes_matrix", ctypes.c_int64),
+                ("bytes_window", ctypes.c_int64), ("window_nnz", ctypes.c_int64),
+                ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+_SIGS = {
+    "spx_last_error": ([], ctypes.c_char_p),
+    "spx_version": ([], ctypes.c_char_p),
+    "spx_set_num_threads": ([_I32], _I32),
+    "spx_csr_upload": ([_I32, _I32, _I64, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_csr_create_host": ([_I32, _I32, _I64, _VP, _VP, _VP, _VP], _I32),
+    "spx_mat_destroy": ([_VP], None),
+    "spx_plan_plain": ([_VP, _VP, _VP], _I32),
+    "spx_reorder_sb": ([_VP, _I32, _I64, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_reorder_db": ([_VP, _I32, _I64, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_split": ([_VP, _I32, _I64, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_plan_retune": ([_VP, _VP], _I32),
+    "spx_plan_destroy": ([_VP], None),
+    "spx_plan_info_get": ([_VP, _VP], _I32),
+    "spx_spmv": ([_VP, _VP, _VP, _VP], _I32),
+    "spx_spmv_split": ([_VP, _VP, _VP, _I32, _VP], _I32),
+    "spx_split_prepare_y": ([_VP, _VP, _VP], _I32),
+    "spx_permute_x": ([_VP, _VP, _VP, _VP], _I32),
+    "spx_unpermute_y": ([_VP, _VP, _VP, _VP], _I32),
+    "spx_plan_export_csr": ([_VP, _VP, _VP, _VP], _I32),
+    "spx_plan_export_split": ([_VP, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_plan_export_parts": ([_VP, _VP, _VP], _I32),
+    "spx_plan_export_perm": ([_VP, _VP, _VP], _I32),
+    "spx_plan_export_sched": ([_VP, _VP, _VP], _I32),
+    "spx_stream_sink_len": ([_I64], _I64),
+    "spx_stream_read": ([_VP, _I64, _VP, _VP], _I32),
+    "spx_stream_copy": ([_VP, _VP, _I64, _VP], _I32),
+}
+
+
+def declared_symbols():
+    """Names of the functions declared in include/*.h."""
+    import re
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    names = set()
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            txt = open(os.path.join(inc, f)).read()
+            names |= set(re.findall(r"\b(spx_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def lib():
+    """Load libspx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1203_2739_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _extra_signatures(L)
+        _lib = L
+    return _lib
+
+
+_EXTRA_SIGS = {}
+
+
+def _extra_signatures(L):
+    for name, (args, res) in _EXTRA_SIGS.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+def _check(rc):
+    if rc != 0:
+        raise SpxError(rc, lib().spx_last_error().decode())
+
+
+def last_error():
+    return lib().spx_last_error().decode()
+
+
+def version():
+    return lib().spx_version().decode()
+
+
+def set_num_threads(n):
+    _check(lib().spx_set_num_threads(int(n)))
+
+
+def _host_i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _host_f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _hp(a):
+    return a.ctypes.data_as(_VP) if a is not None else None
+
+
+def _dev(t, dtype=None, numel=None):
+    """Device pointer of a torch tensor (or an integer address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return _VP(t)
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"tensor has {t.numel()} elements, needs {numel}")
+    return _VP(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return _VP(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return _VP(stream)
+    return _VP(stream.cuda_stream)
+
+
+def make_tune(**kw):
+    t = Tune()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
+
+
+class Mat:
+    """A CSR matrix handle (host copy, and a device copy after upload)."""
+
+    def __init__(self, handle, m, n, nnz, on_device):
+        self._h = _VP(handle)
+        self.m, self.n, self.nnz, self.on_device = m, n, nnz, on_device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.spx_mat_destroy(self._h)
+            self._h = None
+
+
+def _csr_args(rowptr, colidx, vals):
+    rowptr = _host_i32(rowptr)
+    colidx = _host_i32(colidx)
+    vals = _host_f64(vals)
+    if colidx.size != vals.size:
+        raise ValueError("colidx and vals differ in length")
+    return rowptr, colidx, vals
+
+
+def csr_upload(m, n, rowptr, colidx, vals, stream=None) -> Mat:
+    """Validate a CSR matrix and copy it to the current device."""
+    rp, ci, v = _csr_args(rowptr, colidx, vals)
+    if rp.size != int(m) + 1:
+        raise ValueError("rowptr must have m + 1 entries")
+    h = _VP()
+    _check(lib().spx_csr_upload(int(m), int(n), int(ci.size), _hp(rp), _hp(ci),
+                                _hp(v), _stream(stream), ctypes.byref(h)))
+    return Mat(h.value, int(m), int(n), int(ci.size), True)
+
+
+def csr_create_host(m, n, rowptr, colidx, vals) -> Mat:
+    """Validate a CSR matrix and keep a host copy only."""
+    rp, ci, v = _csr_args(rowptr, colidx, vals)
+    if rp.size != int(m) + 1:
+        raise ValueError("rowptr must have m + 1 entries")
+    h = _VP()
+    _check(lib().spx_csr_create_host(int(m), int(n), int(ci.size), _hp(rp),
+                                     _hp(ci), _hp(v), ctypes.byref(h)))
+    return Mat(h.value, int(m), int(n), int(ci.size), False)
+
+
+def from_csr(A, device=True, stream=None) -> Mat:
+    """Matrix handle from any object with m, n, rowptr, colidx, vals."""
+    if device:
+        return csr_upload(A.m, A.n, A.rowptr, A.colidx, A.vals, stream)
+    return csr_create_host(A.m, A.n, A.rowptr, A.colidx, A.vals)
+
+
+class Plan:
+    """A matrix in plain, SB, DB or split form."""
+
+    def __init__(self, handle, mat):
+        self._h = _VP(handle)
+        self.mat_dims = (mat.m, mat.n, mat.nnz)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.spx_plan_destroy(self._h)
+            self._h = None
+
+    def info(self) -> dict:
+        i = PlanInfo()
+        _check(lib().spx_plan_info_get(self._h, ctypes.byref(i)))
+        d = {f: getattr(i, f) for f, _ in PlanInfo._fields_}
+        d["form_name"] = FORM_NAMES[d["form"]]
+        return d
+
+    def export_csr(self):
+        m, n, nnz = self.mat_dims
+        rp = np.empty(m + 1, np.int32)
+        ci = np.empty(max(nnz, 1), np.int32)
+        v = np.empty(max(nnz, 1), np.float64)
+        _check(lib().spx_plan_export_csr(self._h, _hp(rp), _hp(ci), _hp(v)))
+        return rp, ci[:nnz], v[:nnz]
+
+    def export_split(self):
+        inf = self.info()
+        L, S, nnz = inf["nleaves"], inf["nslots"], inf["nnz"]
+        lsp = np.empty(L + 1, np.int32)
+        sr = np.empty(max(S, 1), np.int32)
+        sp = np.empty(S + 1, np.int32)
+        ci = np.empty(max(nnz, 1), np.int32)
+        v = np.empty(max(nnz, 1), np.float64)
+        _check(lib().spx_plan_export_split(self._h, _hp(lsp), _hp(sr), _hp(sp), _hp(ci), _hp(v)))
+        return dict(leaf_slot_ptr=lsp, slot_row=sr[:S], slot_ptr=sp, colidx=ci[:nnz], vals=v[:nnz])
+
+    def export_parts(self):
+        inf = self.info()
+        size = inf["nnz"] if inf["form"] == FORM_SPLIT else inf["m"]
+        a = np.empty(max(size, 1), np.int32)
+        b = np.empty(max(size, 1), np.int32)
+        _check(lib().spx_plan_export_parts(self._h, _hp(a), _hp(b)))
+        return a[:size], b[:size]
+
+    def export_perm(self):
+        m, n, _ = self.mat_dims
+        rp = np.empty(max(m, 1), np.int32)
+        cp = np.empty(max(n, 1), np.int32)
+        _check(lib().spx_plan_export_perm(self._h, _hp(rp), _hp(cp)))
+        return rp[:m], cp[:n]
+
+    def export_sched(self):
+        inf = self.info()
+        bs = np.empty(inf["nblocks"] + 1, np.int32)
+        tl = np.empty(max(4 * inf["ntiles"], 1), np.int32)
+        _check(lib().spx_plan_export_sched(self._h, _hp(bs), _hp(tl)))
+        return bs, tl[:4 * inf["ntiles"]].reshape(-1, 4)
+
+
+def _tune_ptr(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        tune = make_tune(**tune)
+    return ctypes.byref(tune)
+
+
+def plan_plain(A: Mat, tune=None) -> Plan:
+    h = _VP()
+    _check(lib().spx_plan_plain(A.handle, _tune_ptr(tune), ctypes.byref(h)))
+    return Plan(h.value, A)
+
+
+def _reorder(fn, A, K, window_bytes, seed, tune, part_len):
+    rp = np.empty(max(A.m, 1), np.int32)
+    cp = np.empty(max(A.n, 1), np.int32)
+    pp = np.empty(max(part_len, 1), np.int32)
+    h = _VP()
+    _check(fn(A.handle, int(K), int(window_bytes), ctypes.c_uint64(int(seed)), _hp(rp), _hp(cp),
+              _hp(pp), _tune_ptr(tune), ctypes.byref(h)))
+    return Plan(h.value, A), rp[:A.m], cp[:A.n], pp[:part_len]
+
+
+def reorder_sb(A: Mat, K, window_bytes=0, seed=0, tune=None):
+    """SB form (Eq. 1): returns (plan, row_perm, col_perm, part_ptr[K+1])."""
+    return _reorder(lib().spx_reorder_sb, A, K, window_bytes, seed, tune, K + 1)
+
+
+def reorder_db(A: Mat, K, window_bytes=0, seed=0, tune=None):
+    """DB form (Eq. 5): returns (plan, row_perm, col_perm, part_ptr[K+2])."""
+    return _reorder(lib().spx_reorder_db, A, K, window_bytes, seed, tune, K + 2)
+
+
+def split(A: Mat, K, window_bytes=0, seed=0, tune=None):
+    """Splitting (Section 4): returns (plan, row_perm, col_perm, nz_part[nnz])."""
+    return _reorder(lib().spx_split, A, K, window_bytes, seed, tune, A.nnz)
+
+
+def plan_retune(P: Plan, tune=None):
+    _check(lib().spx_plan_retune(P.handle, _tune_ptr(tune)))
+
+
+def spmv(P: Plan, x, y, stream=None):
+    """y <- A x (reordered space for SB/DB/split plans)."""
+    import torch
+    m, n, _ = P.mat_dims
+    _check(lib().spx_spmv(P.handle, _dev(x, torch.float64, n), _dev(y, torch.float64, m),
+                          _stream(stream)))
+
+
+def spmv_split(P: Plan, x, y, accumulate=0, stream=None):
+    """y <- y + A^k x for k = 1..K.  accumulate: 0 = y starts at zero,
+    1 = add to y, 2 = y starts at zero and its shared rows are already zero."""
+    import torch
+    m, n, _ = P.mat_dims
+    _check(lib().spx_spmv_split(P.handle, _dev(x, torch.float64, n), _dev(y, torch.float64, m),
+                                int(accumulate), _stream(stream)))
+
+
+def split_prepare_y(P: Plan, y, stream=None):
+    """Zero the rows of y shared by several leaves of a split plan."""
+    import torch
+    m, n, _ = P.mat_dims
+    _check(lib().spx_split_prepare_y(P.handle, _dev(y, torch.float64, m), _stream(stream)))
+
+
+def permute_x(P: Plan, x, x_hat, stream=None):
+    import torch
+    m, n, _ = P.mat_dims
+    _check(lib().spx_permute_x(P.handle, _dev(x, torch.float64, n), _dev(x_hat, torch.float64, n),
+                               _stream(stream)))
+
+
+def unpermute_y(P: Plan, y_hat, y, stream=None):
+    import torch
+    m, n, _ = P.mat_dims
+    _check(lib().spx_unpermute_y(P.handle, _dev(y_hat, torch.float64, m), _dev(y, torch.float64, m),
+                                 _stream(stream)))
+
+
+def stream_sink_len(nbytes):
+    return int(lib().spx_stream_sink_len(int(nbytes)))
+
+
+def stream_read(src, nbytes, sink, stream=None):
+    _check(lib().spx_stream_read(_dev(src), int(nbytes), _dev(sink), _stream(stream)))
+
+
+def stream_copy(src, dst, nbytes, stream=None):
+    _check(lib().spx_stream_copy(_dev(src), _dev(dst), int(nbytes), _stream(stream)))

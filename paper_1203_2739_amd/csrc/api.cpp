@@ -1,0 +1,493 @@
+// C interface of libspx: validation, handles, device residency and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "spx_internal.h"
+
+namespace spx {
+
+thread_local std::string g_err;
+
+void set_last_error(const std::string &msg) { g_err = msg; }
+
+[[noreturn]] void fail(spx_status code, const std::string &msg) { throw Error{code, msg}; }
+
+static void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(SPX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+DevBuf::~DevBuf() {
+    if (ptr) (void)hipFree(ptr);
+}
+
+DevPtr dev_alloc(size_t bytes) {
+    auto b = std::make_shared<DevBuf>();
+    b->bytes = bytes;
+    if (bytes) {
+        hipError_t e = hipMalloc(&b->ptr, bytes);
+        if (e != hipSuccess) {
+            b->ptr = nullptr;
+            (void)hipGetLastError();
+            fail(e == hipErrorOutOfMemory ? SPX_ENOMEM : SPX_EHIP,
+                 std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+    }
+    return b;
+}
+
+DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream) {
+    DevPtr b = dev_alloc(bytes + pad_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    if (bytes) hip_check(hipMemcpyAsync(b->ptr, host, bytes, hipMemcpyHostToDevice, s), "upload");
+    if (pad_bytes)
+        hip_check(hipMemsetAsync((char *)b->ptr + bytes, 0, pad_bytes, s), "upload padding");
+    return b;
+}
+
+Tune resolve_tune(const spx_tune *t, int form) {
+    (void)form;
+    Tune r;
+    if (t) {
+        if (t->wg_size) r.wg = t->wg_size;
+        if (t->nnz_per_block) r.nnz_per_block = t->nnz_per_block;
+        else r.nnz_per_block = 8 * r.wg;
+        if (t->blocks_per_tile) r.blocks_per_tile = t->blocks_per_tile;
+        if (t->window_entries) r.window_entries = t->window_entries;
+        if (t->xcd_remap) r.xcd_remap = t->xcd_remap > 0 ? 1 : 0;
+        if (t->long_row) r.long_row = t->long_row;
+    }
+    if (r.wg != 256 && r.wg != 512 && r.wg != 1024) fail(SPX_EINVAL, "wg_size must be 256, 512 or 1024");
+    if (r.nnz_per_block != 4 * r.wg && r.nnz_per_block != 8 * r.wg)
+        fail(SPX_EINVAL, "nnz_per_block must be 4 or 8 times wg_size");
+    if (r.blocks_per_tile < 1) fail(SPX_EINVAL, "blocks_per_tile must be >= 1");
+    if (r.long_row < 1) fail(SPX_EINVAL, "long_row must be >= 1");
+    if (r.window_entries < 0) r.window_entries = -1;
+    int wmax = 0;
+    if (!spmv_variant_exists(r.wg, r.nnz_per_block / r.wg, r.window_entries, &wmax))
+        fail(SPX_EUNSUPPORTED, "no kernel variant for this wg_size / nnz_per_block / window");
+    return r;
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+template <class F>
+static spx_status guarded(F f) {
+    try {
+        f();
+        return SPX_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return SPX_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return SPX_EINVAL;
+    } catch (...) {
+        set_last_error("unknown error");
+        return SPX_EINVAL;
+    }
+}
+
+
+static constexpr size_t kPadEntries = 16;
+
+static void validate_csr(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
+                         const int32_t *colidx, const double *vals) {
+    if (m < 0 || n < 0) fail(SPX_EINVAL, "negative dimension");
+    if (nnz < 0 || nnz > (int64_t)INT32_MAX - 64) fail(SPX_EINVAL, "nnz out of range");
+    if (!rowptr) fail(SPX_EINVAL, "rowptr is NULL");
+    if (nnz > 0 && (!colidx || !vals)) fail(SPX_EINVAL, "colidx or vals is NULL");
+    if (rowptr[0] != 0) fail(SPX_EINVAL, "rowptr[0] != 0");
+    if ((int64_t)rowptr[m] != nnz) fail(SPX_EINVAL, "rowptr[m] != nnz");
+    for (int32_t i = 0; i < m; ++i) {
+        if (rowptr[i + 1] < rowptr[i]) fail(SPX_EINVAL, "rowptr decreases at row " + std::to_string(i));
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int32_t c = colidx[p];
+            if (c < 0 || c >= n) fail(SPX_EINVAL, "column index out of range in row " + std::to_string(i));
+            if (p > rowptr[i] && colidx[p - 1] >= c)
+                fail(SPX_EINVAL, "column indices not strictly increasing in row " + std::to_string(i));
+        }
+    }
+}
+
+static spx_mat_s *make_mat(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
+                           const int32_t *colidx, const double *vals) {
+    validate_csr(m, n, nnz, rowptr, colidx, vals);
+    auto *A = new spx_mat_s();
+    A->h.m = m;
+    A->h.n = n;
+    A->h.nnz = nnz;
+    A->h.rowptr.assign(rowptr, rowptr + m + 1);
+    if (nnz) {
+        A->h.colidx.assign(colidx, colidx + nnz);
+        A->h.vals.assign(vals, vals + nnz);
+    }
+    return A;
+}
+
+static void upload_mat(spx_mat_s &A, void *stream) {
+    const CsrHost &h = A.h;
+    A.d_rowptr = dev_upload(h.rowptr.data(), h.rowptr.size() * 4, 0, stream);
+    A.d_colidx = dev_upload(h.colidx.data(), h.colidx.size() * 4, kPadEntries * 4, stream);
+    A.d_vals = dev_upload(h.vals.data(), h.vals.size() * 8, kPadEntries * 8, stream);
+    hip_check(hipStreamSynchronize((hipStream_t)stream), "upload");
+    A.on_device = true;
+}
+
+namespace spx {
+void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream) {
+    if (!A.on_device) {
+        P.on_device = false;
+        return;
+    }
+    if (P.form == SPX_FORM_PLAIN) {
+        P.d_slot_ptr = A.d_rowptr;
+        P.d_colidx = A.d_colidx;
+        P.d_vals = A.d_vals;
+    } else {
+        P.d_slot_ptr = dev_upload(P.slot_ptr.data(), P.slot_ptr.size() * 4, 0, stream);
+        P.d_colidx = dev_upload(P.colidx.data(), P.colidx.size() * 4, kPadEntries * 4, stream);
+        P.d_vals = dev_upload(P.vals.data(), P.vals.size() * 8, kPadEntries * 8, stream);
+        if (!P.slot_row.empty())
+            P.d_slot_row = dev_upload(P.slot_row.data(), P.slot_row.size() * 4, 0, stream);
+        if (!P.row_perm.empty())
+            P.d_row_perm = dev_upload(P.row_perm.data(), P.row_perm.size() * 4, 0, stream);
+        if (!P.col_perm.empty())
+            P.d_col_perm = dev_upload(P.col_perm.data(), P.col_perm.size() * 4, 0, stream);
+    }
+    P.d_blk_slot = dev_upload(P.blk_slot.data(), P.blk_slot.size() * 4, 0, stream);
+    P.d_tiles = dev_upload(P.tiles.data(), P.tiles.size() * 4, 16, stream);
+    hip_check(hipStreamSynchronize((hipStream_t)stream), "plan upload");
+    P.on_device = true;
+}
+}  // namespace spx
+
+static void apply_tune(spx_plan_s &P, const spx_tune *tune, int64_t window_bytes) {
+    spx_tune t{};
+    if (tune) t = *tune;
+    if (!tune || t.window_entries == 0) {
+        // default: the partition's window budget, when one was given
+        t.window_entries = window_bytes > 0 ? (int32_t)std::min<int64_t>(window_bytes / 8, 12288) : -1;
+    }
+    if ((!tune || t.blocks_per_tile == 0) && t.window_entries > 0) t.blocks_per_tile = 4;
+    if (t.window_entries > 0 && (!tune || t.wg_size == 0)) {
+        t.wg_size = t.window_entries > 8192 ? 1024 : (t.window_entries > 4096 ? 512 : 256);
+        t.nnz_per_block = t.wg_size == 1024 ? 4096 : 8 * t.wg_size;
+    }
+    P.tune = resolve_tune(&t, P.form);
+    build_schedule(P);
+}
+
+static void write_outputs(const spx_plan_s &P, int32_t *row_perm, int32_t *col_perm) {
+    if (row_perm) std::copy(P.row_perm.begin(), P.row_perm.end(), row_perm);
+    if (col_perm) std::copy(P.col_perm.begin(), P.col_perm.end(), col_perm);
+}
+
+static spx_status build_reordered(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                                  Model model, int32_t *row_perm, int32_t *col_perm,
+                                  int32_t *part_out, const spx_tune *tune, spx_plan *out) {
+    return guarded([&] {
+        if (!A || !out) fail(SPX_EINVAL, "NULL handle");
+        if (K < 1) fail(SPX_EINVAL, "K must be >= 1");
+        if (window_bytes < 0) fail(SPX_EINVAL, "window_bytes must be >= 0");
+        *out = nullptr;
+        std::unique_ptr<spx_plan_s> P(new spx_plan_s());
+        P->K = K;
+        const CsrHost &h = A->h;
+        PartitionResult r = partition(h, model, K, window_bytes / 8, seed);
+        if (model == Model::ColumnNet) plan_from_rowparts(*P, h, r, false);
+        else if (model == Model::ERowColumnNet) plan_from_rowparts(*P, h, r, true);
+        else plan_from_split(*P, h, r);
+        apply_tune(*P, tune, window_bytes);
+        upload_plan(*P, *A, nullptr);
+        write_outputs(*P, row_perm, col_perm);
+        if (part_out) {
+            if (model == Model::RowColumnNet) std::copy(P->part_a.begin(), P->part_a.end(), part_out);
+            else std::copy(P->part_ptr.begin(), P->part_ptr.begin() + (model == Model::ColumnNet ? K + 1 : K + 2), part_out);
+        }
+        *out = P.release();
+    });
+}
+
+static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t accumulate,
+                              hipStream_t s) {
+    SpmvArgs a{};
+    a.slot_ptr = (const int32_t *)P.d_slot_ptr->ptr;
+    a.slot_row = P.d_slot_row ? (const int32_t *)P.d_slot_row->ptr : nullptr;
+    a.colidx = (const int32_t *)P.d_colidx->ptr;
+    a.vals = (const double *)P.d_vals->ptr;
+    a.x = x;
+    a.y = y;
+    a.blk_slot = (const int32_t *)P.d_blk_slot->ptr;
+    a.tiles = (const int32_t *)P.d_tiles->ptr;
+    a.ntiles = (int32_t)(P.tiles.size() / 4);
+    a.xcd_remap = P.tune.xcd_remap;
+    bool split = P.form == SPX_FORM_SPLIT;
+    if (split) {
+        a.shared_begin = P.row_border_begin;
+        a.accumulate = accumulate == 1 ? 1 : 0;
+        if (accumulate == 0) {
+            hipError_t e = launch_fill(y, P.row_border_begin, P.m, 0.0, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return launch_spmv(a, P.tune.wg, P.tune.nnz_per_block / P.tune.wg, P.tune.window_entries, split, s);
+}
+
+extern "C" {
+
+const char *spx_last_error(void) { return spx::g_err.c_str(); }
+
+const char *spx_version(void) { return "spx 0.1 (gfx950)"; }
+
+spx_status spx_set_num_threads(int32_t nthreads) {
+    return guarded([&] {
+        if (nthreads < 1) fail(SPX_EINVAL, "nthreads must be >= 1");
+        set_num_threads(nthreads);
+    });
+}
+
+spx_status spx_csr_create_host(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
+                               const int32_t *colidx, const double *vals, spx_mat *out) {
+    return guarded([&] {
+        if (!out) fail(SPX_EINVAL, "out is NULL");
+        *out = make_mat(m, n, nnz, rowptr, colidx, vals);
+    });
+}
+
+spx_status spx_csr_upload(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
+                          const int32_t *colidx, const double *vals, void *stream, spx_mat *out) {
+    return guarded([&] {
+        if (!out) fail(SPX_EINVAL, "out is NULL");
+        *out = nullptr;
+        std::unique_ptr<spx_mat_s> A(make_mat(m, n, nnz, rowptr, colidx, vals));
+        upload_mat(*A, stream);
+        *out = A.release();
+    });
+}
+
+void spx_mat_destroy(spx_mat A) { delete A; }
+
+spx_status spx_plan_plain(spx_mat A, const spx_tune *tune, spx_plan *out) {
+    return guarded([&] {
+        if (!A || !out) fail(SPX_EINVAL, "NULL handle");
+        *out = nullptr;
+        std::unique_ptr<spx_plan_s> P(new spx_plan_s());
+        plan_plain(*P, A->h);
+        apply_tune(*P, tune, 0);
+        upload_plan(*P, *A, nullptr);
+        *out = P.release();
+    });
+}
+
+spx_status spx_reorder_sb(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                          int32_t *row_perm, int32_t *col_perm, int32_t *part_ptr,
+                          const spx_tune *tune, spx_plan *out) {
+    return build_reordered(A, K, window_bytes, seed, Model::ColumnNet, row_perm, col_perm,
+                           part_ptr, tune, out);
+}
+
+spx_status spx_reorder_db(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                          int32_t *row_perm, int32_t *col_perm, int32_t *part_ptr,
+                          const spx_tune *tune, spx_plan *out) {
+    return build_reordered(A, K, window_bytes, seed, Model::ERowColumnNet, row_perm, col_perm,
+                           part_ptr, tune, out);
+}
+
+spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
+                     int32_t *row_perm, int32_t *col_perm, int32_t *nz_part,
+                     const spx_tune *tune, spx_plan *out) {
+    return build_reordered(A, K, window_bytes, seed, Model::RowColumnNet, row_perm, col_perm,
+                           nz_part, tune, out);
+}
+
+spx_status spx_plan_retune(spx_plan P, const spx_tune *tune) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        spx_plan_s tmp;  // validate before touching the plan
+        tmp.form = P->form;
+        spx_tune t{};
+        if (tune) t = *tune;
+        if (t.window_entries == 0) t.window_entries = -1;
+        Tune r = resolve_tune(&t, P->form);
+        P->tune = r;
+        build_schedule(*P);
+        if (P->on_device) {
+            P->d_blk_slot = dev_upload(P->blk_slot.data(), P->blk_slot.size() * 4, 0, nullptr);
+            P->d_tiles = dev_upload(P->tiles.data(), P->tiles.size() * 4, 16, nullptr);
+            hip_check(hipStreamSynchronize(nullptr), "retune upload");
+        }
+    });
+}
+
+void spx_plan_destroy(spx_plan P) { delete P; }
+
+spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
+    return guarded([&] {
+        if (!P || !info) fail(SPX_EINVAL, "NULL argument");
+        std::memset(info, 0, sizeof(*info));
+        info->form = P->form;
+        info->K = P->K;
+        info->m = P->m;
+        info->n = P->n;
+        info->nnz = P->nnz;
+        info->nleaves = P->nleaves;
+        info->nblocks = (int32_t)P->blk_slot.size() - 1;
+        info->ntiles = (int32_t)(P->tiles.size() / 4);
+        info->nslots = (int32_t)P->slot_ptr.size() - 1;
+        info->row_border_begin = P->row_border_begin;
+        info->row_empty_begin = P->row_empty_begin;
+        info->col_border_begin = P->col_border_begin;
+        info->wg_size = P->tune.wg;
+        info->nnz_per_block = P->tune.nnz_per_block;
+        info->blocks_per_tile = P->tune.blocks_per_tile;
+        info->window_entries = P->tune.window_entries;
+        info->sum_lambda_col = P->sum_lambda_col;
+        info->sum_lambda_row = P->sum_lambda_row;
+        info->border_row_nnz = P->border_row_nnz;
+        info->cut_connectivity = P->cut;
+        info->bytes_matrix = 12 * P->nnz + 4 * (int64_t)P->slot_ptr.size() +
+                             4 * (int64_t)P->slot_row.size() + 4 * (int64_t)P->blk_slot.size() +
+                             4 * (int64_t)P->tiles.size();
+        info->bytes_window = P->window_bytes_fill;
+        info->window_nnz = P->window_nnz;
+        info->partition_seconds = P->partition_seconds;
+        info->plan_seconds = P->plan_seconds;
+    });
+}
+
+spx_status spx_spmv(spx_plan P, const double *x, double *y, void *stream) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy (host-only matrix)");
+        if (P->m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
+        if (P->nnz > 0 && !x) fail(SPX_EINVAL, "x is NULL");
+        hip_check(run_product(*P, x, y, 0, (hipStream_t)stream), "spmv launch");
+    });
+}
+
+spx_status spx_spmv_split(spx_plan P, const double *x, double *y, int32_t accumulate, void *stream) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form != SPX_FORM_SPLIT) fail(SPX_EUNSUPPORTED, "not a split plan");
+        if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy (host-only matrix)");
+        if (P->m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
+        if (P->nnz > 0 && !x) fail(SPX_EINVAL, "x is NULL");
+        if (accumulate < 0 || accumulate > 2) fail(SPX_EINVAL, "accumulate must be 0, 1 or 2");
+        hip_check(run_product(*P, x, y, accumulate, (hipStream_t)stream), "spmv_split launch");
+    });
+}
+
+spx_status spx_split_prepare_y(spx_plan P, double *y, void *stream) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form != SPX_FORM_SPLIT) fail(SPX_EUNSUPPORTED, "not a split plan");
+        if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");
+        if (P->m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
+        hip_check(launch_fill(y, P->row_border_begin, P->m, 0.0, (hipStream_t)stream), "prepare_y launch");
+    });
+}
+
+spx_status spx_permute_x(spx_plan P, const double *x, double *x_hat, void *stream) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form == SPX_FORM_PLAIN) fail(SPX_EUNSUPPORTED, "plain plans are not reordered");
+        if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");
+        if (P->n > 0 && (!x || !x_hat)) fail(SPX_EINVAL, "NULL vector");
+        hip_check(launch_gather(x, (const int32_t *)P->d_col_perm->ptr, x_hat, P->n, (hipStream_t)stream),
+                  "permute_x launch");
+    });
+}
+
+spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *stream) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form == SPX_FORM_PLAIN) fail(SPX_EUNSUPPORTED, "plain plans are not reordered");
+        if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");
+        if (P->m > 0 && (!y || !y_hat)) fail(SPX_EINVAL, "NULL vector");
+        hip_check(launch_scatter(y_hat, (const int32_t *)P->d_row_perm->ptr, y, P->m, (hipStream_t)stream),
+                  "unpermute_y launch");
+    });
+}
+
+spx_status spx_plan_export_csr(spx_plan P, int32_t *rowptr, int32_t *colidx, double *vals) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form == SPX_FORM_SPLIT) fail(SPX_EUNSUPPORTED, "split plans store per-leaf GCSR");
+        if (rowptr) std::copy(P->slot_ptr.begin(), P->slot_ptr.end(), rowptr);
+        if (colidx) std::copy(P->colidx.begin(), P->colidx.end(), colidx);
+        if (vals) std::copy(P->vals.begin(), P->vals.end(), vals);
+    });
+}
+
+spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *slot_row,
+                                 int32_t *slot_ptr, int32_t *colidx, double *vals) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form != SPX_FORM_SPLIT) fail(SPX_EUNSUPPORTED, "not a split plan");
+        if (leaf_slot_ptr) std::copy(P->leaf_slot_ptr.begin(), P->leaf_slot_ptr.end(), leaf_slot_ptr);
+        if (slot_row) std::copy(P->slot_row.begin(), P->slot_row.end(), slot_row);
+        if (slot_ptr) std::copy(P->slot_ptr.begin(), P->slot_ptr.end(), slot_ptr);
+        if (colidx) std::copy(P->colidx.begin(), P->colidx.end(), colidx);
+        if (vals) std::copy(P->vals.begin(), P->vals.end(), vals);
+    });
+}
+
+spx_status spx_plan_export_parts(spx_plan P, int32_t *a, int32_t *b) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form == SPX_FORM_PLAIN) fail(SPX_EUNSUPPORTED, "plain plans have no partition");
+        if (a) std::copy(P->part_a.begin(), P->part_a.end(), a);
+        if (b) std::copy(P->part_b.begin(), P->part_b.end(), b);
+    });
+}
+
+spx_status spx_plan_export_perm(spx_plan P, int32_t *row_perm, int32_t *col_perm) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (P->form == SPX_FORM_PLAIN) {
+            for (int32_t i = 0; row_perm && i < P->m; ++i) row_perm[i] = i;
+            for (int32_t j = 0; col_perm && j < P->n; ++j) col_perm[j] = j;
+            return;
+        }
+        write_outputs(*P, row_perm, col_perm);
+    });
+}
+
+spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_slot, int32_t *tiles) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (blk_slot) std::copy(P->blk_slot.begin(), P->blk_slot.end(), blk_slot);
+        if (tiles) std::copy(P->tiles.begin(), P->tiles.end(), tiles);
+    });
+}
+
+int64_t spx_stream_sink_len(int64_t bytes) { return bytes > 0 ? stream_grid(bytes) : 0; }
+
+spx_status spx_stream_read(const void *src, int64_t bytes, double *sink, void *stream) {
+    return guarded([&] {
+        if (bytes < 0 || bytes % 16) fail(SPX_EINVAL, "bytes must be a non-negative multiple of 16");
+        if (bytes && (!src || !sink)) fail(SPX_EINVAL, "NULL pointer");
+        hip_check(launch_stream_read(src, bytes, sink, (hipStream_t)stream), "stream_read launch");
+    });
+}
+
+spx_status spx_stream_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+    return guarded([&] {
+        if (bytes < 0 || bytes % 16) fail(SPX_EINVAL, "bytes must be a non-negative multiple of 16");
+        if (bytes && (!src || !dst)) fail(SPX_EINVAL, "NULL pointer");
+        hip_check(launch_stream_copy(src, dst, bytes, (hipStream_t)stream), "stream_copy launch");
+    });
+}
+
+}  // extern "C"

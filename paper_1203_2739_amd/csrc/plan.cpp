@@ -1,0 +1,450 @@
+// Plan construction: canonical row/column orders of the SB, DB and split
+// forms, the reordered storage, and the kernel schedule.
+//
+// Orders (the paper fixes the block structure of Eq. 1 and Eq. 5 but not the
+// order inside a block): rows by part, then by leaf, then by original index,
+// with the row border R_B last (DB).  A column touched (by part rows) from a
+// single leaf goes with that leaf; one touched from several leaves of a
+// single part follows that part's leaf columns; every other column -- touched
+// from several parts, or from none -- forms the column border C_B at the end.
+// The split orders rows the same way over the leaves of their nonzeros, with
+// rows spread over several leaves after all single-leaf rows and empty rows
+// last, so that the rows needing atomic accumulation form one range.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <future>
+#include <numeric>
+
+#include "spx_internal.h"
+
+namespace spx {
+
+namespace {
+
+// Stable counting sort of 0..cnt-1 by bucket.
+std::vector<int32_t> counting_order(const std::vector<int32_t> &bucket, int32_t nb) {
+    std::vector<int64_t> off((size_t)nb + 1, 0);
+    for (int32_t b : bucket) off[b + 1]++;
+    for (int32_t b = 0; b < nb; ++b) off[b + 1] += off[b];
+    std::vector<int32_t> out(bucket.size());
+    for (size_t i = 0; i < bucket.size(); ++i) out[off[bucket[i]]++] = (int32_t)i;
+    return out;
+}
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+    int32_t T = num_threads();
+    if (n < 4096 || T <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::future<void>> futs;
+    int64_t chunk = (n + T - 1) / T;
+    for (int32_t t = 0; t < T; ++t) {
+        int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+        if (lo >= hi) break;
+        futs.push_back(std::async(std::launch::async, [&f, lo, hi] { f(lo, hi); }));
+    }
+    for (auto &x : futs) x.get();
+}
+
+// Column classes from (row-of-nonzero labels).  leaf_of/part_of give the
+// labels of every nonzero of A that counts (label < 0: ignored).
+struct ColClass {
+    std::vector<int32_t> first_leaf, first_part;
+    std::vector<uint8_t> multi_leaf, multi_part;
+};
+
+std::vector<int32_t> column_order(int32_t n, int32_t K, int32_t nleaves,
+                                  const std::vector<int32_t> &leaf_lo_of_part,
+                                  const ColClass &cc, int32_t &border_begin) {
+    std::vector<int32_t> bucket(n);
+    for (int32_t j = 0; j < n; ++j) {
+        int32_t p = cc.first_part[j];
+        if (p < 0 || cc.multi_part[j]) bucket[j] = nleaves + K;
+        else if (cc.multi_leaf[j]) bucket[j] = leaf_lo_of_part[p + 1] + p;
+        else bucket[j] = cc.first_leaf[j] + p;
+    }
+    std::vector<int32_t> order = counting_order(bucket, nleaves + K + 1);
+    border_begin = n;
+    for (int32_t t = 0; t < n; ++t)
+        if (bucket[order[t]] == nleaves + K) { border_begin = t; break; }
+    return order;
+}
+
+void leaf_column_ranges(spx_plan_s &P, const std::vector<int32_t> &col_perm,
+                        const ColClass &cc) {
+    P.leaf_col_lo.assign(P.nleaves, 0);
+    P.leaf_col_hi.assign(P.nleaves, 0);
+    std::vector<uint8_t> seen(P.nleaves, 0);
+    for (int32_t t = 0; t < (int32_t)col_perm.size(); ++t) {
+        int32_t j = col_perm[t];
+        if (cc.first_part[j] < 0 || cc.multi_part[j] || cc.multi_leaf[j]) continue;
+        int32_t l = cc.first_leaf[j];
+        if (!seen[l]) { seen[l] = 1; P.leaf_col_lo[l] = t; }
+        P.leaf_col_hi[l] = t + 1;
+    }
+}
+
+void permuted_rows(spx_plan_s &P, const CsrHost &A, const std::vector<int32_t> &inv_col) {
+    int32_t m = A.m;
+    P.slot_ptr.assign((size_t)m + 1, 0);
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t r = P.row_perm[i];
+        P.slot_ptr[i + 1] = P.slot_ptr[i] + (A.rowptr[r + 1] - A.rowptr[r]);
+    }
+    P.colidx.resize(A.nnz);
+    P.vals.resize(A.nnz);
+    parallel_for(m, [&](int64_t lo, int64_t hi) {
+        std::vector<std::pair<int32_t, int32_t>> buf;
+        for (int64_t i = lo; i < hi; ++i) {
+            int32_t r = P.row_perm[i];
+            buf.clear();
+            for (int32_t p = A.rowptr[r]; p < A.rowptr[r + 1]; ++p)
+                buf.emplace_back(inv_col[A.colidx[p]], p);
+            std::sort(buf.begin(), buf.end());
+            int32_t o = P.slot_ptr[i];
+            for (size_t t = 0; t < buf.size(); ++t) {
+                P.colidx[o + t] = buf[t].first;
+                P.vals[o + t] = A.vals[buf[t].second];
+            }
+        }
+    });
+}
+
+}  // namespace
+
+void plan_plain(spx_plan_s &P, const CsrHost &A) {
+    P.form = SPX_FORM_PLAIN;
+    P.K = 1;
+    P.m = A.m;
+    P.n = A.n;
+    P.nnz = A.nnz;
+    P.slot_ptr = A.rowptr;
+    P.colidx = A.colidx;
+    P.vals = A.vals;
+    P.nleaves = 1;
+    P.leaf_slot_ptr = {0, A.m};
+    P.leaf_col_lo = {0};
+    P.leaf_col_hi = {0};
+    P.part_ptr = {0, A.m};
+    P.row_border_begin = A.m;
+    P.row_empty_begin = A.m;
+    P.col_border_begin = A.n;
+}
+
+void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &r, bool db) {
+    auto t0 = std::chrono::steady_clock::now();
+    int32_t m = A.m, n = A.n, K = P.K;
+    P.m = m;
+    P.n = n;
+    P.nnz = A.nnz;
+    P.form = db ? SPX_FORM_DB : SPX_FORM_SB;
+    P.part_a = r.part;
+    P.part_b = r.leaf;
+    P.nleaves = r.nleaves;
+    int32_t L = r.nleaves;
+    // leaves are numbered part-major: first leaf of every part
+    std::vector<int32_t> leaf_part(L, 0);
+    for (int32_t i = 0; i < m; ++i)
+        if (r.part[i] < K) leaf_part[r.leaf[i]] = r.part[i];
+    std::vector<int32_t> leaf_lo_of_part(K + 1, 0);
+    {
+        std::vector<int32_t> cnt(K + 1, 0);
+        for (int32_t l = 0; l < L; ++l) cnt[leaf_part[l] + 1]++;
+        for (int32_t k = 0; k < K; ++k) leaf_lo_of_part[k + 1] = leaf_lo_of_part[k] + cnt[k + 1];
+    }
+    // rows: by leaf (border rows last), stable
+    std::vector<int32_t> rb(m);
+    for (int32_t i = 0; i < m; ++i) rb[i] = (r.part[i] >= K) ? L : r.leaf[i];
+    P.row_perm = counting_order(rb, L + 1);
+    // columns
+    ColClass cc;
+    cc.first_leaf.assign(n, -1);
+    cc.first_part.assign(n, -1);
+    cc.multi_leaf.assign(n, 0);
+    cc.multi_part.assign(n, 0);
+    for (int32_t i = 0; i < m; ++i) {
+        if (r.part[i] >= K) continue;
+        int32_t p = r.part[i], l = r.leaf[i];
+        for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+            int32_t j = A.colidx[q];
+            if (cc.first_part[j] < 0) { cc.first_part[j] = p; cc.first_leaf[j] = l; }
+            else {
+                if (cc.first_part[j] != p) cc.multi_part[j] = 1;
+                if (cc.first_leaf[j] != l) cc.multi_leaf[j] = 1;
+            }
+        }
+    }
+    int32_t cb = n;
+    P.col_perm = column_order(n, K, L, leaf_lo_of_part, cc, cb);
+    P.col_border_begin = cb;
+    std::vector<int32_t> inv_col(n);
+    for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;
+    permuted_rows(P, A, inv_col);
+    // parts and leaves in the new row order
+    P.part_ptr.assign(K + 2, 0);
+    for (int32_t i = 0; i < m; ++i) P.part_ptr[std::min(r.part[i], K) + 1]++;
+    for (int32_t k = 0; k <= K; ++k) P.part_ptr[k + 1] += P.part_ptr[k];
+    P.row_border_begin = P.part_ptr[K];
+    P.row_empty_begin = m;
+    P.leaf_slot_ptr.assign(L + 1, 0);
+    for (int32_t i = 0; i < m; ++i)
+        if (r.part[i] < K) P.leaf_slot_ptr[r.leaf[i] + 1]++;
+    for (int32_t l = 0; l < L; ++l) P.leaf_slot_ptr[l + 1] += P.leaf_slot_ptr[l];
+    leaf_column_ranges(P, P.col_perm, cc);
+    // Theorem 1 / Theorem 2 quantities
+    std::vector<int32_t> mark(n, -1);
+    int64_t lam = 0, bnnz = 0;
+    for (int32_t t = 0; t < m; ++t) {
+        int32_t i = P.row_perm[t];
+        if (r.part[i] >= K) {
+            bnnz += A.rowptr[i + 1] - A.rowptr[i];
+            continue;
+        }
+        for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+            int32_t j = A.colidx[q];
+            if (mark[j] != r.part[i]) { mark[j] = r.part[i]; ++lam; }
+        }
+    }
+    P.sum_lambda_col = lam;
+    P.border_row_nnz = db ? bnnz : 0;
+    P.cut = r.cut;
+    P.partition_seconds = r.seconds;
+    P.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) {
+    auto t0 = std::chrono::steady_clock::now();
+    int32_t m = A.m, n = A.n, K = P.K;
+    int64_t nnz = A.nnz;
+    P.m = m;
+    P.n = n;
+    P.nnz = nnz;
+    P.form = SPX_FORM_SPLIT;
+    P.part_a = r.part;
+    P.part_b = r.leaf;
+    P.nleaves = r.nleaves;
+    int32_t L = r.nleaves;
+    std::vector<int32_t> leaf_part(L, 0);
+    for (int64_t p = 0; p < nnz; ++p) leaf_part[r.leaf[p]] = r.part[p];
+    std::vector<int32_t> leaf_lo_of_part(K + 1, 0);
+    {
+        std::vector<int32_t> cnt(K + 1, 0);
+        for (int32_t l = 0; l < L; ++l) cnt[leaf_part[l] + 1]++;
+        for (int32_t k = 0; k < K; ++k) leaf_lo_of_part[k + 1] = leaf_lo_of_part[k] + cnt[k + 1];
+    }
+    // row classes
+    std::vector<int32_t> rb(m);
+    for (int32_t i = 0; i < m; ++i) {
+        int32_t fl = -1, fp = -1;
+        bool ml = false, mp = false;
+        for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+            if (fl < 0) { fl = r.leaf[q]; fp = r.part[q]; }
+            else {
+                if (r.leaf[q] != fl) ml = true;
+                if (r.part[q] != fp) mp = true;
+            }
+        }
+        if (fl < 0) rb[i] = L + K + 1;
+        else if (!ml) rb[i] = fl;
+        else rb[i] = L + (mp ? K : fp);
+    }
+    P.row_perm = counting_order(rb, L + K + 2);
+    P.row_border_begin = m;
+    P.row_empty_begin = m;
+    for (int32_t t = 0; t < m; ++t) {
+        int32_t b = rb[P.row_perm[t]];
+        if (b >= L && P.row_border_begin == m) P.row_border_begin = t;
+        if (b == L + K + 1) { P.row_empty_begin = t; break; }
+    }
+    if (P.row_empty_begin < P.row_border_begin) P.row_border_begin = P.row_empty_begin;
+    // column classes
+    ColClass cc;
+    cc.first_leaf.assign(n, -1);
+    cc.first_part.assign(n, -1);
+    cc.multi_leaf.assign(n, 0);
+    cc.multi_part.assign(n, 0);
+    for (int64_t q = 0; q < nnz; ++q) {
+        int32_t j = A.colidx[q];
+        if (cc.first_part[j] < 0) { cc.first_part[j] = r.part[q]; cc.first_leaf[j] = r.leaf[q]; }
+        else {
+            if (cc.first_part[j] != r.part[q]) cc.multi_part[j] = 1;
+            if (cc.first_leaf[j] != r.leaf[q]) cc.multi_leaf[j] = 1;
+        }
+    }
+    int32_t cb = n;
+    P.col_perm = column_order(n, K, L, leaf_lo_of_part, cc, cb);
+    P.col_border_begin = cb;
+    std::vector<int32_t> inv_col(n), inv_row(m);
+    for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;
+    for (int32_t t = 0; t < m; ++t) inv_row[P.row_perm[t]] = t;
+    // per-leaf GCSR: nonzeros grouped by leaf, then by (new row, new col)
+    std::vector<int32_t> row_of(nnz);
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) row_of[q] = i;
+    std::vector<int64_t> loff((size_t)L + 1, 0);
+    for (int64_t q = 0; q < nnz; ++q) loff[r.leaf[q] + 1]++;
+    for (int32_t l = 0; l < L; ++l) loff[l + 1] += loff[l];
+    std::vector<int64_t> key(nnz);
+    std::vector<int32_t> src(nnz);
+    {
+        std::vector<int64_t> fill(loff.begin(), loff.end() - 1);
+        for (int64_t q = 0; q < nnz; ++q) {
+            int64_t o = fill[r.leaf[q]]++;
+            key[o] = ((int64_t)inv_row[row_of[q]] << 32) | (uint32_t)inv_col[A.colidx[q]];
+            src[o] = (int32_t)q;
+        }
+    }
+    parallel_for(L, [&](int64_t lo, int64_t hi) {
+        std::vector<std::pair<int64_t, int32_t>> buf;
+        for (int64_t l = lo; l < hi; ++l) {
+            buf.clear();
+            for (int64_t o = loff[l]; o < loff[l + 1]; ++o) buf.emplace_back(key[o], src[o]);
+            std::sort(buf.begin(), buf.end());
+            for (size_t t = 0; t < buf.size(); ++t) {
+                key[loff[l] + t] = buf[t].first;
+                src[loff[l] + t] = buf[t].second;
+            }
+        }
+    });
+    P.colidx.resize(nnz);
+    P.vals.resize(nnz);
+    P.slot_ptr.clear();
+    P.slot_row.clear();
+    P.leaf_slot_ptr.assign(L + 1, 0);
+    for (int32_t l = 0; l < L; ++l) {
+        int64_t prev = -1;
+        for (int64_t o = loff[l]; o < loff[l + 1]; ++o) {
+            int64_t row = key[o] >> 32;
+            if (row != prev) {
+                P.slot_ptr.push_back((int32_t)o);
+                P.slot_row.push_back((int32_t)row);
+                prev = row;
+            }
+            P.colidx[o] = (int32_t)(key[o] & 0xffffffff);
+            P.vals[o] = A.vals[src[o]];
+        }
+        P.leaf_slot_ptr[l + 1] = (int32_t)P.slot_row.size();
+    }
+    P.slot_ptr.push_back((int32_t)nnz);
+    P.part_ptr.clear();
+    leaf_column_ranges(P, P.col_perm, cc);
+    // Corollary 4 quantities for the K parts
+    std::vector<int64_t> poff((size_t)K + 1, 0);
+    for (int64_t q = 0; q < nnz; ++q) poff[r.part[q] + 1]++;
+    for (int32_t k = 0; k < K; ++k) poff[k + 1] += poff[k];
+    std::vector<int32_t> byp(nnz);
+    {
+        std::vector<int64_t> fill(poff.begin(), poff.end() - 1);
+        for (int64_t q = 0; q < nnz; ++q) byp[fill[r.part[q]]++] = (int32_t)q;
+    }
+    std::vector<int32_t> mr(m, -1), mc(n, -1);
+    int64_t lr = 0, lc = 0;
+    for (int64_t t = 0; t < nnz; ++t) {
+        int32_t q = byp[t], k = r.part[q];
+        if (mr[row_of[q]] != k) { mr[row_of[q]] = k; ++lr; }
+        if (mc[A.colidx[q]] != k) { mc[A.colidx[q]] = k; ++lc; }
+    }
+    P.sum_lambda_row = lr;
+    P.sum_lambda_col = lc;
+    P.cut = r.cut;
+    P.partition_seconds = r.seconds;
+    P.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ----------------------------------------------------------------- schedule
+//
+// Row blocks: consecutive slots of one leaf whose nonzeros fit the
+// workgroup's staging buffer (nnz_per_block - 3, because loads start at a
+// 4-aligned nonzero); a slot longer than long_row gets a block of its own
+// and is reduced by the whole workgroup.  Tiles: up to blocks_per_tile
+// consecutive blocks of a leaf, processed by one workgroup with the leaf's
+// x window loaded into LDS once.  The window is the densest contiguous range
+// of at most window_entries columns among the leaf's nonzeros, kept only
+// when it serves at least half an x read per entry loaded.
+void build_schedule(spx_plan_s &P) {
+    const Tune &T = P.tune;
+    int32_t NT = T.nnz_per_block;
+    int32_t cap = NT - 3;
+    int32_t rmax = 4 * T.wg;
+    P.blk_slot.clear();
+    P.tiles.clear();
+    P.window_nnz = 0;
+    P.window_bytes_fill = 0;
+    P.blk_slot.push_back(0);
+    // scheduling units: the leaves, then (DB) the row border as one more unit
+    std::vector<std::pair<int32_t, int32_t>> units;
+    std::vector<int32_t> unit_leaf;
+    for (int32_t l = 0; l < P.nleaves; ++l) {
+        units.emplace_back(P.leaf_slot_ptr[l], P.leaf_slot_ptr[l + 1]);
+        unit_leaf.push_back(l);
+    }
+    int32_t nslots = (int32_t)P.slot_ptr.size() - 1;
+    int32_t covered = P.nleaves ? P.leaf_slot_ptr[P.nleaves] : 0;
+    if (covered < nslots) {
+        units.emplace_back(covered, nslots);
+        unit_leaf.push_back(-1);
+    }
+    std::vector<int32_t> cols;
+    for (size_t u = 0; u < units.size(); ++u) {
+        int32_t s0 = units[u].first, s1 = units[u].second;
+        if (s0 >= s1) continue;
+        size_t first_blk = P.blk_slot.size() - 1;
+        int32_t cur_lo = s0, cur_nnz = 0;
+        for (int32_t s = s0; s < s1; ++s) {
+            int32_t len = P.slot_ptr[s + 1] - P.slot_ptr[s];
+            if (len > T.long_row || len > cap) {
+                if (s > cur_lo) P.blk_slot.push_back(s);
+                P.blk_slot.push_back(s + 1);
+                cur_lo = s + 1;
+                cur_nnz = 0;
+                continue;
+            }
+            if (s > cur_lo && (cur_nnz + len > cap || s - cur_lo >= rmax)) {
+                P.blk_slot.push_back(s);
+                cur_lo = s;
+                cur_nnz = 0;
+            }
+            cur_nnz += len;
+        }
+        if (s1 > cur_lo) P.blk_slot.push_back(s1);
+        size_t last_blk = P.blk_slot.size() - 1;
+        // window of this unit
+        int32_t wlo = 0, wlen = 0;
+        int32_t nblk = (int32_t)(last_blk - first_blk);
+        int32_t B = std::max(1, T.blocks_per_tile);
+        int32_t ntile = (nblk + B - 1) / B;
+        int32_t l = unit_leaf[u];
+        if (T.window_entries > 0 && l >= 0) {
+            int64_t z0 = P.slot_ptr[s0], z1 = P.slot_ptr[s1];
+            cols.assign(P.colidx.begin() + z0, P.colidx.begin() + z1);
+            std::sort(cols.begin(), cols.end());
+            int64_t best = 0;
+            size_t bi = 0, bj = 0;
+            size_t j = 0;
+            for (size_t i = 0; i < cols.size(); ++i) {
+                while (j < cols.size() && cols[j] < (int64_t)cols[i] + T.window_entries) ++j;
+                if ((int64_t)(j - i) > best) { best = (int64_t)(j - i); bi = i; bj = j; }
+            }
+            if (best > 0) {
+                int32_t lo = cols[bi], hi = cols[bj - 1] + 1;
+                int64_t fill = (int64_t)ntile * (hi - lo);
+                if (2 * best >= fill) {
+                    wlo = lo;
+                    wlen = hi - lo;
+                    P.window_nnz += best;
+                    P.window_bytes_fill += fill * 8;
+                }
+            }
+        }
+        for (int32_t t = 0; t < ntile; ++t) {
+            int32_t b0 = (int32_t)first_blk + t * B;
+            int32_t b1 = std::min((int32_t)last_blk, b0 + B);
+            P.tiles.insert(P.tiles.end(), {b0, b1, wlo, wlen});
+        }
+    }
+}
+
+}  // namespace spx

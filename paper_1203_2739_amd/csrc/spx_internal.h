@@ -1,0 +1,129 @@
+// Internal declarations shared by the host-side translation units of libspx.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/spx.h"
+
+namespace spx {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    spx_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(spx_status code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+// ------------------------------------------------------------- hypergraph
+// Pins stored both ways: net -> vertices and vertex -> nets.
+struct Hypergraph {
+    int32_t nv = 0, nn = 0;
+    std::vector<int64_t> vw;     // vertex weights
+    std::vector<int64_t> nc;     // net costs
+    std::vector<uint8_t> nrow;   // 1 = row net removed when cut (DB model)
+    std::vector<int64_t> xpins;  // [nn+1]
+    std::vector<int32_t> pins;
+    std::vector<int64_t> xnets;  // [nv+1]
+    std::vector<int32_t> vnets;
+    int64_t total_weight() const;
+    void build_vertex_side();    // fills xnets/vnets from xpins/pins
+};
+
+// One bisection: side[v] in {0, 1}; part 0 gets about frac0 of the weight.
+// Returns the cutsize (sum of costs of cut nets).
+int64_t bisect(const Hypergraph &H, double frac0, double eps, uint64_t seed,
+               std::vector<uint8_t> &side);
+
+// Matrix in CSR (host).
+struct CsrHost {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> rowptr, colidx;
+    std::vector<double> vals;
+};
+
+enum class Model { ColumnNet, ERowColumnNet, RowColumnNet };
+
+// Recursive bisection into K parts, optionally refined into leaves whose
+// window (distinct columns, plus distinct rows for the split) fits
+// window_entries.  For ColumnNet: out_part/out_leaf have m entries (rows).
+// For ERowColumnNet: m entries, part K marks a row of R_B.  For
+// RowColumnNet: nnz entries (nonzeros in CSR order).  Leaves are numbered
+// part-major.  Returns the top-level connectivity cutsize.
+struct PartitionResult {
+    std::vector<int32_t> part, leaf;
+    int32_t nleaves = 0;
+    int64_t cut = 0;
+    double seconds = 0.0;
+};
+PartitionResult partition(const CsrHost &A, Model model, int32_t K, int64_t window_entries,
+                          uint64_t seed);
+
+int32_t num_threads();
+void set_num_threads(int32_t t);
+
+// Device buffer owned through shared_ptr so that plans outlive matrices.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ~DevBuf();
+};
+using DevPtr = std::shared_ptr<DevBuf>;
+DevPtr dev_alloc(size_t bytes);
+DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream);
+
+struct Tune {
+    int32_t wg = 256, nnz_per_block = 2048, blocks_per_tile = 1, window_entries = -1;
+    int32_t xcd_remap = 1, long_row = 1024;
+};
+Tune resolve_tune(const spx_tune *t, int form);
+
+}  // namespace spx
+
+// Handles.
+struct spx_mat_s {
+    spx::CsrHost h;
+    bool on_device = false;
+    spx::DevPtr d_rowptr, d_colidx, d_vals;
+};
+
+struct spx_plan_s {
+    int form = SPX_FORM_PLAIN;
+    int32_t K = 1, m = 0, n = 0;
+    int64_t nnz = 0;
+    bool on_device = false;
+    // stored matrix: slots are rows (plain/SB/DB) or (leaf, row) pairs (split)
+    std::vector<int32_t> slot_ptr, slot_row, colidx;
+    std::vector<double> vals;
+    std::vector<int32_t> row_perm, col_perm;
+    std::vector<int32_t> part_a, part_b;        // r2p/r2leaf or nz_part/nz_leaf
+    std::vector<int32_t> part_ptr;              // rows per part (+ border)
+    std::vector<int32_t> leaf_slot_ptr;         // slots per leaf
+    std::vector<int32_t> leaf_col_lo, leaf_col_hi;  // exclusive column range per leaf
+    int32_t nleaves = 0;
+    int32_t row_border_begin = 0, row_empty_begin = 0, col_border_begin = 0;
+    // schedule
+    spx::Tune tune;
+    std::vector<int32_t> blk_slot;              // [nblocks+1]
+    std::vector<int32_t> tiles;                 // 4 per tile
+    int64_t window_nnz = 0, window_bytes_fill = 0;
+    // device copies
+    spx::DevPtr d_slot_ptr, d_slot_row, d_colidx, d_vals, d_row_perm, d_col_perm;
+    spx::DevPtr d_blk_slot, d_tiles;
+    // statistics
+    int64_t sum_lambda_col = 0, sum_lambda_row = 0, border_row_nnz = 0, cut = 0;
+    double partition_seconds = 0.0, plan_seconds = 0.0;
+};
+
+namespace spx {
+// plan.cpp
+void build_schedule(spx_plan_s &P);
+void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream);
+void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &r, bool db);
+void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r);
+void plan_plain(spx_plan_s &P, const CsrHost &A);
+}  // namespace spx

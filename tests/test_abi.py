@@ -1,0 +1,263 @@
+"""Host-side checks of libspx: exports, validation, partitions and plans.
+
+These run without a GPU (matrices created with csr_create_host keep a host
+copy only) and compare every integer output with the oracle bit for bit.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from synth import CSR, gen_c1, gen_uniform_zipf
+
+spx = pytest.importorskip("paper_1203_2739_amd")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return spx.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = spx.declared_symbols()
+    assert "spx_spmv" in names and "spx_split" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version(L):
+    assert "gfx950" in spx.version()
+
+
+def small_csr():
+    return CSR(3, 4, np.array([0, 2, 2, 4]), np.array([0, 3, 1, 2], np.int32),
+               np.array([1.0, 2.0, 3.0, 4.0]))
+
+
+@pytest.mark.parametrize("case", ["rowptr0", "decreasing", "last", "colrange", "unsorted", "dup"])
+def test_validation_errors(case):
+    A = small_csr()
+    rp, ci = A.rowptr.copy(), A.colidx.copy()
+    if case == "rowptr0":
+        rp = rp + 1
+    elif case == "decreasing":
+        rp = np.array([0, 2, 1, 4])
+    elif case == "last":
+        rp = np.array([0, 2, 2, 3])
+    elif case == "colrange":
+        ci = np.array([0, 4, 1, 2], np.int32)
+    elif case == "unsorted":
+        ci = np.array([3, 0, 1, 2], np.int32)
+    elif case == "dup":
+        ci = np.array([0, 0, 1, 2], np.int32)
+    with pytest.raises(spx.SpxError) as e:
+        spx.csr_create_host(3, 4, rp, ci, A.vals)
+    assert e.value.code == -1
+    assert spx.last_error()
+
+
+def test_bad_arguments():
+    M = spx.from_csr(small_csr(), device=False)
+    with pytest.raises(spx.SpxError):
+        spx.reorder_sb(M, 0)
+    with pytest.raises(spx.SpxError):
+        spx.split(M, 2, window_bytes=-8)
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M, tune=dict(wg_size=100))
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M, tune=dict(wg_size=256, nnz_per_block=300))
+    with pytest.raises(spx.SpxError):
+        spx.set_num_threads(0)
+
+
+def test_host_only_plan_cannot_run():
+    M = spx.from_csr(small_csr(), device=False)
+    P = spx.plan_plain(M)
+    rc = spx.lib().spx_spmv(P.handle, ctypes.c_void_p(8), ctypes.c_void_p(8), None)
+    assert rc == -6  # SPX_ENODEVICE
+
+
+def check_rowparts(orc, A, P, rp, cp, pp, K, db):
+    inf = P.info()
+    a, b = P.export_parts()
+    c = orc.canonical_rowcol(A, a, b, K, nleaves=inf["nleaves"])
+    assert np.array_equal(c["row_perm"], rp)
+    assert np.array_equal(c["col_perm"], cp)
+    assert np.array_equal(c["part_ptr"][: K + (2 if db else 1)], pp)
+    orp, oci, ov = orc.permute_csr(A, rp, cp)
+    erp, eci, ev = P.export_csr()
+    assert np.array_equal(orp, erp) and np.array_equal(oci, eci) and np.array_equal(ov, ev)
+    assert orc.check_sb(erp, eci, c["part_ptr"], c["col_part_ptr"], K, db=db) == []
+    if db:
+        assert inf["sum_lambda_col"] + inf["border_row_nnz"] == orc.bound_db(A, a, K)
+        assert inf["row_border_begin"] == c["part_ptr"][K]
+    else:
+        assert inf["sum_lambda_col"] == orc.bound_sb(A, a, K)
+        assert np.all(a < K)
+    assert inf["col_border_begin"] == c["col_part_ptr"][K]
+
+
+def check_split(orc, A, P, rp, cp, part, K):
+    inf = P.info()
+    a, b = P.export_parts()
+    assert np.array_equal(a, part)
+    assert orc.check_split(A, a, K) == []
+    c = orc.canonical_split(A, a, b, K)
+    assert np.array_equal(c["row_perm"], rp)
+    assert np.array_equal(c["col_perm"], cp)
+    assert inf["row_border_begin"] == c["row_shared_begin"]
+    assert inf["row_empty_begin"] == c["row_empty_begin"]
+    g = orc.split_gcsr(A, b, inf["nleaves"], rp, cp)
+    e = P.export_split()
+    for k in g:
+        assert np.array_equal(g[k], e[k]), k
+    lr, lc = orc.lambda_split(A, a, K)
+    assert inf["sum_lambda_row"] == lr.sum() and inf["sum_lambda_col"] == lc.sum()
+
+
+def check_schedule(P):
+    inf = P.info()
+    bs, tiles = P.export_sched()
+    nslots, NT = inf["nslots"], inf["nnz_per_block"]
+    assert bs[0] == 0 and bs[-1] == nslots and np.all(np.diff(bs) > 0)
+    if inf["form"] == 3:
+        sp = P.export_split()["slot_ptr"]
+    else:
+        sp = P.export_csr()[0]
+    blk_nnz = sp[bs[1:]] - sp[bs[:-1]]
+    multi = np.diff(bs) > 1
+    assert np.all(blk_nnz[multi] <= NT - 3)
+    assert tiles[0, 0] == 0 and tiles[-1, 1] == inf["nblocks"]
+    assert np.all(tiles[1:, 0] == tiles[:-1, 1]) and np.all(tiles[:, 1] > tiles[:, 0])
+    assert np.all(tiles[:, 3] >= 0) and np.all(tiles[:, 2] + tiles[:, 3] <= inf["n"])
+    assert np.all(tiles[:, 3] <= max(inf["window_entries"], 0))
+
+
+@pytest.mark.parametrize("K", [1, 2, 8])
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_c1_plans_match_oracle(orc, form, K):
+    A = gen_c1()
+    M = spx.from_csr(A, device=False)
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P, rp, cp, pp = fn(M, K, 0, 7)
+    if form == "split":
+        check_split(orc, A, P, rp, cp, pp, K)
+    else:
+        check_rowparts(orc, A, P, rp, cp, pp, K, form == "db")
+    check_schedule(P)
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_window_leaves(orc, form):
+    """With a window budget every leaf's vector window fits it (SB/DB: the
+    distinct columns of its rows; split: distinct rows plus columns)."""
+    A = gen_c1()
+    M = spx.from_csr(A, device=False)
+    W = 2048 * 8
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P, rp, cp, pp = fn(M, 4, W, 3)
+    inf = P.info()
+    assert inf["nleaves"] > 4
+    a, b = P.export_parts()
+    rows = np.repeat(np.arange(A.m), np.diff(A.rowptr))
+    if form == "split":
+        check_split(orc, A, P, rp, cp, pp, 4)
+        for l in range(inf["nleaves"]):
+            sel = b == l
+            w = np.unique(rows[sel]).size + np.unique(A.colidx[sel]).size
+            assert w <= W // 8 or sel.sum() <= 1
+    else:
+        check_rowparts(orc, A, P, rp, cp, pp, 4, form == "db")
+        for l in range(inf["nleaves"]):
+            rsel = b == l
+            w = np.unique(A.colidx[rsel[rows]]).size
+            assert w <= W // 8 or rsel.sum() <= 1
+    check_schedule(P)
+
+
+def test_determinism_across_threads_and_runs():
+    A = gen_uniform_zipf(21, 3000, 30000, 200)
+    M = spx.from_csr(A, device=False)
+    outs = []
+    for threads in [1, 3, 8, 1]:
+        spx.set_num_threads(threads)
+        for fn in (spx.reorder_sb, spx.reorder_db, spx.split):
+            P, rp, cp, pp = fn(M, 8, 4096 * 8, 5)
+            outs.append((fn.__name__, rp.tobytes(), cp.tobytes(), pp.tobytes(),
+                         *[x.tobytes() for x in P.export_parts()]))
+    spx.set_num_threads(8)
+    for i in range(3):
+        assert outs[i] == outs[3 + i] == outs[6 + i] == outs[9 + i]
+
+
+def test_seed_changes_partition():
+    A = gen_uniform_zipf(22, 2000, 20000, 100)
+    M = spx.from_csr(A, device=False)
+    a = spx.reorder_sb(M, 4, 0, 1)[1]
+    b = spx.reorder_sb(M, 4, 0, 2)[1]
+    assert not np.array_equal(a, b)
+
+
+def hidden_block_diag(seed, K, bs, deg=4):
+    rng = np.random.default_rng(seed)
+    n = K * bs
+    rows, cols = [], []
+    for i in range(n):
+        k = i // bs
+        c = rng.choice(bs, size=deg, replace=False) + k * bs
+        c = np.union1d(c, [i])
+        rows += [i] * c.size
+        cols += list(c)
+    rows, cols = np.array(rows), np.array(cols)
+    p = rng.permutation(n)
+    r2, c2 = p[rows], p[cols]
+    o = np.lexsort((c2, r2))
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r2, minlength=n), out=rp[1:])
+    return CSR(n, n, rp, c2[o].astype(np.int32), rng.uniform(-1, 1, rows.size)), p
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_hidden_block_diagonal_found(orc, form):
+    """A block-diagonal matrix hidden by a symmetric permutation: the
+    partitioner recovers the blocks, so the border is empty and
+    sum_j lambda(c_j) = n (Theorems 1-3 at their minimum)."""
+    A, _ = hidden_block_diag(4, 8, 400)
+    M = spx.from_csr(A, device=False)
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P, rp, cp, pp = fn(M, 8, 0, 1)
+    inf = P.info()
+    assert inf["col_border_begin"] == A.n
+    assert inf["sum_lambda_col"] == A.n
+    if form == "db":
+        assert inf["border_row_nnz"] == 0
+    if form == "split":
+        assert inf["sum_lambda_row"] == A.m
+
+
+def test_empty_and_degenerate(orc):
+    # matrix with empty rows and columns, one long row, rectangular
+    rng = np.random.default_rng(0)
+    m, n = 300, 500
+    rows = [0] * 450 + list(rng.integers(1, m, 600))
+    cols = list(rng.choice(n, 450, replace=False)) + list(rng.integers(0, n, 600))
+    key = np.unique(np.array(rows) * n + np.array(cols))
+    r, c = key // n, key % n
+    rp = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=m), out=rp[1:])
+    A = CSR(m, n, rp, c.astype(np.int32), rng.uniform(-1, 1, key.size))
+    M = spx.from_csr(A, device=False)
+    for fn, db in ((spx.reorder_sb, False), (spx.reorder_db, True)):
+        P, rp_, cp_, pp = fn(M, 4, 0, 0)
+        check_rowparts(orc, A, P, rp_, cp_, pp, 4, db)
+        check_schedule(P)
+    P, rp_, cp_, part = spx.split(M, 4, 0, 0)
+    check_split(orc, A, P, rp_, cp_, part, 4)
+    check_schedule(P)
+    # empty matrix
+    E = spx.csr_create_host(5, 3, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    for fn in (spx.reorder_sb, spx.reorder_db, spx.split):
+        P = fn(E, 2, 0, 0)[0]
+        assert P.info()["nnz"] == 0
+    P = spx.plan_plain(E)
+    check_schedule(P)

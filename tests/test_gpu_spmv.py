@@ -1,0 +1,217 @@
+"""GPU parity of the SpMV forms against the CPU oracle, through the C ABI.
+
+Binary64 results must satisfy |y - y_ref| <= 1e-12 * sum_j |a_ij x_j| per
+entry; with small-integer values and inputs every summation order is exact,
+so those cases are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import assert_close_rowwise, dev, host, integer_problem
+from synth import CSR, gen_c1, gen_uniform_zipf, gen_vectors
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+spx = pytest.importorskip("paper_1203_2739_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def run_plain(A, x, tune=None):
+    M = spx.from_csr(A)
+    P = spx.plan_plain(M, tune=tune)
+    xd = dev(x)
+    yd = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
+    spx.spmv(P, xd, yd)
+    return host(yd)
+
+
+def run_reordered(A, x, form, K, window_bytes=0, tune=None, seed=0):
+    M = spx.from_csr(A)
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P, rp, cp, part = fn(M, K, window_bytes, seed, tune=tune)
+    xh = dev(x[cp])
+    yh = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
+    if form == "split":
+        spx.spmv_split(P, xh, yh)
+    else:
+        spx.spmv(P, xh, yh)
+    return host(yh), rp, cp, part, P
+
+
+TUNES = [None,
+         dict(wg_size=256, nnz_per_block=1024),
+         dict(wg_size=512, nnz_per_block=2048),
+         dict(wg_size=512, nnz_per_block=4096),
+         dict(wg_size=1024, nnz_per_block=4096),
+         dict(wg_size=256, nnz_per_block=2048, xcd_remap=-1),
+         dict(wg_size=256, nnz_per_block=2048, long_row=64)]
+
+
+@pytest.mark.parametrize("ti", range(len(TUNES)))
+def test_plain_c1(orc, ti):
+    A = gen_c1()
+    x = gen_vectors(101, A.n)[0]
+    y = run_plain(A, x, TUNES[ti])
+    assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), "plain C1")
+
+
+def test_plain_c1_integer_exact(orc):
+    A, x = integer_problem(gen_c1(), 5)
+    assert np.array_equal(run_plain(A, x), orc.spmv(A, x))
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("K", [1, 8])
+def test_reordered_c1(orc, form, K):
+    A = gen_c1()
+    x = gen_vectors(102, A.n)[0]
+    y, rp, cp, part, P = run_reordered(A, x, form, K)
+    assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], f"{form} C1")
+    if form == "split":
+        ys = orc.split_spmv(A, part, K, x)
+        assert_close_rowwise(y, ys[rp], orc.abs_rowsum(A, x)[rp], "split vs part order")
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_reordered_c1_integer_exact(orc, form):
+    A, x = integer_problem(gen_c1(), 9)
+    y, rp, cp, part, P = run_reordered(A, x, form, 8)
+    assert np.array_equal(y, orc.spmv(A, x)[rp])
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("wb", [4096 * 8, 8192 * 8, 12288 * 8])
+def test_windows_c1(orc, form, wb):
+    """LDS windows (leaves refined to the window budget, tiles of several
+    blocks) give the same products."""
+    A = gen_c1()
+    x = gen_vectors(103, A.n)[0]
+    y, rp, cp, part, P = run_reordered(A, x, form, 4, window_bytes=wb)
+    inf = P.info()
+    assert inf["window_entries"] > 0
+    assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], f"{form} window")
+    Ai, xi = integer_problem(A, 4)
+    yi, rp, _, _, _ = run_reordered(Ai, xi, form, 4, window_bytes=wb)
+    assert np.array_equal(yi, orc.spmv(Ai, xi)[rp])
+
+
+def test_split_accumulate(orc):
+    A = gen_c1()
+    x = gen_vectors(104, A.n)[0]
+    y0 = gen_vectors(105, A.m)[0]
+    M = spx.from_csr(A)
+    P, rp, cp, part = spx.split(M, 8, 0, 0)
+    yd = dev(y0[rp])
+    spx.spmv_split(P, dev(x[cp]), yd, accumulate=1)
+    ref = orc.split_spmv(A, part, 8, x, y0)
+    bound = orc.abs_rowsum(A, x) + np.abs(y0)
+    assert_close_rowwise(host(yd), ref[rp], bound[rp], "split accumulate")
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_permute_roundtrip(orc, form):
+    A = gen_c1()
+    x = gen_vectors(106, A.n)[0]
+    M = spx.from_csr(A)
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P, rp, cp, _ = fn(M, 8, 0, 0)
+    xd = dev(x)
+    xh = torch.empty_like(xd)
+    spx.permute_x(P, xd, xh)
+    assert np.array_equal(host(xh), x[cp])
+    yh = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    spx.spmv(P, xh, yh)
+    y = torch.empty_like(yh)
+    spx.unpermute_y(P, yh, y)
+    assert_close_rowwise(host(y), orc.spmv(A, x), orc.abs_rowsum(A, x), "P A Q (Q^T x) = P (A x)")
+
+
+def odd_matrix(seed, m, n, long_len=0, empty_frac=0.3):
+    """Rectangular, many empty rows, optionally one very long row."""
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(0, 12, size=m)
+    deg[rng.random(m) < empty_frac] = 0
+    if long_len:
+        deg[m // 3] = long_len
+    deg = np.minimum(deg, n)
+    rows = np.repeat(np.arange(m), deg)
+    cols = np.concatenate([np.sort(rng.choice(n, d, replace=False)) for d in deg]) if deg.sum() else np.zeros(0, int)
+    rp = np.zeros(m + 1, np.int64)
+    np.cumsum(deg, out=rp[1:])
+    return CSR(m, n, rp, cols.astype(np.int32), rng.uniform(-1, 1, rows.size))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 50000), (777, 3), (5000, 20000), (20000, 5000)])
+@pytest.mark.parametrize("long_len", [0, 3000, 20000])
+def test_edge_shapes(orc, shape, long_len):
+    m, n = shape
+    A = odd_matrix(m * 7 + n, m, n, long_len=long_len if n >= long_len else 0)
+    x = gen_vectors(107, n)[0]
+    for ti in (0, 1, 4):
+        y = run_plain(A, x, TUNES[ti])
+        assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), f"plain {shape} {long_len}")
+    if A.nnz:
+        for form in ("sb", "db", "split"):
+            y, rp, cp, _, _ = run_reordered(A, x, form, 4)
+            assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], f"{form} {shape}")
+
+
+def test_empty_matrices(orc):
+    for m, n in [(0, 0), (0, 5), (5, 0), (7, 9)]:
+        A = CSR(m, n, np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+        M = spx.from_csr(A)
+        P = spx.plan_plain(M)
+        yd = torch.full((max(m, 1),), np.nan, dtype=torch.float64, device="cuda")
+        xd = torch.ones(max(n, 1), dtype=torch.float64, device="cuda")
+        spx.spmv(P, xd, yd)
+        if m:
+            assert np.all(host(yd)[:m] == 0.0)
+        if m and n:
+            P, rp, cp, _ = spx.split(M, 2, 0, 0)
+            yd[:] = float("nan")
+            spx.spmv_split(P, xd, yd)
+            assert np.all(host(yd)[:m] == 0.0)
+
+
+def test_rows_at_block_capacity(orc):
+    """Rows whose lengths straddle the staging capacity (NT - 3, NT, NT + 1)
+    and the long-row threshold."""
+    lens = [2045, 2046, 2048, 2049, 1024, 1025, 1, 0, 4093, 4096, 8190, 3]
+    n = 9000
+    rng = np.random.default_rng(3)
+    cols = np.concatenate([np.sort(rng.choice(n, d, replace=False)) for d in lens])
+    rp = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    A = CSR(len(lens), n, rp, cols.astype(np.int32), rng.uniform(-1, 1, cols.size))
+    x = gen_vectors(108, n)[0]
+    for t in TUNES:
+        y = run_plain(A, x, t)
+        assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), f"capacity {t}")
+
+
+def test_larger_irregular(orc):
+    """Several thousand tiles, Zipf rows up to 5,000 nonzeros."""
+    A = gen_uniform_zipf(31, 200_000, 4_000_000, 5000, diagonal=True)
+    x = gen_vectors(109, A.n)[0]
+    y = run_plain(A, x)
+    assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), "zipf 200k")
+    y, rp, cp, part, P = run_reordered(A, x, "split", 16)
+    assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], "zipf 200k split")
+    y, rp, cp, part, P = run_reordered(A, x, "db", 16, window_bytes=8192 * 8)
+    assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], "zipf 200k db window")
+
+
+def test_stream_probe():
+    nbytes = 64 << 20
+    src = torch.arange(nbytes // 8, dtype=torch.float64, device="cuda")
+    sink = torch.zeros(spx.stream_sink_len(nbytes), dtype=torch.float64, device="cuda")
+    spx.stream_read(src, nbytes, sink)
+    assert abs(host(sink).sum() - host(src).sum()) <= 1e-9 * abs(host(src).sum())
+    dst = torch.zeros_like(src)
+    spx.stream_copy(src, dst, nbytes)
+    assert torch.equal(dst, src)
