@@ -58,15 +58,17 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
 
 /* Kernel schedule.  Any field set to 0 takes the library default.
  *   wg_size          threads per workgroup: 256, 512 or 1024
- *   nnz_per_block    nonzeros one workgroup stages per step: 4 or 8 per
- *                    thread (a multiple of wg_size)
- *   blocks_per_tile  row blocks one workgroup processes in sequence; the
+ *   nnz_per_block    nonzeros one workgroup stages per step: 4 per thread
+ *                    (4 * wg_size, the default)
+ *   blocks_per_tile  least number of row blocks one workgroup processes in
+ *                    sequence (a tile also ends only where a row ends); the
  *                    tile's x window is loaded into LDS once per tile
  *   window_entries   largest LDS x window in binary64 entries (0 = default,
  *                    -1 = no window); windows are contiguous column ranges
  *   xcd_remap        1 = map consecutive tiles to the same XCD (default),
  *                    -1 = hardware dispatch order
- *   long_row         rows longer than this get a workgroup of their own  */
+ *   long_row         unused (rows of any length are split across the blocks
+ *                    of one tile)                                          */
 typedef struct spx_tune_s {
     int32_t wg_size;
     int32_t nnz_per_block;
@@ -222,16 +224,18 @@ spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *str
  *   original row, K for R_B) and r2leaf[m] (leaf, -1 for R_B).  Split:
  *   nz_part[nnz] and nz_leaf[nnz] in A's CSR order.
  * spx_plan_export_perm: row_perm[m], col_perm[n] (identity for plain).
- * spx_plan_export_sched: blk_slot[nblocks+1] (slot range of each row block)
- *   and tiles[4*ntiles] = {first block, end block, window first column,
- *   window length} per tile.
+ * spx_plan_export_sched: blk_desc[4*nblocks] = {first slot starting in the
+ *   block, end of those slots, first nonzero, end nonzero} per row block (a
+ *   row may continue from one block into the next of the same tile) and
+ *   tiles[4*ntiles] = {first block, end block, window first column, window
+ *   length} per tile.
  */
 spx_status spx_plan_export_csr(spx_plan P, int32_t *rowptr, int32_t *colidx, double *vals);
 spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *slot_row,
                                  int32_t *slot_ptr, int32_t *colidx, double *vals);
 spx_status spx_plan_export_parts(spx_plan P, int32_t *a, int32_t *b);
 spx_status spx_plan_export_perm(spx_plan P, int32_t *row_perm, int32_t *col_perm);
-spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_slot, int32_t *tiles);
+spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_desc, int32_t *tiles);
 
 /* ----------------------------------------------------------------------
  * Measurement helpers.

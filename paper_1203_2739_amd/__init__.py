@@ -304,11 +304,12 @@ class Plan:
         return rp[:m], cp[:n]
 
     def export_sched(self):
+        """(blk_desc[nblocks, 4], tiles[ntiles, 4])."""
         inf = self.info()
-        bs = np.empty(inf["nblocks"] + 1, np.int32)
+        bd = np.empty(max(4 * inf["nblocks"], 1), np.int32)
         tl = np.empty(max(4 * inf["ntiles"], 1), np.int32)
-        _check(lib().spx_plan_export_sched(self._h, _hp(bs), _hp(tl)))
-        return bs, tl[:4 * inf["ntiles"]].reshape(-1, 4)
+        _check(lib().spx_plan_export_sched(self._h, _hp(bd), _hp(tl)))
+        return bd[:4 * inf["nblocks"]].reshape(-1, 4), tl[:4 * inf["ntiles"]].reshape(-1, 4)
 
 
 def _tune_ptr(tune):

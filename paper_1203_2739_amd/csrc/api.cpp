@@ -56,21 +56,18 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (t) {
         if (t->wg_size) r.wg = t->wg_size;
         if (t->nnz_per_block) r.nnz_per_block = t->nnz_per_block;
-        else r.nnz_per_block = 8 * r.wg;
         if (t->blocks_per_tile) r.blocks_per_tile = t->blocks_per_tile;
         if (t->window_entries) r.window_entries = t->window_entries;
         if (t->xcd_remap) r.xcd_remap = t->xcd_remap > 0 ? 1 : 0;
-        if (t->long_row) r.long_row = t->long_row;
     }
-    if (r.wg != 256 && r.wg != 512 && r.wg != 1024) fail(SPX_EINVAL, "wg_size must be 256, 512 or 1024");
-    if (r.nnz_per_block != 4 * r.wg && r.nnz_per_block != 8 * r.wg)
-        fail(SPX_EINVAL, "nnz_per_block must be 4 or 8 times wg_size");
+    if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512)
+        fail(SPX_EINVAL, "wg_size must be 64, 128, 256 or 512");
+    if (r.nnz_per_block != kChunkSpan) fail(SPX_EINVAL, "nnz_per_block must be 256 (4 per lane of a wave)");
     if (r.blocks_per_tile < 1) fail(SPX_EINVAL, "blocks_per_tile must be >= 1");
-    if (r.long_row < 1) fail(SPX_EINVAL, "long_row must be >= 1");
     if (r.window_entries < 0) r.window_entries = -1;
     int wmax = 0;
-    if (!spmv_variant_exists(r.wg, r.nnz_per_block / r.wg, r.window_entries, &wmax))
-        fail(SPX_EUNSUPPORTED, "no kernel variant for this wg_size / nnz_per_block / window");
+    if (!spmv_variant_exists(r.wg, r.window_entries, &wmax))
+        fail(SPX_EUNSUPPORTED, "no kernel variant for this wg_size / window");
     return r;
 }
 
@@ -165,7 +162,7 @@ void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream) {
         if (!P.col_perm.empty())
             P.d_col_perm = dev_upload(P.col_perm.data(), P.col_perm.size() * 4, 0, stream);
     }
-    P.d_blk_slot = dev_upload(P.blk_slot.data(), P.blk_slot.size() * 4, 0, stream);
+    P.d_blk_desc = dev_upload(P.blk_desc.data(), P.blk_desc.size() * 4, 16, stream);
     P.d_tiles = dev_upload(P.tiles.data(), P.tiles.size() * 4, 16, stream);
     hip_check(hipStreamSynchronize((hipStream_t)stream), "plan upload");
     P.on_device = true;
@@ -179,11 +176,7 @@ static void apply_tune(spx_plan_s &P, const spx_tune *tune, int64_t window_bytes
         // default: the partition's window budget, when one was given
         t.window_entries = window_bytes > 0 ? (int32_t)std::min<int64_t>(window_bytes / 8, 12288) : -1;
     }
-    if ((!tune || t.blocks_per_tile == 0) && t.window_entries > 0) t.blocks_per_tile = 4;
-    if (t.window_entries > 0 && (!tune || t.wg_size == 0)) {
-        t.wg_size = t.window_entries > 8192 ? 1024 : (t.window_entries > 4096 ? 512 : 256);
-        t.nnz_per_block = t.wg_size == 1024 ? 4096 : 8 * t.wg_size;
-    }
+    if (t.window_entries > 0 && (!tune || t.wg_size == 0)) t.wg_size = t.window_entries > 8192 ? 512 : 256;
     P.tune = resolve_tune(&t, P.form);
     build_schedule(P);
 }
@@ -228,10 +221,11 @@ static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t
     a.vals = (const double *)P.d_vals->ptr;
     a.x = x;
     a.y = y;
-    a.blk_slot = (const int32_t *)P.d_blk_slot->ptr;
+    a.blk_desc = (const int32_t *)P.d_blk_desc->ptr;
     a.tiles = (const int32_t *)P.d_tiles->ptr;
-    a.ntiles = (int32_t)(P.tiles.size() / 4);
+    a.ntiles = (int32_t)(P.tiles.size() / 4) / (P.tune.wg / 64);  // workgroups
     a.xcd_remap = P.tune.xcd_remap;
+    a.n = P.n;
     bool split = P.form == SPX_FORM_SPLIT;
     if (split) {
         a.shared_begin = P.row_border_begin;
@@ -241,7 +235,7 @@ static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t
             if (e != hipSuccess) return e;
         }
     }
-    return launch_spmv(a, P.tune.wg, P.tune.nnz_per_block / P.tune.wg, P.tune.window_entries, split, s);
+    return launch_spmv(a, P.tune.wg, P.tune.window_entries, split, s);
 }
 
 extern "C" {
@@ -323,7 +317,7 @@ spx_status spx_plan_retune(spx_plan P, const spx_tune *tune) {
         P->tune = r;
         build_schedule(*P);
         if (P->on_device) {
-            P->d_blk_slot = dev_upload(P->blk_slot.data(), P->blk_slot.size() * 4, 0, nullptr);
+            P->d_blk_desc = dev_upload(P->blk_desc.data(), P->blk_desc.size() * 4, 16, nullptr);
             P->d_tiles = dev_upload(P->tiles.data(), P->tiles.size() * 4, 16, nullptr);
             hip_check(hipStreamSynchronize(nullptr), "retune upload");
         }
@@ -342,7 +336,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->n = P->n;
         info->nnz = P->nnz;
         info->nleaves = P->nleaves;
-        info->nblocks = (int32_t)P->blk_slot.size() - 1;
+        info->nblocks = (int32_t)(P->blk_desc.size() / 4);
         info->ntiles = (int32_t)(P->tiles.size() / 4);
         info->nslots = (int32_t)P->slot_ptr.size() - 1;
         info->row_border_begin = P->row_border_begin;
@@ -357,7 +351,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->border_row_nnz = P->border_row_nnz;
         info->cut_connectivity = P->cut;
         info->bytes_matrix = 12 * P->nnz + 4 * (int64_t)P->slot_ptr.size() +
-                             4 * (int64_t)P->slot_row.size() + 4 * (int64_t)P->blk_slot.size() +
+                             4 * (int64_t)P->slot_row.size() + 4 * (int64_t)P->blk_desc.size() +
                              4 * (int64_t)P->tiles.size();
         info->bytes_window = P->window_bytes_fill;
         info->window_nnz = P->window_nnz;
@@ -464,10 +458,10 @@ spx_status spx_plan_export_perm(spx_plan P, int32_t *row_perm, int32_t *col_perm
     });
 }
 
-spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_slot, int32_t *tiles) {
+spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_desc, int32_t *tiles) {
     return guarded([&] {
         if (!P) fail(SPX_EINVAL, "NULL handle");
-        if (blk_slot) std::copy(P->blk_slot.begin(), P->blk_slot.end(), blk_slot);
+        if (blk_desc) std::copy(P->blk_desc.begin(), P->blk_desc.end(), blk_desc);
         if (tiles) std::copy(P->tiles.begin(), P->tiles.end(), tiles);
     });
 }

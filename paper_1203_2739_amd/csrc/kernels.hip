@@ -113,130 +113,200 @@ __device__ __forceinline__ double xval(const double *__restrict__ x, const doubl
 
 }  // namespace
 
-template <int WG, int IPT, bool SPLIT, int WMAX>
-__global__ __launch_bounds__(WG) void spmv_tiles(SpmvArgs a) {
-    constexpr int NT = WG * IPT;
-    constexpr int GPT = IPT / 4;  // 4-nonzero groups per thread per step
-    __shared__ double sprod[NT];
-    __shared__ double swin[WMAX > 0 ? WMAX : 1];
-    __shared__ double sred[WG / 64];
+// ---------------------------------------------------------------------------
+// Wave-level SpMV.  Every wave owns a tile: a run of chunks of at most 253
+// nonzeros (loads start at a 4-aligned nonzero, so a chunk spans at most
+// 256 = 4 per lane) in which at most 256 rows start.  A row may continue
+// from one chunk into the next of the same tile; its partial sum is carried
+// in scalar registers.  Waves never wait for each other: the only workgroup
+// barrier follows the load of the group's shared LDS x window.
 
-    const int tid = threadIdx.x;
-    const int tile = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
-    const int32_t b0 = a.tiles[4 * tile + 0];
-    const int32_t b1 = a.tiles[4 * tile + 1];
-    const int32_t wlo = a.tiles[4 * tile + 2];
-    const int32_t wlen = WMAX > 0 ? a.tiles[4 * tile + 3] : 0;
+constexpr int kRowPtrPerLane = (kChunkRows + 1 + 63) / 64;
+
+struct Stage {
+    int32_t s_lo, s_hi, z_lo, z_hi;
+    v4i cc;
+    v2d va, vb;
+    int32_t rp[kRowPtrPerLane];
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Every load is issued unconditionally (out-of-range lanes read a clamped,
+// valid address; their values are masked later), so the number of loads in
+// flight is known at compile time and waiting for the oldest ones does not
+// drain the younger prefetches.
+__device__ __forceinline__ void issue_chunk(const SpmvArgs &a, v4i d, int lane, Stage &st) {
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
     const v2d *__restrict__ v2 = reinterpret_cast<const v2d *>(a.vals);
-    const double *__restrict__ x = a.x;
+    // the descriptor is uniform across the wave: keep it in scalar registers
+    st.s_lo = __builtin_amdgcn_readfirstlane(d.x);
+    st.s_hi = __builtin_amdgcn_readfirstlane(d.y);
+    st.z_lo = __builtin_amdgcn_readfirstlane(d.z);
+    st.z_hi = __builtin_amdgcn_readfirstlane(d.w);
+    const int32_t nr = st.s_hi - st.s_lo;
+    const int32_t zb = st.z_lo & ~3;
+    const int32_t G = (st.z_hi - zb + 3) >> 2;
+    const int32_t g = min(lane, G > 0 ? G - 1 : 0);
+    st.cc = __builtin_nontemporal_load(&c4[(zb >> 2) + g]);
+    st.va = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * g]);
+    st.vb = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * g + 1]);
+#pragma unroll
+    for (int k = 0; k < kRowPtrPerLane; ++k) st.rp[k] = a.slot_ptr[st.s_lo + min(lane + 64 * k, nr)];
+}
 
-    if (WMAX > 0 && wlen > 0) {
-        for (int i = tid; i < wlen; i += WG) swin[i] = x[wlo + i];
+// Wave-private LDS.
+struct WaveSmem {
+    uint32_t flag[8];             // row-start bits of the 256 staged nonzeros
+    int32_t row[256];             // slot id at each row start
+    int32_t ptr[64 * kRowPtrPerLane];
+};
+
+// One chunk.  Gathers of x for the staged nonzeros are issued first, then
+// the loads of the next chunk, so both latencies overlap.  Lane t holds the
+// products of nonzeros 4t .. 4t+3.  Rows starting in the chunk are marked in
+// LDS; a lane finishes the rows lying inside it and keeps the sum before its
+// first row start (head) and of its last open row (tail); a segmented scan
+// over the 64 lanes finishes the rows spanning lanes; the row still open at
+// the end of the chunk is carried to the next chunk (cv, cr).
+template <bool SPLIT, int WMAX>
+__device__ __forceinline__ void run_chunk(const SpmvArgs &a, v4i dn, int lane, Stage &cur,
+                                          Stage &nxt, WaveSmem &ws, const double *swin,
+                                          int32_t wlo, int32_t wlen, double &cv, int32_t &cr) {
+    const double *__restrict__ x = a.x;
+    const int32_t s_lo = cur.s_lo, z_lo = cur.z_lo, z_hi = cur.z_hi;
+    const int32_t nr = cur.s_hi - s_lo;
+    const int32_t zb = z_lo & ~3;
+
+    double xv[4];
+    if (a.n > 0) {
+        xv[0] = xval<WMAX>(x, swin, cur.cc.x, wlo, wlen);
+        xv[1] = xval<WMAX>(x, swin, cur.cc.y, wlo, wlen);
+        xv[2] = xval<WMAX>(x, swin, cur.cc.z, wlo, wlen);
+        xv[3] = xval<WMAX>(x, swin, cur.cc.w, wlo, wlen);
+    } else {
+        xv[0] = xv[1] = xv[2] = xv[3] = 0.0;
+    }
+    issue_chunk(a, dn, lane, nxt);
+
+#pragma unroll
+    for (int k = 0; k < kRowPtrPerLane; ++k) {
+        int32_t i = lane + 64 * k;
+        if (i <= nr) ws.ptr[i] = cur.rp[k] - zb;
+    }
+    if (lane < 8) ws.flag[lane] = 0u;
+    const int32_t z = zb + 4 * lane;
+    double p[4];
+    p[0] = (z + 0 >= z_lo && z + 0 < z_hi) ? cur.va.x * xv[0] : 0.0;
+    p[1] = (z + 1 >= z_lo && z + 1 < z_hi) ? cur.va.y * xv[1] : 0.0;
+    p[2] = (z + 2 >= z_lo && z + 2 < z_hi) ? cur.vb.x * xv[2] : 0.0;
+    p[3] = (z + 3 >= z_lo && z + 3 < z_hi) ? cur.vb.y * xv[3] : 0.0;
+    wave_sync();
+    // mark the first nonzero of every non-empty row; empty rows are zero
+    for (int32_t r = lane; r < nr; r += 64) {
+        int32_t lo = ws.ptr[r], hi = ws.ptr[r + 1];
+        if (lo == hi) {
+            store_row<SPLIT>(a.y, a.slot_row, s_lo + r, 0.0, a.shared_begin, a.accumulate);
+        } else {
+            atomicOr(&ws.flag[lo >> 5], 1u << (lo & 31));
+            ws.row[lo] = s_lo + r;
+        }
+    }
+    const bool row_ends = ws.ptr[nr] + zb <= z_hi;  // no row continues past the chunk
+    wave_sync();
+    const uint32_t f = (ws.flag[lane >> 3] >> ((lane & 7) * 4)) & 0xFu;
+    double head = 0.0, tail = 0.0;
+    int32_t trow = -1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if ((f >> e) & 1u) {
+            if (trow >= 0) store_row<SPLIT>(a.y, a.slot_row, trow, tail, a.shared_begin, a.accumulate);
+            trow = ws.row[4 * lane + e];
+            tail = p[e];
+        } else if (trow >= 0) {
+            tail += p[e];
+        } else {
+            head += p[e];
+        }
+    }
+    // segmented inclusive scan of (open row, partial sum) over the lanes
+    double v = trow >= 0 ? tail : head;
+    int32_t rw = trow;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        double vo = __shfl_up(v, off);
+        int32_t ro = __shfl_up(rw, off);
+        if (lane >= off && rw < 0) {
+            v += vo;
+            rw = ro;
+        }
+    }
+    if (rw < 0) {
+        v += cv;
+        rw = cr;
+    }
+    double av = __shfl_up(v, 1);
+    int32_t ar = __shfl_up(rw, 1);
+    if (lane == 0) {
+        av = cv;
+        ar = cr;
+    }
+    if (f != 0u && ar >= 0) store_row<SPLIT>(a.y, a.slot_row, ar, av + head, a.shared_begin, a.accumulate);
+    const int32_t t_end = (z_hi - zb - 1) >> 2;  // lane of the chunk's last nonzero (uniform)
+    if (t_end >= 0) {
+        double ov = f != 0u ? tail : av + head;
+        int32_t orow = f != 0u ? trow : ar;
+        if (row_ends) {
+            if (lane == t_end && orow >= 0)
+                store_row<SPLIT>(a.y, a.slot_row, orow, ov, a.shared_begin, a.accumulate);
+            cv = 0.0;
+            cr = -1;
+        } else {
+            cv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ov), t_end),
+                                  __builtin_amdgcn_readlane(__double2loint(ov), t_end));
+            cr = __builtin_amdgcn_readlane(orow, t_end);
+        }
+    }
+    wave_sync();
+}
+
+template <int WPG, bool SPLIT, int WMAX>
+__global__ __launch_bounds__(64 * WPG) void spmv_waves(SpmvArgs a) {
+    __shared__ WaveSmem wsm[WPG];
+    __shared__ double swin[WMAX > 0 ? WMAX : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int group = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
+    const v4i *__restrict__ tiles = reinterpret_cast<const v4i *>(a.tiles);
+    const v4i *__restrict__ desc = reinterpret_cast<const v4i *>(a.blk_desc);
+    const v4i t4 = tiles[group * WPG + wave];
+    const int32_t b0 = __builtin_amdgcn_readfirstlane(t4.x);
+    const int32_t b1 = __builtin_amdgcn_readfirstlane(t4.y);
+    int32_t wlo = 0, wlen = 0;
+    Stage s0, s1;
+    if (b0 < b1) issue_chunk(a, desc[b0], lane, s0);
+    if (WMAX > 0) {
+        // the tiles of a group share one LDS x window
+        const v4i g4 = tiles[group * WPG];
+        wlo = __builtin_amdgcn_readfirstlane(g4.z);
+        wlen = __builtin_amdgcn_readfirstlane(g4.w);
+        for (int i = threadIdx.x; i < wlen; i += 64 * WPG) swin[i] = a.x[wlo + i];
         __syncthreads();
     }
-
-    for (int32_t b = b0; b < b1; ++b) {
-        const int32_t s_lo = a.blk_slot[b];
-        const int32_t s_hi = a.blk_slot[b + 1];
-        const int32_t z_lo = a.slot_ptr[s_lo];
-        const int32_t z_hi = a.slot_ptr[s_hi];
-        const int32_t nr = s_hi - s_lo;
-
-        if (nr == 1) {
-            // a single row: whole-workgroup reduction in registers
-            double acc = 0.0;
-            const int32_t gbeg = z_lo >> 2, gend = (z_hi + 3) >> 2;
-            for (int32_t gb = gbeg; gb < gend; gb += WG * GPT) {
-                v4i cc[GPT];
-                v2d va[GPT], vb[GPT];
-#pragma unroll
-                for (int k = 0; k < GPT; ++k) {
-                    int32_t g = gb + tid + k * WG;
-                    if (g < gend) {
-                        cc[k] = __builtin_nontemporal_load(&c4[g]);
-                        va[k] = __builtin_nontemporal_load(&v2[2 * g]);
-                        vb[k] = __builtin_nontemporal_load(&v2[2 * g + 1]);
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < GPT; ++k) {
-                    int32_t g = gb + tid + k * WG;
-                    if (g < gend) {
-                        int32_t z = 4 * g;
-                        double vv[4] = {va[k].x, va[k].y, vb[k].x, vb[k].y};
-                        int32_t ci[4] = {cc[k].x, cc[k].y, cc[k].z, cc[k].w};
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (z + e >= z_lo && z + e < z_hi)
-                                acc += vv[e] * xval<WMAX>(x, swin, ci[e], wlo, wlen);
-                    }
-                }
-            }
-            acc = group_sum(acc, 64);
-            if ((tid & 63) == 0) sred[tid >> 6] = acc;
-            __syncthreads();
-            if (tid == 0) {
-                double s = 0.0;
-#pragma unroll
-                for (int w = 0; w < WG / 64; ++w) s += sred[w];
-                store_row<SPLIT>(a.y, a.slot_row, s_lo, s, a.shared_begin, a.accumulate);
-            }
-            __syncthreads();
-            continue;
-        }
-
-        // phase 1: stream the block, products to LDS
-        const int32_t zb = z_lo & ~3;
-        const int32_t G = (z_hi - zb + 3) >> 2;  // <= NT / 4 by construction
-        {
-            v4i cc[GPT];
-            v2d va[GPT], vb[GPT];
-#pragma unroll
-            for (int k = 0; k < GPT; ++k) {
-                int32_t g = tid + k * WG;
-                if (g < G) {
-                    cc[k] = __builtin_nontemporal_load(&c4[(zb >> 2) + g]);
-                    va[k] = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * g]);
-                    vb[k] = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * g + 1]);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < GPT; ++k) {
-                int32_t g = tid + k * WG;
-                if (g < G) {
-                    int32_t z = zb + 4 * g;
-                    double p0 = (z + 0 >= z_lo && z + 0 < z_hi) ? va[k].x * xval<WMAX>(x, swin, cc[k].x, wlo, wlen) : 0.0;
-                    double p1 = (z + 1 >= z_lo && z + 1 < z_hi) ? va[k].y * xval<WMAX>(x, swin, cc[k].y, wlo, wlen) : 0.0;
-                    double p2 = (z + 2 >= z_lo && z + 2 < z_hi) ? vb[k].x * xval<WMAX>(x, swin, cc[k].z, wlo, wlen) : 0.0;
-                    double p3 = (z + 3 >= z_lo && z + 3 < z_hi) ? vb[k].y * xval<WMAX>(x, swin, cc[k].w, wlo, wlen) : 0.0;
-                    v2d *sp = reinterpret_cast<v2d *>(&sprod[4 * g]);
-                    sp[0] = v2d{p0, p1};
-                    sp[1] = v2d{p2, p3};
-                }
-            }
-        }
-        __syncthreads();
-
-        // phase 2: one power-of-two lane group per row
-        int gsz = WG / nr;
-        gsz = gsz >= 64 ? 64 : gsz;
-        gsz = gsz < 1 ? 1 : (1 << (31 - __builtin_clz(gsz)));
-        const int ngroups = WG / gsz;
-        const int grp = tid / gsz, lane = tid & (gsz - 1);
-        for (int32_t rb = 0; rb < nr; rb += ngroups) {
-            int32_t r = rb + grp;
-            double s = 0.0;
-            if (r < nr) {
-                int32_t lo = a.slot_ptr[s_lo + r] - zb;
-                int32_t hi = a.slot_ptr[s_lo + r + 1] - zb;
-                for (int32_t k = lo + lane; k < hi; k += gsz) s += sprod[k];
-            }
-            s = group_sum(s, gsz);
-            if (r < nr && lane == 0)
-                store_row<SPLIT>(a.y, a.slot_row, s_lo + r, s, a.shared_begin, a.accumulate);
-        }
-        __syncthreads();
+    if (b0 >= b1) return;
+    WaveSmem &ws = wsm[wave];
+    double cv = 0.0;
+    int32_t cr = -1;
+    // two register stages alternate so that no load result is copied
+    for (int32_t b = b0; b < b1; b += 2) {
+        v4i dn = desc[b + 1 < b1 ? b + 1 : b];
+        run_chunk<SPLIT, WMAX>(a, dn, lane, s0, s1, ws, swin, wlo, wlen, cv, cr);
+        if (b + 1 >= b1) break;
+        dn = desc[b + 2 < b1 ? b + 2 : b + 1];
+        run_chunk<SPLIT, WMAX>(a, dn, lane, s1, s0, ws, swin, wlo, wlen, cv, cr);
     }
 }
 
@@ -302,38 +372,36 @@ __global__ __launch_bounds__(kStreamWG) void stream_copy_kernel(const v2d *__res
 // ----------------------------------------------------------------- launchers
 
 namespace {
-template <int WG, int IPT, int WMAX>
+template <int WPG, int WMAX>
 hipError_t launch_variant(const SpmvArgs &a, bool split, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
+    // a.ntiles counts workgroups here: WPG tiles each
     if (split)
-        hipLaunchKernelGGL((spmv_tiles<WG, IPT, true, WMAX>), dim3(a.ntiles), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((spmv_waves<WPG, true, WMAX>), dim3(a.ntiles), dim3(64 * WPG), 0, s, a);
     else
-        hipLaunchKernelGGL((spmv_tiles<WG, IPT, false, WMAX>), dim3(a.ntiles), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((spmv_waves<WPG, false, WMAX>), dim3(a.ntiles), dim3(64 * WPG), 0, s, a);
     return hipGetLastError();
 }
 }  // namespace
 
 struct Variant {
-    int wg, ipt, wmax;
+    int wg, wmax;
     hipError_t (*fn)(const SpmvArgs &, bool, hipStream_t);
 };
 
 static const Variant kVariants[] = {
-    {256, 4, 0, launch_variant<256, 4, 0>},
-    {256, 8, 0, launch_variant<256, 8, 0>},
-    {512, 4, 0, launch_variant<512, 4, 0>},
-    {512, 8, 0, launch_variant<512, 8, 0>},
-    {1024, 4, 0, launch_variant<1024, 4, 0>},
-    {256, 8, 4096, launch_variant<256, 8, 4096>},
-    {512, 4, 8192, launch_variant<512, 4, 8192>},
-    {512, 8, 8192, launch_variant<512, 8, 8192>},
-    {1024, 4, 12288, launch_variant<1024, 4, 12288>},
+    {64, 0, launch_variant<1, 0>},
+    {128, 0, launch_variant<2, 0>},
+    {256, 0, launch_variant<4, 0>},
+    {256, 4096, launch_variant<4, 4096>},
+    {256, 8192, launch_variant<4, 8192>},
+    {512, 12288, launch_variant<8, 12288>},
 };
 
-bool spmv_variant_exists(int wg, int ipt, int window_entries, int *wmax_out) {
+bool spmv_variant_exists(int wg, int window_entries, int *wmax_out) {
     int best = -1;
     for (const Variant &v : kVariants) {
-        if (v.wg != wg || v.ipt != ipt) continue;
+        if (v.wg != wg) continue;
         if (window_entries <= 0 ? v.wmax == 0 : v.wmax >= window_entries) {
             if (best < 0 || v.wmax < best) best = v.wmax;
         }
@@ -343,12 +411,11 @@ bool spmv_variant_exists(int wg, int ipt, int window_entries, int *wmax_out) {
     return true;
 }
 
-hipError_t launch_spmv(const SpmvArgs &a, int wg, int ipt, int window_entries, bool split,
-                       hipStream_t s) {
+hipError_t launch_spmv(const SpmvArgs &a, int wg, int window_entries, bool split, hipStream_t s) {
     int wmax = 0;
-    if (!spmv_variant_exists(wg, ipt, window_entries, &wmax)) return hipErrorInvalidValue;
+    if (!spmv_variant_exists(wg, window_entries, &wmax)) return hipErrorInvalidValue;
     for (const Variant &v : kVariants)
-        if (v.wg == wg && v.ipt == ipt && v.wmax == wmax) return v.fn(a, split, s);
+        if (v.wg == wg && v.wmax == wmax) return v.fn(a, split, s);
     return hipErrorInvalidValue;
 }
 

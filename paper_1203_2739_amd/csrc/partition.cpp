@@ -59,6 +59,7 @@ constexpr int32_t kCoarsenTo = 320;
 constexpr int64_t kMatchNetCap = 32;    // nets larger than this are ignored by clustering
 constexpr int64_t kCoarseNetCap = 512;  // nets larger than this are left out of coarse levels
 constexpr int kInitTrials = 8;
+constexpr int32_t kAbsorbFrom = 20000;  // first-level absorption above this many vertices
 
 // ------------------------------------------------------------ indexed heap
 class MaxHeap {
@@ -476,6 +477,83 @@ void match_hcc(const Hypergraph &H, int64_t maxw, Rng &rng, std::vector<int32_t>
     }
 }
 
+// Absorption clustering over nets, for the first level of large
+// hypergraphs: nets are visited from the smallest up and each net gathers its
+// still unclustered pins into clusters of at most maxw weight; a lone
+// unclustered pin joins the cluster of the net's first clustered pin when the
+// weight allows.  One pass over the pins, mostly sequential in memory.
+void absorb_nets(const Hypergraph &H, int64_t maxw, int64_t heavy_maxw, std::vector<int32_t> &cmap,
+                 int32_t &ncoarse) {
+    int32_t nv = H.nv;
+    // strongest connections first: cost / (|n| - 1) descending, then size
+    std::vector<std::pair<double, int32_t>> rated;
+    for (int32_t n = 0; n < H.nn; ++n) {
+        int64_t sz = H.xpins[n + 1] - H.xpins[n];
+        if (sz >= 2 && (sz <= kMatchNetCap || H.nc[n] >= sz - 1))
+            rated.emplace_back(-(double)H.nc[n] / (double)(sz - 1) + 1e-9 * (double)sz, n);
+    }
+    std::stable_sort(rated.begin(), rated.end(),
+                     [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                         return a.first < b.first;
+                     });
+    std::vector<int32_t> order(rated.size());
+    for (size_t i = 0; i < rated.size(); ++i) order[i] = rated[i].second;
+    rated.clear();
+    rated.shrink_to_fit();
+    std::vector<int32_t> cl(nv, -1);
+    std::vector<int64_t> cw;
+    std::vector<int32_t> fresh;
+    for (int32_t n : order) {
+        fresh.clear();
+        int32_t host = -1;
+        // a net at least as strong as a two-pin net (cost >= |n| - 1, the row
+        // nets of the enhanced model) is kept together
+        int64_t sz = H.xpins[n + 1] - H.xpins[n];
+        int64_t cap = H.nc[n] >= sz - 1 && sz > 2 ? heavy_maxw : maxw;
+        for (int64_t p = H.xpins[n]; p < H.xpins[n + 1]; ++p) {
+            int32_t u = H.pins[p];
+            if (cl[u] < 0) fresh.push_back(u);
+            else if (host < 0) host = cl[u];
+        }
+        if (fresh.empty()) continue;
+        if (fresh.size() == 1) {
+            int32_t u = fresh[0];
+            if (host >= 0 && cw[host] + H.vw[u] <= cap) {
+                cl[u] = host;
+                cw[host] += H.vw[u];
+            }
+            continue;
+        }
+        int32_t c = -1;
+        for (int32_t u : fresh) {
+            if (c < 0 || cw[c] + H.vw[u] > cap) {
+                c = (int32_t)cw.size();
+                cw.push_back(0);
+            }
+            cl[u] = c;
+            cw[c] += H.vw[u];
+        }
+    }
+    if (getenv("SPX_DEBUG")) {
+        int64_t heavy = 0, single = 0;
+        for (int32_t n : order) {
+            int64_t sz = H.xpins[n + 1] - H.xpins[n];
+            if (H.nc[n] >= sz - 1 && sz > 2) ++heavy;
+        }
+        for (int32_t v = 0; v < nv; ++v) single += cl[v] < 0;
+        fprintf(stderr, "    absorb nv=%d nets=%zu heavy=%lld clusters=%zu singletons=%lld maxw=%lld heavyw=%lld\n", nv,
+                order.size(), (long long)heavy, cw.size(), (long long)single, (long long)maxw, (long long)heavy_maxw);
+    }
+    std::vector<int32_t> ren(cw.size(), -1);
+    cmap.assign(nv, -1);
+    ncoarse = 0;
+    for (int32_t v = 0; v < nv; ++v) {
+        if (cl[v] < 0) { cmap[v] = ncoarse++; continue; }
+        if (ren[cl[v]] < 0) ren[cl[v]] = ncoarse++;
+        cmap[v] = ren[cl[v]];
+    }
+}
+
 // Contract clusters into a coarse hypergraph.  Nets reduced to one cluster
 // vanish, nets spanning more than kCoarseNetCap clusters are left out of the
 // coarse levels (they are cut by nearly every bisection and only slow the
@@ -592,7 +670,14 @@ int64_t bisect(const Hypergraph &H, double frac0, double eps, uint64_t seed,
         int32_t nc = 0;
         double t1 = now_s();
         // clusters may grow to a few times the current average vertex weight
-        match_hcc(*cur, maxw, rng, cmap, nc);
+        // absorption on the first level of very large hypergraphs, heavy
+        // connectivity clustering afterwards
+        if (levels.empty() && cur->nv > kAbsorbFrom) {
+            int64_t aw = std::min<int64_t>(maxw, std::max<int64_t>(maxv, 8 * (tot / cur->nv) + 1));
+            absorb_nets(*cur, aw, maxw, cmap, nc);
+        } else {
+            match_hcc(*cur, maxw, rng, cmap, nc);
+        }
         tm += now_s() - t1;
         if (debug_on() && H.nv > 500000)
             fprintf(stderr, "  level nv=%d nn=%d pins=%zu -> %d (maxw %lld)\n", cur->nv, cur->nn,
@@ -642,6 +727,69 @@ int64_t bisect(const Hypergraph &H, double frac0, double eps, uint64_t seed,
         fprintf(stderr, "bisect nv=%d nn=%d pins=%zu levels=%zu coarse=(%d,%d,%zu) match=%.2f contract=%.2f init=%.2f fm=%.2f total=%.2f cut=%lld\n",
                 H.nv, H.nn, H.pins.size(), maps.size(), coarse_nv, coarse_nn, coarse_pins, tm, tc, ti, tf, now_s() - tb, (long long)F.cut);
     return F.cut;
+}
+
+// Enhanced row-column-net model: a cut row net costs nnz(r_i); moving all of
+// the row's pins to the side holding most of them removes that cost and adds
+// at most one column-net cut per moved pin.  Single-vertex moves cannot see
+// this (the gain appears only at the last pin), so after each bisection every
+// cut row is moved whole when that strictly lowers the cutsize and keeps the
+// balance.  Returns the new cutsize.
+static int64_t uncut_rows(const Hypergraph &H, std::vector<uint8_t> &side, double frac0, double eps,
+                   int64_t cut) {
+    std::vector<int32_t> cnt0(H.nn, 0), cnt1(H.nn, 0);
+    int64_t W[2] = {0, 0}, tot = 0;
+    for (int32_t v = 0; v < H.nv; ++v) {
+        W[side[v]] += H.vw[v];
+        tot += H.vw[v];
+    }
+    int64_t maxW[2] = {(int64_t)(frac0 * (double)tot * (1.0 + eps)),
+                       (int64_t)((1.0 - frac0) * (double)tot * (1.0 + eps))};
+    for (int32_t n = 0; n < H.nn; ++n)
+        for (int64_t p = H.xpins[n]; p < H.xpins[n + 1]; ++p) (side[H.pins[p]] ? cnt1 : cnt0)[n]++;
+    std::vector<int32_t> *cnt[2] = {&cnt0, &cnt1};
+    for (int32_t r = 0; r < H.nn; ++r) {
+        if (!H.nrow[r] || cnt0[r] == 0 || cnt1[r] == 0) continue;
+        int s = cnt1[r] > cnt0[r] ? 1 : 0, o = 1 - s;
+        int64_t dw = 0, delta = -H.nc[r];
+        for (int64_t p = H.xpins[r]; p < H.xpins[r + 1]; ++p) {
+            int32_t u = H.pins[p];
+            if (side[u] != o) continue;
+            dw += H.vw[u];
+            for (int64_t q = H.xnets[u]; q < H.xnets[u + 1]; ++q) {
+                int32_t c = H.vnets[q];
+                if (c == r) continue;
+                bool was_cut = (*cnt[0])[c] > 0 && (*cnt[1])[c] > 0;
+                (*cnt[o])[c]--;
+                (*cnt[s])[c]++;
+                bool now_cut = (*cnt[0])[c] > 0 && (*cnt[1])[c] > 0;
+                delta += (int64_t)now_cut * H.nc[c] - (int64_t)was_cut * H.nc[c];
+            }
+        }
+        bool ok = delta < 0 && W[s] + dw <= maxW[s];
+        for (int64_t p = H.xpins[r]; p < H.xpins[r + 1]; ++p) {
+            int32_t u = H.pins[p];
+            if (side[u] != o) continue;
+            if (ok) {
+                side[u] = (uint8_t)s;
+            } else {
+                for (int64_t q = H.xnets[u]; q < H.xnets[u + 1]; ++q) {
+                    int32_t c = H.vnets[q];
+                    if (c == r) continue;
+                    (*cnt[s])[c]--;
+                    (*cnt[o])[c]++;
+                }
+            }
+        }
+        if (ok) {
+            (*cnt[s])[r] += (*cnt[o])[r];
+            (*cnt[o])[r] = 0;
+            W[s] += dw;
+            W[o] -= dw;
+            cut += delta;
+        }
+    }
+    return cut;
 }
 
 // ------------------------------------------------------------ RB driver
@@ -860,6 +1008,29 @@ void recurse(Ctx &C, Sub S, int32_t K, int32_t part, uint64_t path, int32_t dept
                          path * 2654435761ull + (uint64_t)depth + (leafmode ? 77 : 0));
     std::vector<uint8_t> side;
     int64_t c = bisect(S.H, frac0, C.eps, sseed, side);
+    if (!leafmode && C.model == Model::ERowColumnNet) {
+        int64_t c0 = c;
+        auto rows_cut = [&](int64_t &nnzc) {
+            int64_t k = 0;
+            nnzc = 0;
+            for (int32_t n = 0; n < S.H.nn; ++n) {
+                if (!S.H.nrow[n]) continue;
+                bool a = false, b = false;
+                for (int64_t p = S.H.xpins[n]; p < S.H.xpins[n + 1]; ++p) (side[S.H.pins[p]] ? b : a) = true;
+                if (a && b) { ++k; nnzc += S.H.xpins[n + 1] - S.H.xpins[n]; }
+            }
+            return k;
+        };
+        int64_t z0 = 0, z1 = 0, k0 = 0, k1 = 0;
+        bool dbg = getenv("SPX_DEBUG") && S.H.nv > 1000000;
+        if (dbg) k0 = rows_cut(z0);
+        c = uncut_rows(S.H, side, frac0, C.eps, c);
+        if (dbg) {
+            k1 = rows_cut(z1);
+            fprintf(stderr, "  ercn nv=%d cut %lld -> %lld, cut rows %lld (%lld nnz) -> %lld (%lld nnz)\n", S.H.nv,
+                    (long long)c0, (long long)c, (long long)k0, (long long)z0, (long long)k1, (long long)z1);
+        }
+    }
     if (!leafmode) C.cut += c;
     Sub out[2];
     std::vector<int32_t> removed;

@@ -356,25 +356,26 @@ void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) 
 
 // ----------------------------------------------------------------- schedule
 //
-// Row blocks: consecutive slots of one leaf whose nonzeros fit the
-// workgroup's staging buffer (nnz_per_block - 3, because loads start at a
-// 4-aligned nonzero); a slot longer than long_row gets a block of its own
-// and is reduced by the whole workgroup.  Tiles: up to blocks_per_tile
-// consecutive blocks of a leaf, processed by one workgroup with the leaf's
-// x window loaded into LDS once.  The window is the densest contiguous range
-// of at most window_entries columns among the leaf's nonzeros, kept only
-// when it serves at least half an x read per entry loaded.
+// Row blocks are ranges of nonzeros of one scheduling unit (a leaf, or the
+// row border of a DB form) of at most nnz_per_block - 3 nonzeros (loads
+// start at a 4-aligned nonzero) in which at most 2 wg rows start.  A row may
+// continue into the next block: blocks are balanced by nonzeros whatever the
+// row lengths.  Tiles are runs of at least blocks_per_tile consecutive
+// blocks of a unit that end where a row ends, so a row never leaves its tile
+// and its partial sum is carried from block to block inside one workgroup.
+// A tile's x window is the densest contiguous range of at most window_entries
+// columns among the unit's nonzeros, kept only when it serves at least half
+// an x read per entry loaded.
 void build_schedule(spx_plan_s &P) {
     const Tune &T = P.tune;
-    int32_t NT = T.nnz_per_block;
-    int32_t cap = NT - 3;
-    int32_t rmax = 4 * T.wg;
+    const int64_t cap = kChunkSpan - 3;
+    const int32_t rmax = kChunkRows;
+    const int32_t wpg = T.wg / 64;  // tiles (waves) per workgroup
     P.blk_slot.clear();
+    P.blk_desc.clear();
     P.tiles.clear();
     P.window_nnz = 0;
     P.window_bytes_fill = 0;
-    P.blk_slot.push_back(0);
-    // scheduling units: the leaves, then (DB) the row border as one more unit
     std::vector<std::pair<int32_t, int32_t>> units;
     std::vector<int32_t> unit_leaf;
     for (int32_t l = 0; l < P.nleaves; ++l) {
@@ -388,34 +389,46 @@ void build_schedule(spx_plan_s &P) {
         unit_leaf.push_back(-1);
     }
     std::vector<int32_t> cols;
+    auto close_block = [&](int32_t s_lo, int32_t s_hi, int32_t z_lo, int32_t z_hi) {
+        P.blk_desc.insert(P.blk_desc.end(), {s_lo, s_hi, z_lo, z_hi});
+    };
     for (size_t u = 0; u < units.size(); ++u) {
         int32_t s0 = units[u].first, s1 = units[u].second;
         if (s0 >= s1) continue;
-        size_t first_blk = P.blk_slot.size() - 1;
-        int32_t cur_lo = s0, cur_nnz = 0;
+        int32_t first_blk = (int32_t)(P.blk_desc.size() / 4);
+        // blocks
+        int32_t b_slo = s0, b_zlo = P.slot_ptr[s0], rows = 0;
         for (int32_t s = s0; s < s1; ++s) {
-            int32_t len = P.slot_ptr[s + 1] - P.slot_ptr[s];
-            if (len > T.long_row || len > cap) {
-                if (s > cur_lo) P.blk_slot.push_back(s);
-                P.blk_slot.push_back(s + 1);
-                cur_lo = s + 1;
-                cur_nnz = 0;
-                continue;
+            int32_t ps = P.slot_ptr[s], pe = P.slot_ptr[s + 1];
+            // a row that does not fit but would fit a fresh block starts one,
+            // when the current block is at least half full
+            if ((int64_t)pe - b_zlo > cap && pe - ps <= cap && 2 * ((int64_t)ps - b_zlo) >= cap) {
+                close_block(b_slo, s, b_zlo, ps);
+                b_slo = s;
+                b_zlo = ps;
+                rows = 0;
             }
-            if (s > cur_lo && (cur_nnz + len > cap || s - cur_lo >= rmax)) {
-                P.blk_slot.push_back(s);
-                cur_lo = s;
-                cur_nnz = 0;
+            ++rows;
+            while ((int64_t)pe - b_zlo > cap) {  // the row continues in a new block
+                int32_t cut = b_zlo + (int32_t)cap;
+                int32_t s_hi = ps < cut ? s + 1 : s;  // a row belongs where its first nonzero is
+                close_block(b_slo, s_hi, b_zlo, cut);
+                b_slo = s_hi;
+                b_zlo = cut;
+                rows = s_hi == s ? 1 : 0;
             }
-            cur_nnz += len;
+            if (rows >= rmax) {
+                close_block(b_slo, s + 1, b_zlo, pe);
+                b_slo = s + 1;
+                b_zlo = pe;
+                rows = 0;
+            }
         }
-        if (s1 > cur_lo) P.blk_slot.push_back(s1);
-        size_t last_blk = P.blk_slot.size() - 1;
+        if (b_slo < s1 || b_zlo < P.slot_ptr[s1]) close_block(b_slo, s1, b_zlo, P.slot_ptr[s1]);
+        int32_t last_blk = (int32_t)(P.blk_desc.size() / 4);
         // window of this unit
         int32_t wlo = 0, wlen = 0;
-        int32_t nblk = (int32_t)(last_blk - first_blk);
         int32_t B = std::max(1, T.blocks_per_tile);
-        int32_t ntile = (nblk + B - 1) / B;
         int32_t l = unit_leaf[u];
         if (T.window_entries > 0 && l >= 0) {
             int64_t z0 = P.slot_ptr[s0], z1 = P.slot_ptr[s1];
@@ -428,23 +441,48 @@ void build_schedule(spx_plan_s &P) {
                 while (j < cols.size() && cols[j] < (int64_t)cols[i] + T.window_entries) ++j;
                 if ((int64_t)(j - i) > best) { best = (int64_t)(j - i); bi = i; bj = j; }
             }
+            int32_t est_tiles = std::max(1, (last_blk - first_blk + B - 1) / B);
             if (best > 0) {
                 int32_t lo = cols[bi], hi = cols[bj - 1] + 1;
-                int64_t fill = (int64_t)ntile * (hi - lo);
+                int64_t fill = (int64_t)est_tiles * (hi - lo);
                 if (2 * best >= fill) {
                     wlo = lo;
                     wlen = hi - lo;
                     P.window_nnz += best;
-                    P.window_bytes_fill += fill * 8;
                 }
             }
         }
-        for (int32_t t = 0; t < ntile; ++t) {
-            int32_t b0 = (int32_t)first_blk + t * B;
-            int32_t b1 = std::min((int32_t)last_blk, b0 + B);
-            P.tiles.insert(P.tiles.end(), {b0, b1, wlo, wlen});
+        // the tiles of a workgroup share its LDS window (the window only
+        // decides where x is read from, so any grouping is correct): a unit
+        // with a window starts and ends on a workgroup boundary
+        if (wlen > 0)
+            while ((P.tiles.size() / 4) % wpg) P.tiles.insert(P.tiles.end(), {first_blk, first_blk, 0, 0});
+        size_t tiles_before = P.tiles.size() / 4;
+        // tiles: at least B blocks, ending where a row ends
+        int32_t t0 = first_blk;
+        for (int32_t b = first_blk; b < last_blk; ++b) {
+            const int32_t *d = &P.blk_desc[4 * (size_t)b];
+            bool row_ends = P.slot_ptr[d[1]] <= d[3];
+            if ((b + 1 - t0 >= B && row_ends) || b + 1 == last_blk) {
+                P.tiles.insert(P.tiles.end(), {t0, b + 1, wlo, wlen});
+                t0 = b + 1;
+            }
+        }
+        // the tiles of a workgroup share its LDS window: with windows, a
+        // unit's tiles fill whole workgroups (empty tiles pad the last one)
+        if (wlen > 0) {
+            while ((P.tiles.size() / 4) % wpg) P.tiles.insert(P.tiles.end(), {last_blk, last_blk, wlo, wlen});
+            P.window_bytes_fill += (int64_t)wlen * 8 * (int64_t)((P.tiles.size() / 4 - tiles_before) / wpg);
         }
     }
+    while ((P.tiles.size() / 4) % wpg) {
+        int32_t nb_ = (int32_t)(P.blk_desc.size() / 4);
+        P.tiles.insert(P.tiles.end(), {nb_, nb_, 0, 0});
+    }
+    int32_t nb = (int32_t)(P.blk_desc.size() / 4);
+    P.blk_slot.resize((size_t)nb + 1);
+    for (int32_t b = 0; b < nb; ++b) P.blk_slot[b] = P.blk_desc[4 * (size_t)b];
+    P.blk_slot[nb] = nslots;
 }
 
 }  // namespace spx

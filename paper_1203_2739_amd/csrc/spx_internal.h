@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/spx.h"
+#include "sched_limits.h"
 
 namespace spx {
 
@@ -77,7 +78,7 @@ DevPtr dev_alloc(size_t bytes);
 DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream);
 
 struct Tune {
-    int32_t wg = 256, nnz_per_block = 2048, blocks_per_tile = 1, window_entries = -1;
+    int32_t wg = 256, nnz_per_block = kChunkSpan, blocks_per_tile = 8, window_entries = -1;
     int32_t xcd_remap = 1, long_row = 1024;
 };
 Tune resolve_tune(const spx_tune *t, int form);
@@ -109,11 +110,12 @@ struct spx_plan_s {
     // schedule
     spx::Tune tune;
     std::vector<int32_t> blk_slot;              // [nblocks+1]
+    std::vector<int32_t> blk_desc;              // 4 per block: slot range, nonzero range
     std::vector<int32_t> tiles;                 // 4 per tile
     int64_t window_nnz = 0, window_bytes_fill = 0;
     // device copies
     spx::DevPtr d_slot_ptr, d_slot_row, d_colidx, d_vals, d_row_perm, d_col_perm;
-    spx::DevPtr d_blk_slot, d_tiles;
+    spx::DevPtr d_blk_desc, d_tiles;
     // statistics
     int64_t sum_lambda_col = 0, sum_lambda_row = 0, border_row_nnz = 0, cut = 0;
     double partition_seconds = 0.0, plan_seconds = 0.0;

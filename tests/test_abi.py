@@ -65,7 +65,7 @@ def test_bad_arguments():
     with pytest.raises(spx.SpxError):
         spx.plan_plain(M, tune=dict(wg_size=100))
     with pytest.raises(spx.SpxError):
-        spx.plan_plain(M, tune=dict(wg_size=256, nnz_per_block=300))
+        spx.plan_plain(M, tune=dict(wg_size=256, nnz_per_block=1024))
     with pytest.raises(spx.SpxError):
         spx.set_num_threads(0)
 
@@ -116,19 +116,34 @@ def check_split(orc, A, P, rp, cp, part, K):
 
 
 def check_schedule(P):
+    """Blocks cover every unit's nonzeros contiguously with at most
+    nnz_per_block - 3 nonzeros and 2 wg row starts each; every slot starts in
+    exactly one block; tiles cover the blocks and end where a row ends."""
     inf = P.info()
-    bs, tiles = P.export_sched()
-    nslots, NT = inf["nslots"], inf["nnz_per_block"]
-    assert bs[0] == 0 and bs[-1] == nslots and np.all(np.diff(bs) > 0)
+    bd, tiles = P.export_sched()
+    nslots, NT, wg = inf["nslots"], inf["nnz_per_block"], 64  # a chunk is one wave's
     if inf["form"] == 3:
-        sp = P.export_split()["slot_ptr"]
+        sp = P.export_split()["slot_ptr"].astype(np.int64)
     else:
-        sp = P.export_csr()[0]
-    blk_nnz = sp[bs[1:]] - sp[bs[:-1]]
-    multi = np.diff(bs) > 1
-    assert np.all(blk_nnz[multi] <= NT - 3)
+        sp = P.export_csr()[0].astype(np.int64)
+    if bd.shape[0] == 0:
+        assert nslots == 0 or sp[-1] == 0
+        return
+    s_lo, s_hi, z_lo, z_hi = (bd[:, i].astype(np.int64) for i in range(4))
+    assert np.all(z_hi - z_lo <= NT - 3) and np.all(z_hi >= z_lo)
+    assert np.all(s_hi - s_lo <= 4 * wg) and np.all(s_hi >= s_lo)
+    assert s_lo[0] == 0 and s_hi[-1] == nslots and np.all(s_lo[1:] == s_hi[:-1])
+    assert z_lo[0] == 0 and z_hi[-1] == sp[-1] and np.all(z_lo[1:] == z_hi[:-1])
+    # a slot starting in a block starts inside its nonzero range
+    for b in range(bd.shape[0]):
+        st = sp[s_lo[b]:s_hi[b]]
+        assert np.all((st >= z_lo[b]) & (st <= z_hi[b]))
+    assert tiles.shape[0] % (inf["wg_size"] // 64) == 0
+    tiles = tiles[tiles[:, 1] > tiles[:, 0]]  # drop the padding of workgroups
     assert tiles[0, 0] == 0 and tiles[-1, 1] == inf["nblocks"]
-    assert np.all(tiles[1:, 0] == tiles[:-1, 1]) and np.all(tiles[:, 1] > tiles[:, 0])
+    assert np.all(tiles[1:, 0] == tiles[:-1, 1])
+    ends = tiles[:, 1] - 1
+    assert np.all(sp[s_hi[ends]] <= z_hi[ends])
     assert np.all(tiles[:, 3] >= 0) and np.all(tiles[:, 2] + tiles[:, 3] <= inf["n"])
     assert np.all(tiles[:, 3] <= max(inf["window_entries"], 0))
 

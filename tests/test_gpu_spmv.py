@@ -44,12 +44,11 @@ def run_reordered(A, x, form, K, window_bytes=0, tune=None, seed=0):
 
 
 TUNES = [None,
-         dict(wg_size=256, nnz_per_block=1024),
-         dict(wg_size=512, nnz_per_block=2048),
-         dict(wg_size=512, nnz_per_block=4096),
-         dict(wg_size=1024, nnz_per_block=4096),
-         dict(wg_size=256, nnz_per_block=2048, xcd_remap=-1),
-         dict(wg_size=256, nnz_per_block=2048, long_row=64)]
+         dict(wg_size=64, blocks_per_tile=1),
+         dict(wg_size=128, blocks_per_tile=3),
+         dict(wg_size=256, blocks_per_tile=32),
+         dict(wg_size=256, blocks_per_tile=2, xcd_remap=-1),
+         dict(wg_size=64, blocks_per_tile=200)]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -152,7 +151,7 @@ def test_edge_shapes(orc, shape, long_len):
     m, n = shape
     A = odd_matrix(m * 7 + n, m, n, long_len=long_len if n >= long_len else 0)
     x = gen_vectors(107, n)[0]
-    for ti in (0, 1, 4):
+    for ti in (0, 1, 3, 5):
         y = run_plain(A, x, TUNES[ti])
         assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), f"plain {shape} {long_len}")
     if A.nnz:
@@ -181,7 +180,7 @@ def test_empty_matrices(orc):
 def test_rows_at_block_capacity(orc):
     """Rows whose lengths straddle the staging capacity (NT - 3, NT, NT + 1)
     and the long-row threshold."""
-    lens = [2045, 2046, 2048, 2049, 1024, 1025, 1, 0, 4093, 4096, 8190, 3]
+    lens = [1021, 1022, 1024, 1025, 2045, 2046, 2048, 2049, 1, 0, 4093, 4096, 8190, 3, 0, 0, 2]
     n = 9000
     rng = np.random.default_rng(3)
     cols = np.concatenate([np.sort(rng.choice(n, d, replace=False)) for d in lens])
