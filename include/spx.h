@@ -57,25 +57,30 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
 #define SPX_FORM_SPLIT 3 /* nonzero-disjoint splitting, Section 4           */
 
 /* Kernel schedule.  Any field set to 0 takes the library default.
- *   wg_size          threads per workgroup: 256, 512 or 1024
- *   nnz_per_block    nonzeros one workgroup stages per step: 4 per thread
- *                    (4 * wg_size, the default)
+ *   wg_size          threads per workgroup: 64, 128 (default), 256 or 512
+ *   nnz_per_block    nonzeros one workgroup stages per block: 4 * wg_size
+ *                    (default; 8 * wg_size for wg_size 64) or 8 * wg_size
+ *                    (every thread loads 4 or 8 consecutive nonzeros)
  *   blocks_per_tile  least number of row blocks one workgroup processes in
- *                    sequence (a tile also ends only where a row ends); the
+ *                    sequence (default 1; a tile never crosses a leaf); the
  *                    tile's x window is loaded into LDS once per tile
- *   window_entries   largest LDS x window in binary64 entries (0 = default,
- *                    -1 = no window); windows are contiguous column ranges
+ *   window_entries   largest LDS x window in binary64 entries (0 = default:
+ *                    none, -1 = none); at most 16384; windows are contiguous
+ *                    column ranges chosen per leaf
  *   xcd_remap        1 = map consecutive tiles to the same XCD (default),
  *                    -1 = hardware dispatch order
- *   long_row         unused (rows of any length are split across the blocks
- *                    of one tile)                                          */
+ *   reduce_iters     bound on the strided per-row reduction loop inside a
+ *                    block, 1..64 (default 64); smaller bounds make blocks of
+ *                    mixed row lengths hold fewer rows                       
+ * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
+ * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
     int32_t wg_size;
     int32_t nnz_per_block;
     int32_t blocks_per_tile;
     int32_t window_entries;
     int32_t xcd_remap;
-    int32_t long_row;
+    int32_t reduce_iters;
     int32_t reserved[2];
 } spx_tune;
 
@@ -100,6 +105,8 @@ typedef struct spx_plan_info_s {
     int64_t window_nnz;       /* nonzeros whose x entry is read from an LDS window */
     double partition_seconds; /* host time of the partitioner */
     double plan_seconds;      /* host time of ordering and table building */
+    int32_t reduce_iters;     /* bound on the per-row reduction loop of a block */
+    int32_t nlong_rows;       /* slots too long for one block, run as one-round segments */
 } spx_plan_info;
 
 const char *spx_last_error(void);

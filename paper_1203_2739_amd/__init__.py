@@ -33,7 +33,7 @@ class SpxError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("nnz_per_block", ctypes.c_int32),
                 ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("long_row", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
 
 
@@ -48,7 +48,8 @@ class PlanInfo(ctypes.Structure):
                 ("sum_lambda_row", ctypes.c_int64), ("border_row_nnz", ctypes.c_int64),
                 ("cut_connectivity", ctypes.c_int64), ("bytes_matrix", ctypes.c_int64),
                 ("bytes_window", ctypes.c_int64), ("window_nnz", ctypes.c_int64),
-                ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+                ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
+                ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p

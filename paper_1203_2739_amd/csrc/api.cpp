@@ -59,14 +59,18 @@ Tune resolve_tune(const spx_tune *t, int form) {
         if (t->blocks_per_tile) r.blocks_per_tile = t->blocks_per_tile;
         if (t->window_entries) r.window_entries = t->window_entries;
         if (t->xcd_remap) r.xcd_remap = t->xcd_remap > 0 ? 1 : 0;
+        if (t->reduce_iters) r.reduce_iters = t->reduce_iters;
     }
     if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512)
         fail(SPX_EINVAL, "wg_size must be 64, 128, 256 or 512");
-    if (r.nnz_per_block != kChunkSpan) fail(SPX_EINVAL, "nnz_per_block must be 256 (4 per lane of a wave)");
+    if (!t || !t->nnz_per_block) r.nnz_per_block = (r.wg == 64 ? 8 : kDefaultNpt) * r.wg;
+    if (r.nnz_per_block != 4 * r.wg && r.nnz_per_block != 8 * r.wg)
+        fail(SPX_EINVAL, "nnz_per_block must be 4 or 8 times wg_size (nonzeros per thread)");
+    if (r.reduce_iters < 1 || r.reduce_iters > 64) fail(SPX_EINVAL, "reduce_iters must be in 1..64");
     if (r.blocks_per_tile < 1) fail(SPX_EINVAL, "blocks_per_tile must be >= 1");
     if (r.window_entries < 0) r.window_entries = -1;
     int wmax = 0;
-    if (!spmv_variant_exists(r.wg, r.window_entries, &wmax))
+    if (!spmv_variant_exists(r.wg, r.nnz_per_block / r.wg, r.window_entries, &wmax))
         fail(SPX_EUNSUPPORTED, "no kernel variant for this wg_size / window");
     return r;
 }
@@ -164,6 +168,14 @@ void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream) {
     }
     P.d_blk_desc = dev_upload(P.blk_desc.data(), P.blk_desc.size() * 4, 16, stream);
     P.d_tiles = dev_upload(P.tiles.data(), P.tiles.size() * 4, 16, stream);
+    P.d_long_seg_ptr = dev_upload(P.long_seg_ptr.data(), P.long_seg_ptr.size() * 4, 16, stream);
+    {
+        size_t nlong = P.long_seg_ptr.empty() ? 0 : P.long_seg_ptr.size() - 1;
+        size_t nseg = nlong ? (size_t)P.long_seg_ptr.back() : 0;
+        P.d_partials = dev_alloc(nseg * 8 + 16);
+        P.d_counters = dev_alloc(nlong * 4 + 16);
+        hip_check(hipMemsetAsync(P.d_counters->ptr, 0, nlong * 4 + 16, (hipStream_t)stream), "counter init");
+    }
     hip_check(hipStreamSynchronize((hipStream_t)stream), "plan upload");
     P.on_device = true;
 }
@@ -172,11 +184,7 @@ void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream) {
 static void apply_tune(spx_plan_s &P, const spx_tune *tune, int64_t window_bytes) {
     spx_tune t{};
     if (tune) t = *tune;
-    if (!tune || t.window_entries == 0) {
-        // default: the partition's window budget, when one was given
-        t.window_entries = window_bytes > 0 ? (int32_t)std::min<int64_t>(window_bytes / 8, 12288) : -1;
-    }
-    if (t.window_entries > 0 && (!tune || t.wg_size == 0)) t.wg_size = t.window_entries > 8192 ? 512 : 256;
+    (void)window_bytes;  // leaves are sized by the partition; LDS windows only on request
     P.tune = resolve_tune(&t, P.form);
     build_schedule(P);
 }
@@ -223,9 +231,13 @@ static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t
     a.y = y;
     a.blk_desc = (const int32_t *)P.d_blk_desc->ptr;
     a.tiles = (const int32_t *)P.d_tiles->ptr;
-    a.ntiles = (int32_t)(P.tiles.size() / 4) / (P.tune.wg / 64);  // workgroups
+    const bool tl = tiled(P.tune);
+    a.ntiles = (int32_t)(tl ? P.tiles.size() / 4 : P.blk_desc.size() / 4);
     a.xcd_remap = P.tune.xcd_remap;
     a.n = P.n;
+    a.long_seg_ptr = (const int32_t *)P.d_long_seg_ptr->ptr;
+    a.partials = (double *)P.d_partials->ptr;
+    a.counters = (uint32_t *)P.d_counters->ptr;
     bool split = P.form == SPX_FORM_SPLIT;
     if (split) {
         a.shared_begin = P.row_border_begin;
@@ -235,7 +247,8 @@ static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t
             if (e != hipSuccess) return e;
         }
     }
-    return launch_spmv(a, P.tune.wg, P.tune.window_entries, split, s);
+
+    return launch_spmv(a, P.tune.wg, P.tune.nnz_per_block / P.tune.wg, P.tune.window_entries, tl, split, s);
 }
 
 extern "C" {
@@ -357,6 +370,8 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->window_nnz = P->window_nnz;
         info->partition_seconds = P->partition_seconds;
         info->plan_seconds = P->plan_seconds;
+        info->reduce_iters = P->tune.reduce_iters;
+        info->nlong_rows = P->long_seg_ptr.empty() ? 0 : (int32_t)P->long_seg_ptr.size() - 1;
     });
 }
 

@@ -20,17 +20,21 @@ struct SpmvArgs {
     double *y;
     const int32_t *blk_desc;  // 4 per block: first slot, end slot, first nonzero, end nonzero
     const int32_t *tiles;     // 4 per tile: first block, end block, window lo, window len
-    int32_t ntiles;
+    int32_t ntiles;           // workgroups: tiles, or blocks when not tiled
     int32_t shared_begin;     // split: rows >= this are accumulated atomically
     int32_t accumulate;       // split: add to y for rows owned by one leaf
     int32_t xcd_remap;
     int32_t n;                // columns (no gathers when 0)
+    const int32_t *long_seg_ptr;  // [nlong+1] partial-sum entries of each long slot
+    double *partials;             // one per long-slot segment
+    uint32_t *counters;           // one per long slot, zero between products
 };
 
-// wg = 64 * waves per workgroup; each wave owns one tile, ntiles counts
-// workgroups.
-bool spmv_variant_exists(int wg, int window_entries, int *wmax_out);
-hipError_t launch_spmv(const SpmvArgs &a, int wg, int window_entries, bool split, hipStream_t s);
+// One workgroup of wg threads per tile (tiled) or per block (not tiled);
+// ntiles counts workgroups.  npt = nonzeros staged per thread.
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out);
+hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
+                       hipStream_t s);
 hipError_t launch_fill(double *y, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_gather(const double *x, const int32_t *perm, double *out, int64_t n, hipStream_t s);
 hipError_t launch_scatter(const double *yhat, const int32_t *perm, double *y, int64_t m, hipStream_t s);

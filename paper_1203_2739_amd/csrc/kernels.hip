@@ -3,26 +3,22 @@
 // The SpMV is bound by HBM streaming of the matrix (12 bytes per binary64
 // nonzero against 2 flops), so the kernels are organised around memory:
 //
-//  * A workgroup processes a tile: a run of row blocks of one leaf.  A row
-//    block is a range of consecutive slots (rows, or the non-empty rows of a
-//    split leaf) whose nonzeros fit the staging buffer.
-//  * Phase 1 streams the block's column indices and values with 16-byte
-//    non-temporal loads starting at a 4-aligned nonzero (every lane fetches
-//    4 consecutive nonzeros per load triple), gathers x -- from the tile's
-//    LDS window when the column falls inside it, else through L2 -- and
-//    stores the products in LDS.
-//  * Phase 2 reduces the products row by row: each row gets a power-of-two
-//    group of lanes (the block's thread count divided by its row count,
-//    capped at a wave) that sum strided products and combine them with DPP
-//    (lane distance 1, 2), ds_swizzle (4, 8, 16) and a cross-half permute (32).
-//  * A block made of a single slot (a long row) is reduced by the whole
-//    workgroup: every lane accumulates in registers, then waves combine in
-//    LDS.
-//  * Tiles are assigned to XCDs in contiguous chunks: the hardware hands out
-//    workgroups to the 8 XCDs round robin, so workgroup b runs tile
-//    start(b mod 8) + b div 8.  The tiles of a part then run on one XCD and
-//    its x entries stay in that XCD's L2, the GPU counterpart of a part that
-//    "fits into the cache" (Section 3, Theorem 1).
+//  * One workgroup runs one row block (or, when tiles are requested, a run of
+//    blocks of one leaf sharing an LDS x window).  A block is a range of
+//    whole consecutive slots (rows, or the non-empty rows of a split leaf)
+//    whose nonzeros fit one load round: every thread fetches 4 or 8
+//    consecutive nonzeros with 16-byte non-temporal loads from a 4-aligned
+//    start, so the workgroup issues all of its HBM traffic at once.
+//  * Products go to LDS; each row is then summed by a power-of-two group of
+//    lanes with DPP (lane distance 1, 2), ds_swizzle (4, 8, 16) and a
+//    cross-half permute (32).
+//  * A slot too long for one block is cut into one-round segments whose
+//    partial sums are combined by the last segment to finish.
+//  * Blocks are assigned to XCDs in contiguous chunks: the hardware hands out
+//    workgroups to the 8 XCDs round robin, so workgroup b runs block
+//    start(b mod 8) + b div 8.  Consecutive blocks of a part then run on one
+//    XCD and share its x entries in that XCD's L2, the GPU counterpart of a
+//    part that fits into the cache (Section 3, Theorem 1).
 //  * Split products (y <- y + A^k x, Section 4) store rows owned by a single
 //    leaf directly and add rows shared by several leaves with binary64
 //    atomics after the shared range was zeroed.
@@ -71,13 +67,6 @@ __device__ __forceinline__ double xor_lanes(double v, int off) {
     return __hiloint2double(hi, lo);
 }
 
-// Sum over aligned groups of g lanes (g a power of two, at most 64); every
-// lane of the group receives the total.  Must be reached by the whole wave.
-__device__ __forceinline__ double group_sum(double v, int g) {
-    for (int off = 1; off < g; off <<= 1) v += xor_lanes(v, off);
-    return v;
-}
-
 __device__ __forceinline__ int remap_tile(int bid, int ntiles, int on) {
     if (!on) return bid;
     int x = bid & 7, i = bid >> 3;
@@ -85,19 +74,20 @@ __device__ __forceinline__ int remap_tile(int bid, int ntiles, int on) {
     return x * per + (x < rem ? x : rem) + i;
 }
 
+// Writes the sum of one slot: an atomic add for rows shared by several
+// leaves of a split, an add for a split product that accumulates, a plain
+// store otherwise.
 template <bool SPLIT>
 __device__ __forceinline__ void store_row(double *__restrict__ y, const int32_t *__restrict__ slot_row,
                                           int32_t slot, double v, int32_t shared_begin,
                                           int32_t accumulate) {
-    if (SPLIT) {
-        int32_t row = slot_row[slot];
-        if (row >= shared_begin) {
-            unsafeAtomicAdd(&y[row], v);
-        } else {
-            y[row] = accumulate ? y[row] + v : v;
-        }
+    const int32_t row = SPLIT ? slot_row[slot] : slot;
+    if (SPLIT && row >= shared_begin) {
+        unsafeAtomicAdd(&y[row], v);
+    } else if (SPLIT && accumulate) {
+        y[row] += v;
     } else {
-        y[slot] = v;
+        y[row] = v;
     }
 }
 
@@ -113,200 +103,151 @@ __device__ __forceinline__ double xval(const double *__restrict__ x, const doubl
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Wave-level SpMV.  Every wave owns a tile: a run of chunks of at most 253
-// nonzeros (loads start at a 4-aligned nonzero, so a chunk spans at most
-// 256 = 4 per lane) in which at most 256 rows start.  A row may continue
-// from one chunk into the next of the same tile; its partial sum is carried
-// in scalar registers.  Waves never wait for each other: the only workgroup
-// barrier follows the load of the group's shared LDS x window.
-
-constexpr int kRowPtrPerLane = (kChunkRows + 1 + 63) / 64;
-
-struct Stage {
-    int32_t s_lo, s_hi, z_lo, z_hi;
-    v4i cc;
-    v2d va, vb;
-    int32_t rp[kRowPtrPerLane];
-};
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Sum over aligned groups of g lanes (g a power of two, at most 64); every
+// lane of the group receives the total.  Must be reached by the whole wave.
+__device__ __forceinline__ double group_sum_unrolled(double v, int g) {
+    if (g > 1) v += xor_lanes(v, 1);
+    if (g > 2) v += xor_lanes(v, 2);
+    if (g > 4) v += xor_lanes(v, 4);
+    if (g > 8) v += xor_lanes(v, 8);
+    if (g > 16) v += xor_lanes(v, 16);
+    if (g > 32) v += xor_lanes(v, 32);
+    return v;
 }
 
-// Every load is issued unconditionally (out-of-range lanes read a clamped,
-// valid address; their values are masked later), so the number of loads in
-// flight is known at compile time and waiting for the oldest ones does not
-// drain the younger prefetches.
-__device__ __forceinline__ void issue_chunk(const SpmvArgs &a, v4i d, int lane, Stage &st) {
+// One multi-row block: whole slots [d.x, d.y) with nonzeros [d.z, d.w).
+template <int WG, int NPT, bool SPLIT, int WMAX>
+__device__ __forceinline__ void multi_row_block(const SpmvArgs &a, const v4i d, double *sprod, int32_t *sptr,
+                                                const double *swin, int32_t wlo, int32_t wlen) {
+    const int tid = threadIdx.x;
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
     const v2d *__restrict__ v2 = reinterpret_cast<const v2d *>(a.vals);
-    // the descriptor is uniform across the wave: keep it in scalar registers
-    st.s_lo = __builtin_amdgcn_readfirstlane(d.x);
-    st.s_hi = __builtin_amdgcn_readfirstlane(d.y);
-    st.z_lo = __builtin_amdgcn_readfirstlane(d.z);
-    st.z_hi = __builtin_amdgcn_readfirstlane(d.w);
-    const int32_t nr = st.s_hi - st.s_lo;
-    const int32_t zb = st.z_lo & ~3;
-    const int32_t G = (st.z_hi - zb + 3) >> 2;
-    const int32_t g = min(lane, G > 0 ? G - 1 : 0);
-    st.cc = __builtin_nontemporal_load(&c4[(zb >> 2) + g]);
-    st.va = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * g]);
-    st.vb = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * g + 1]);
+    const int32_t zb = d.z & ~3;
+    const int32_t nr = d.y - d.x;
+    const int32_t G = (d.w - zb + 3) >> 2;
 #pragma unroll
-    for (int k = 0; k < kRowPtrPerLane; ++k) st.rp[k] = a.slot_ptr[st.s_lo + min(lane + 64 * k, nr)];
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid + u * WG;
+        if (gi < G) {
+            const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
+            const v2d va = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi]);
+            const v2d vb = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi + 1]);
+            v2d *sp = reinterpret_cast<v2d *>(&sprod[4 * gi]);
+            sp[0] = v2d{va.x * xval<WMAX>(a.x, swin, cc.x, wlo, wlen), va.y * xval<WMAX>(a.x, swin, cc.y, wlo, wlen)};
+            sp[1] = v2d{vb.x * xval<WMAX>(a.x, swin, cc.z, wlo, wlen), vb.y * xval<WMAX>(a.x, swin, cc.w, wlo, wlen)};
+        }
+    }
+    for (int i = tid; i <= nr; i += WG) sptr[i] = a.slot_ptr[d.x + i] - zb;
+    __syncthreads();
+    // lanes per row: the largest power of two <= WG / nr, at most 64
+    const int q = WG / nr;
+    const int lg = q >= 64 ? 6 : 31 - __builtin_clz(q);
+    const int g = 1 << lg;
+    const int grp = tid >> lg, lane = tid & (g - 1);
+    double sum = 0.0;
+    if (grp < nr) {
+        const int k1 = sptr[grp + 1];
+        for (int k = sptr[grp] + lane; k < k1; k += g) sum += sprod[k];
+    }
+    sum = group_sum_unrolled(sum, g);
+    if (grp < nr && lane == 0) store_row<SPLIT>(a.y, a.slot_row, d.x + grp, sum, a.shared_begin, a.accumulate);
 }
 
-// Wave-private LDS.
-struct WaveSmem {
-    uint32_t flag[8];             // row-start bits of the 256 staged nonzeros
-    int32_t row[256];             // slot id at each row start
-    int32_t ptr[64 * kRowPtrPerLane];
-};
-
-// One chunk.  Gathers of x for the staged nonzeros are issued first, then
-// the loads of the next chunk, so both latencies overlap.  Lane t holds the
-// products of nonzeros 4t .. 4t+3.  Rows starting in the chunk are marked in
-// LDS; a lane finishes the rows lying inside it and keeps the sum before its
-// first row start (head) and of its last open row (tail); a segmented scan
-// over the 64 lanes finishes the rows spanning lanes; the row still open at
-// the end of the chunk is carried to the next chunk (cv, cr).
-template <bool SPLIT, int WMAX>
-__device__ __forceinline__ void run_chunk(const SpmvArgs &a, v4i dn, int lane, Stage &cur,
-                                          Stage &nxt, WaveSmem &ws, const double *swin,
-                                          int32_t wlo, int32_t wlen, double &cv, int32_t &cr) {
-    const double *__restrict__ x = a.x;
-    const int32_t s_lo = cur.s_lo, z_lo = cur.z_lo, z_hi = cur.z_hi;
-    const int32_t nr = cur.s_hi - s_lo;
-    const int32_t zb = z_lo & ~3;
-
-    double xv[4];
-    if (a.n > 0) {
-        xv[0] = xval<WMAX>(x, swin, cur.cc.x, wlo, wlen);
-        xv[1] = xval<WMAX>(x, swin, cur.cc.y, wlo, wlen);
-        xv[2] = xval<WMAX>(x, swin, cur.cc.z, wlo, wlen);
-        xv[3] = xval<WMAX>(x, swin, cur.cc.w, wlo, wlen);
-    } else {
-        xv[0] = xv[1] = xv[2] = xv[3] = 0.0;
-    }
-    issue_chunk(a, dn, lane, nxt);
-
+// One segment [d.z, d.w) of long slot d.x: one load round like a multi-row
+// block, summed in registers and across waves.  A slot cut into several
+// segments combines them without atomics on y: each segment stores its
+// partial sum, and the workgroup that arrives last (counted by an atomic
+// counter) adds the partials in segment order, writes the slot and resets
+// the counter for the next product.
+template <int WG, int NPT, bool SPLIT, int WMAX>
+__device__ __forceinline__ void long_row_segment(const SpmvArgs &a, const v4i d, double *swave,
+                                                 const double *swin, int32_t wlo, int32_t wlen) {
+    const int tid = threadIdx.x;
+    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
+    const v2d *__restrict__ v2 = reinterpret_cast<const v2d *>(a.vals);
+    const int32_t zb = d.z & ~3;
+    const int32_t G = (d.w - zb + 3) >> 2;
+    double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < kRowPtrPerLane; ++k) {
-        int32_t i = lane + 64 * k;
-        if (i <= nr) ws.ptr[i] = cur.rp[k] - zb;
-    }
-    if (lane < 8) ws.flag[lane] = 0u;
-    const int32_t z = zb + 4 * lane;
-    double p[4];
-    p[0] = (z + 0 >= z_lo && z + 0 < z_hi) ? cur.va.x * xv[0] : 0.0;
-    p[1] = (z + 1 >= z_lo && z + 1 < z_hi) ? cur.va.y * xv[1] : 0.0;
-    p[2] = (z + 2 >= z_lo && z + 2 < z_hi) ? cur.vb.x * xv[2] : 0.0;
-    p[3] = (z + 3 >= z_lo && z + 3 < z_hi) ? cur.vb.y * xv[3] : 0.0;
-    wave_sync();
-    // mark the first nonzero of every non-empty row; empty rows are zero
-    for (int32_t r = lane; r < nr; r += 64) {
-        int32_t lo = ws.ptr[r], hi = ws.ptr[r + 1];
-        if (lo == hi) {
-            store_row<SPLIT>(a.y, a.slot_row, s_lo + r, 0.0, a.shared_begin, a.accumulate);
-        } else {
-            atomicOr(&ws.flag[lo >> 5], 1u << (lo & 31));
-            ws.row[lo] = s_lo + r;
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid + u * WG;
+        if (gi < G) {
+            const int32_t k0 = zb + 4 * gi;
+            const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
+            const v2d va = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi]);
+            const v2d vb = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi + 1]);
+            const double p0 = va.x * xval<WMAX>(a.x, swin, cc.x, wlo, wlen);
+            const double p1 = va.y * xval<WMAX>(a.x, swin, cc.y, wlo, wlen);
+            const double p2 = vb.x * xval<WMAX>(a.x, swin, cc.z, wlo, wlen);
+            const double p3 = vb.y * xval<WMAX>(a.x, swin, cc.w, wlo, wlen);
+            acc += (k0 >= d.z) ? p0 : 0.0;
+            acc += (k0 + 1 >= d.z && k0 + 1 < d.w) ? p1 : 0.0;
+            acc += (k0 + 2 >= d.z && k0 + 2 < d.w) ? p2 : 0.0;
+            acc += (k0 + 3 >= d.z && k0 + 3 < d.w) ? p3 : 0.0;
         }
     }
-    const bool row_ends = ws.ptr[nr] + zb <= z_hi;  // no row continues past the chunk
-    wave_sync();
-    const uint32_t f = (ws.flag[lane >> 3] >> ((lane & 7) * 4)) & 0xFu;
-    double head = 0.0, tail = 0.0;
-    int32_t trow = -1;
+    acc = group_sum_unrolled(acc, 64);
+    if ((tid & 63) == 0) swave[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double part = 0.0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        if ((f >> e) & 1u) {
-            if (trow >= 0) store_row<SPLIT>(a.y, a.slot_row, trow, tail, a.shared_begin, a.accumulate);
-            trow = ws.row[4 * lane + e];
-            tail = p[e];
-        } else if (trow >= 0) {
-            tail += p[e];
+        for (int w = 0; w < WG / 64; ++w) part += swave[w];
+        const int32_t lr = -1 - d.y;
+        const int32_t base = a.long_seg_ptr[lr];
+        const int32_t nseg = a.long_seg_ptr[lr + 1] - base;
+        if (nseg == 1) {
+            store_row<SPLIT>(a.y, a.slot_row, d.x, part, a.shared_begin, a.accumulate);
         } else {
-            head += p[e];
+            const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / (NPT * WG);
+            // The partial goes to the device-coherent level (an agent-scope
+            // atomic store writes through the XCD's L2) and must have landed
+            // before the counter moves: wait for the store to complete.  An
+            // acquire/release fence would also write back and invalidate the
+            // whole L2 of the XCD, discarding the cached x entries.
+            __hip_atomic_store(&a.partials[base + seg], part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): expcnt and lgkmcnt left unconstrained
+            const uint32_t done =
+                __hip_atomic_fetch_add(&a.counters[lr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (done == (uint32_t)nseg - 1) {
+                double sum = 0.0;
+                for (int32_t k = 0; k < nseg; ++k)
+                    sum += __hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                store_row<SPLIT>(a.y, a.slot_row, d.x, sum, a.shared_begin, a.accumulate);
+            }
         }
     }
-    // segmented inclusive scan of (open row, partial sum) over the lanes
-    double v = trow >= 0 ? tail : head;
-    int32_t rw = trow;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        double vo = __shfl_up(v, off);
-        int32_t ro = __shfl_up(rw, off);
-        if (lane >= off && rw < 0) {
-            v += vo;
-            rw = ro;
-        }
-    }
-    if (rw < 0) {
-        v += cv;
-        rw = cr;
-    }
-    double av = __shfl_up(v, 1);
-    int32_t ar = __shfl_up(rw, 1);
-    if (lane == 0) {
-        av = cv;
-        ar = cr;
-    }
-    if (f != 0u && ar >= 0) store_row<SPLIT>(a.y, a.slot_row, ar, av + head, a.shared_begin, a.accumulate);
-    const int32_t t_end = (z_hi - zb - 1) >> 2;  // lane of the chunk's last nonzero (uniform)
-    if (t_end >= 0) {
-        double ov = f != 0u ? tail : av + head;
-        int32_t orow = f != 0u ? trow : ar;
-        if (row_ends) {
-            if (lane == t_end && orow >= 0)
-                store_row<SPLIT>(a.y, a.slot_row, orow, ov, a.shared_begin, a.accumulate);
-            cv = 0.0;
-            cr = -1;
-        } else {
-            cv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ov), t_end),
-                                  __builtin_amdgcn_readlane(__double2loint(ov), t_end));
-            cr = __builtin_amdgcn_readlane(orow, t_end);
-        }
-    }
-    wave_sync();
 }
 
-template <int WPG, bool SPLIT, int WMAX>
-__global__ __launch_bounds__(64 * WPG) void spmv_waves(SpmvArgs a) {
-    __shared__ WaveSmem wsm[WPG];
+// TILED = false: workgroup i runs block remap(i), no window.  TILED = true:
+// workgroup i runs the blocks of tile remap(i) with the tile's LDS window.
+template <int WG, int NPT, bool SPLIT, int WMAX, bool TILED>
+__global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgs a) {
+    __shared__ double sprod[NPT * WG];
+    __shared__ int32_t sptr[WG + 1];
+    __shared__ double swave[WG / 64];
     __shared__ double swin[WMAX > 0 ? WMAX : 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int group = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
-    const v4i *__restrict__ tiles = reinterpret_cast<const v4i *>(a.tiles);
-    const v4i *__restrict__ desc = reinterpret_cast<const v4i *>(a.blk_desc);
-    const v4i t4 = tiles[group * WPG + wave];
-    const int32_t b0 = __builtin_amdgcn_readfirstlane(t4.x);
-    const int32_t b1 = __builtin_amdgcn_readfirstlane(t4.y);
-    int32_t wlo = 0, wlen = 0;
-    Stage s0, s1;
-    if (b0 < b1) issue_chunk(a, desc[b0], lane, s0);
-    if (WMAX > 0) {
-        // the tiles of a group share one LDS x window
-        const v4i g4 = tiles[group * WPG];
-        wlo = __builtin_amdgcn_readfirstlane(g4.z);
-        wlen = __builtin_amdgcn_readfirstlane(g4.w);
-        for (int i = threadIdx.x; i < wlen; i += 64 * WPG) swin[i] = a.x[wlo + i];
+    const int tid = threadIdx.x;
+    const int id = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
+    if (!TILED) {
+        const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
+        if (d.y >= 0) multi_row_block<WG, NPT, SPLIT, 0>(a, d, sprod, sptr, swin, 0, 0);
+        else long_row_segment<WG, NPT, SPLIT, 0>(a, d, swave, swin, 0, 0);
+        return;
+    }
+    const v4i tl = reinterpret_cast<const v4i *>(a.tiles)[id];
+    const int32_t wlo = tl.z;
+    const int32_t wlen = WMAX > 0 ? tl.w : 0;
+    if (WMAX > 0 && wlen > 0) {
+        for (int i = tid; i < wlen; i += WG) swin[i] = a.x[wlo + i];
         __syncthreads();
     }
-    if (b0 >= b1) return;
-    WaveSmem &ws = wsm[wave];
-    double cv = 0.0;
-    int32_t cr = -1;
-    // two register stages alternate so that no load result is copied
-    for (int32_t b = b0; b < b1; b += 2) {
-        v4i dn = desc[b + 1 < b1 ? b + 1 : b];
-        run_chunk<SPLIT, WMAX>(a, dn, lane, s0, s1, ws, swin, wlo, wlen, cv, cr);
-        if (b + 1 >= b1) break;
-        dn = desc[b + 2 < b1 ? b + 2 : b + 1];
-        run_chunk<SPLIT, WMAX>(a, dn, lane, s1, s0, ws, swin, wlo, wlen, cv, cr);
+    for (int b = tl.x; b < tl.y; ++b) {
+        const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[b];
+        if (d.y >= 0) multi_row_block<WG, NPT, SPLIT, WMAX>(a, d, sprod, sptr, swin, wlo, wlen);
+        else long_row_segment<WG, NPT, SPLIT, WMAX>(a, d, swave, swin, wlo, wlen);
+        __syncthreads();
     }
 }
 
@@ -372,36 +313,48 @@ __global__ __launch_bounds__(kStreamWG) void stream_copy_kernel(const v2d *__res
 // ----------------------------------------------------------------- launchers
 
 namespace {
-template <int WPG, int WMAX>
-hipError_t launch_variant(const SpmvArgs &a, bool split, hipStream_t s) {
+template <int WG, int NPT, int WMAX>
+hipError_t launch_variant(const SpmvArgs &a, bool split, bool tiled, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
-    // a.ntiles counts workgroups here: WPG tiles each
-    if (split)
-        hipLaunchKernelGGL((spmv_waves<WPG, true, WMAX>), dim3(a.ntiles), dim3(64 * WPG), 0, s, a);
-    else
-        hipLaunchKernelGGL((spmv_waves<WPG, false, WMAX>), dim3(a.ntiles), dim3(64 * WPG), 0, s, a);
+    if (WMAX == 0 && !tiled) {
+        if (split)
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, 0, false>), dim3(a.ntiles), dim3(WG), 0, s, a);
+        else
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, 0, false>), dim3(a.ntiles), dim3(WG), 0, s, a);
+    } else {
+        if (split)
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, WMAX, true>), dim3(a.ntiles), dim3(WG), 0, s, a);
+        else
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, WMAX, true>), dim3(a.ntiles), dim3(WG), 0, s, a);
+    }
     return hipGetLastError();
 }
 }  // namespace
 
 struct Variant {
-    int wg, wmax;
-    hipError_t (*fn)(const SpmvArgs &, bool, hipStream_t);
+    int wg, npt, wmax;
+    hipError_t (*fn)(const SpmvArgs &, bool, bool, hipStream_t);
 };
 
 static const Variant kVariants[] = {
-    {64, 0, launch_variant<1, 0>},
-    {128, 0, launch_variant<2, 0>},
-    {256, 0, launch_variant<4, 0>},
-    {256, 4096, launch_variant<4, 4096>},
-    {256, 8192, launch_variant<4, 8192>},
-    {512, 12288, launch_variant<8, 12288>},
+    {64, 8, 0, launch_variant<64, 8, 0>},
+    {128, 4, 0, launch_variant<128, 4, 0>},
+    {128, 8, 0, launch_variant<128, 8, 0>},
+    {256, 4, 0, launch_variant<256, 4, 0>},
+    {512, 4, 0, launch_variant<512, 4, 0>},
+    {128, 4, 4096, launch_variant<128, 4, 4096>},
+    {128, 4, 8192, launch_variant<128, 4, 8192>},
+    {128, 4, 16384, launch_variant<128, 4, 16384>},
+    {256, 4, 4096, launch_variant<256, 4, 4096>},
+    {256, 4, 8192, launch_variant<256, 4, 8192>},
+    {256, 4, 16384, launch_variant<256, 4, 16384>},
+    {512, 4, 16384, launch_variant<512, 4, 16384>},
 };
 
-bool spmv_variant_exists(int wg, int window_entries, int *wmax_out) {
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out) {
     int best = -1;
     for (const Variant &v : kVariants) {
-        if (v.wg != wg) continue;
+        if (v.wg != wg || v.npt != npt) continue;
         if (window_entries <= 0 ? v.wmax == 0 : v.wmax >= window_entries) {
             if (best < 0 || v.wmax < best) best = v.wmax;
         }
@@ -411,11 +364,12 @@ bool spmv_variant_exists(int wg, int window_entries, int *wmax_out) {
     return true;
 }
 
-hipError_t launch_spmv(const SpmvArgs &a, int wg, int window_entries, bool split, hipStream_t s) {
+hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
+                       hipStream_t s) {
     int wmax = 0;
-    if (!spmv_variant_exists(wg, window_entries, &wmax)) return hipErrorInvalidValue;
+    if (!spmv_variant_exists(wg, npt, window_entries, &wmax)) return hipErrorInvalidValue;
     for (const Variant &v : kVariants)
-        if (v.wg == wg && v.wmax == wmax) return v.fn(a, split, s);
+        if (v.wg == wg && v.npt == npt && v.wmax == wmax) return v.fn(a, split, tiled, s);
     return hipErrorInvalidValue;
 }
 

@@ -355,25 +355,33 @@ void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) 
 }
 
 // ----------------------------------------------------------------- schedule
-//
-// Row blocks are ranges of nonzeros of one scheduling unit (a leaf, or the
-// row border of a DB form) of at most nnz_per_block - 3 nonzeros (loads
-// start at a 4-aligned nonzero) in which at most 2 wg rows start.  A row may
-// continue into the next block: blocks are balanced by nonzeros whatever the
-// row lengths.  Tiles are runs of at least blocks_per_tile consecutive
-// blocks of a unit that end where a row ends, so a row never leaves its tile
-// and its partial sum is carried from block to block inside one workgroup.
-// A tile's x window is the densest contiguous range of at most window_entries
-// columns among the unit's nonzeros, kept only when it serves at least half
-// an x read per entry loaded.
+
+// Lanes the kernel gives to each row of a block of nr rows: the largest
+// power of two <= wg / nr, at most a wave.
+static int32_t lanes_per_row(int32_t wg, int32_t nr) {
+    int32_t q = wg / nr, g = 1;
+    while (g * 2 <= q && g < 64) g *= 2;
+    return g;
+}
+
+// Row blocks and tiles.  A multi-row block holds whole consecutive slots of
+// one unit (a leaf, or the rows outside all leaves) while (i) its nonzeros
+// span at most nnz_per_block entries from the 4-aligned start, (ii) it has at most
+// wg slots and (iii) ceil(longest / lanes_per_row) <= reduce_iters.  A slot
+// that cannot form a block alone is a long slot: it is cut at 4-aligned
+// offsets into segments of one load round each (at most nnz_per_block
+// entries from the aligned start).  Descriptors are {first slot, end slot,
+// first nonzero, end nonzero}; a segment of long slot number l has end slot
+// -1 - l, and long_seg_ptr[l] is the first of its partial-sum entries.  A tile is a run of at least blocks_per_tile blocks
+// of one unit, with an optional LDS x window.
 void build_schedule(spx_plan_s &P) {
     const Tune &T = P.tune;
-    const int64_t cap = kChunkSpan - 3;
-    const int32_t rmax = kChunkRows;
-    const int32_t wpg = T.wg / 64;  // tiles (waves) per workgroup
+    const int64_t span = T.nnz_per_block;
+    const int32_t iters = T.reduce_iters;
     P.blk_slot.clear();
     P.blk_desc.clear();
     P.tiles.clear();
+    P.long_seg_ptr.assign(1, 0);
     P.window_nnz = 0;
     P.window_bytes_fill = 0;
     std::vector<std::pair<int32_t, int32_t>> units;
@@ -388,96 +396,80 @@ void build_schedule(spx_plan_s &P) {
         units.emplace_back(covered, nslots);
         unit_leaf.push_back(-1);
     }
-    std::vector<int32_t> cols;
-    auto close_block = [&](int32_t s_lo, int32_t s_hi, int32_t z_lo, int32_t z_hi) {
-        P.blk_desc.insert(P.blk_desc.end(), {s_lo, s_hi, z_lo, z_hi});
+    // a slot too long for a block of its own
+    auto is_long = [&](int64_t len) {
+        return len > span - 3 || (len + 63) / 64 > iters;
     };
+    std::vector<int32_t> cols;
     for (size_t u = 0; u < units.size(); ++u) {
         int32_t s0 = units[u].first, s1 = units[u].second;
         if (s0 >= s1) continue;
         int32_t first_blk = (int32_t)(P.blk_desc.size() / 4);
-        // blocks
-        int32_t b_slo = s0, b_zlo = P.slot_ptr[s0], rows = 0;
+        int32_t b_slo = s0, nr = 0;
+        int64_t lmax = 0;
+        auto close = [&](int32_t s_hi) {
+            if (nr > 0)
+                P.blk_desc.insert(P.blk_desc.end(), {b_slo, s_hi, P.slot_ptr[b_slo], P.slot_ptr[s_hi]});
+            b_slo = s_hi;
+            nr = 0;
+            lmax = 0;
+        };
         for (int32_t s = s0; s < s1; ++s) {
-            int32_t ps = P.slot_ptr[s], pe = P.slot_ptr[s + 1];
-            // a row that does not fit but would fit a fresh block starts one,
-            // when the current block is at least half full
-            if ((int64_t)pe - b_zlo > cap && pe - ps <= cap && 2 * ((int64_t)ps - b_zlo) >= cap) {
-                close_block(b_slo, s, b_zlo, ps);
-                b_slo = s;
-                b_zlo = ps;
-                rows = 0;
-            }
-            ++rows;
-            while ((int64_t)pe - b_zlo > cap) {  // the row continues in a new block
-                int32_t cut = b_zlo + (int32_t)cap;
-                int32_t s_hi = ps < cut ? s + 1 : s;  // a row belongs where its first nonzero is
-                close_block(b_slo, s_hi, b_zlo, cut);
-                b_slo = s_hi;
-                b_zlo = cut;
-                rows = s_hi == s ? 1 : 0;
-            }
-            if (rows >= rmax) {
-                close_block(b_slo, s + 1, b_zlo, pe);
+            const int64_t ps = P.slot_ptr[s], pe = P.slot_ptr[s + 1], len = pe - ps;
+            if (is_long(len)) {
+                close(s);
+                // segments end on 4-aligned offsets: each is one load round
+                const int32_t lr = (int32_t)P.long_seg_ptr.size() - 1;
+                int32_t nseg = 0;
+                for (int64_t z = ps, e = (ps & ~(int64_t)3) + span; z < pe; z = e, e += span, ++nseg)
+                    P.blk_desc.insert(P.blk_desc.end(), {s, -1 - lr, (int32_t)z, (int32_t)std::min<int64_t>(e, pe)});
+                P.long_seg_ptr.push_back(P.long_seg_ptr.back() + nseg);
                 b_slo = s + 1;
-                b_zlo = pe;
-                rows = 0;
+                continue;
             }
+            const int64_t zb = P.slot_ptr[b_slo] & ~(int64_t)3;
+            const int64_t lm = std::max(lmax, len);
+            const int32_t g = lanes_per_row(T.wg, nr + 1);
+            if (nr > 0 && (pe - zb > span || nr + 1 > T.wg || (lm + g - 1) / g > iters)) close(s);
+            ++nr;
+            lmax = std::max(lmax, len);
         }
-        if (b_slo < s1 || b_zlo < P.slot_ptr[s1]) close_block(b_slo, s1, b_zlo, P.slot_ptr[s1]);
+        close(s1);
         int32_t last_blk = (int32_t)(P.blk_desc.size() / 4);
         // window of this unit
         int32_t wlo = 0, wlen = 0;
         int32_t B = std::max(1, T.blocks_per_tile);
         int32_t l = unit_leaf[u];
-        if (T.window_entries > 0 && l >= 0) {
+        if (T.window_entries > 0 && l >= 0 && last_blk > first_blk) {
             int64_t z0 = P.slot_ptr[s0], z1 = P.slot_ptr[s1];
             cols.assign(P.colidx.begin() + z0, P.colidx.begin() + z1);
             std::sort(cols.begin(), cols.end());
             int64_t best = 0;
-            size_t bi = 0, bj = 0;
-            size_t j = 0;
+            size_t bi = 0, bj = 0, j = 0;
             for (size_t i = 0; i < cols.size(); ++i) {
                 while (j < cols.size() && cols[j] < (int64_t)cols[i] + T.window_entries) ++j;
-                if ((int64_t)(j - i) > best) { best = (int64_t)(j - i); bi = i; bj = j; }
+                if ((int64_t)(j - i) > best) {
+                    best = (int64_t)(j - i);
+                    bi = i;
+                    bj = j;
+                }
             }
             int32_t est_tiles = std::max(1, (last_blk - first_blk + B - 1) / B);
             if (best > 0) {
                 int32_t lo = cols[bi], hi = cols[bj - 1] + 1;
-                int64_t fill = (int64_t)est_tiles * (hi - lo);
-                if (2 * best >= fill) {
+                // the window pays when the gathers it serves outnumber the
+                // entries loaded to fill it
+                if (2 * best >= (int64_t)est_tiles * (hi - lo)) {
                     wlo = lo;
                     wlen = hi - lo;
                     P.window_nnz += best;
                 }
             }
         }
-        // the tiles of a workgroup share its LDS window (the window only
-        // decides where x is read from, so any grouping is correct): a unit
-        // with a window starts and ends on a workgroup boundary
-        if (wlen > 0)
-            while ((P.tiles.size() / 4) % wpg) P.tiles.insert(P.tiles.end(), {first_blk, first_blk, 0, 0});
-        size_t tiles_before = P.tiles.size() / 4;
-        // tiles: at least B blocks, ending where a row ends
-        int32_t t0 = first_blk;
-        for (int32_t b = first_blk; b < last_blk; ++b) {
-            const int32_t *d = &P.blk_desc[4 * (size_t)b];
-            bool row_ends = P.slot_ptr[d[1]] <= d[3];
-            if ((b + 1 - t0 >= B && row_ends) || b + 1 == last_blk) {
-                P.tiles.insert(P.tiles.end(), {t0, b + 1, wlo, wlen});
-                t0 = b + 1;
-            }
+        for (int32_t b = first_blk; b < last_blk; b += B) {
+            P.tiles.insert(P.tiles.end(), {b, std::min(b + B, last_blk), wlo, wlen});
+            if (wlen > 0) P.window_bytes_fill += (int64_t)wlen * 8;
         }
-        // the tiles of a workgroup share its LDS window: with windows, a
-        // unit's tiles fill whole workgroups (empty tiles pad the last one)
-        if (wlen > 0) {
-            while ((P.tiles.size() / 4) % wpg) P.tiles.insert(P.tiles.end(), {last_blk, last_blk, wlo, wlen});
-            P.window_bytes_fill += (int64_t)wlen * 8 * (int64_t)((P.tiles.size() / 4 - tiles_before) / wpg);
-        }
-    }
-    while ((P.tiles.size() / 4) % wpg) {
-        int32_t nb_ = (int32_t)(P.blk_desc.size() / 4);
-        P.tiles.insert(P.tiles.end(), {nb_, nb_, 0, 0});
     }
     int32_t nb = (int32_t)(P.blk_desc.size() / 4);
     P.blk_slot.resize((size_t)nb + 1);

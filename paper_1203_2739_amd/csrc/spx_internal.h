@@ -78,10 +78,11 @@ DevPtr dev_alloc(size_t bytes);
 DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream);
 
 struct Tune {
-    int32_t wg = 256, nnz_per_block = kChunkSpan, blocks_per_tile = 8, window_entries = -1;
-    int32_t xcd_remap = 1, long_row = 1024;
+    int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
+    int32_t xcd_remap = 1, reduce_iters = kReduceIters;
 };
 Tune resolve_tune(const spx_tune *t, int form);
+inline bool tiled(const Tune &t) { return t.window_entries > 0 || t.blocks_per_tile > 1; }
 
 }  // namespace spx
 
@@ -112,10 +113,11 @@ struct spx_plan_s {
     std::vector<int32_t> blk_slot;              // [nblocks+1]
     std::vector<int32_t> blk_desc;              // 4 per block: slot range, nonzero range
     std::vector<int32_t> tiles;                 // 4 per tile
+    std::vector<int32_t> long_seg_ptr;          // [nlong+1] first partial-sum entry of each long slot
     int64_t window_nnz = 0, window_bytes_fill = 0;
     // device copies
     spx::DevPtr d_slot_ptr, d_slot_row, d_colidx, d_vals, d_row_perm, d_col_perm;
-    spx::DevPtr d_blk_desc, d_tiles;
+    spx::DevPtr d_blk_desc, d_tiles, d_long_seg_ptr, d_partials, d_counters;
     // statistics
     int64_t sum_lambda_col = 0, sum_lambda_row = 0, border_row_nnz = 0, cut = 0;
     double partition_seconds = 0.0, plan_seconds = 0.0;

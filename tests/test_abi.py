@@ -65,7 +65,13 @@ def test_bad_arguments():
     with pytest.raises(spx.SpxError):
         spx.plan_plain(M, tune=dict(wg_size=100))
     with pytest.raises(spx.SpxError):
-        spx.plan_plain(M, tune=dict(wg_size=256, nnz_per_block=1024))
+        spx.plan_plain(M, tune=dict(wg_size=256, nnz_per_block=512))
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M, tune=dict(wg_size=512, nnz_per_block=4096))
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M, tune=dict(reduce_iters=65))
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M, tune=dict(window_entries=40000))
     with pytest.raises(spx.SpxError):
         spx.set_num_threads(0)
 
@@ -115,37 +121,74 @@ def check_split(orc, A, P, rp, cp, part, K):
     assert inf["sum_lambda_row"] == lr.sum() and inf["sum_lambda_col"] == lc.sum()
 
 
+def lanes_per_row(wg, nr):
+    g = 1
+    while g * 2 <= wg // nr and g < 64:
+        g *= 2
+    return g
+
+
 def check_schedule(P):
-    """Blocks cover every unit's nonzeros contiguously with at most
-    nnz_per_block - 3 nonzeros and 2 wg row starts each; every slot starts in
-    exactly one block; tiles cover the blocks and end where a row ends."""
+    """Blocks cover the slots in order.  A multi-row block holds whole slots
+    spanning at most nnz_per_block entries from its 4-aligned start, at most
+    wg slots, and its longest slot needs at most reduce_iters strided steps of
+    the lanes the kernel gives each row; a slot that cannot form a block
+    (long slots) is cut into one-load-round segments, in order; tiles cover
+    the blocks in order."""
     inf = P.info()
     bd, tiles = P.export_sched()
-    nslots, NT, wg = inf["nslots"], inf["nnz_per_block"], 64  # a chunk is one wave's
+    nslots, NT, wg, it = inf["nslots"], inf["nnz_per_block"], inf["wg_size"], inf["reduce_iters"]
+    assert NT in (4 * wg, 8 * wg)
     if inf["form"] == 3:
-        sp = P.export_split()["slot_ptr"].astype(np.int64)
+        ex = P.export_split()
+        sp = ex["slot_ptr"].astype(np.int64)
     else:
         sp = P.export_csr()[0].astype(np.int64)
     if bd.shape[0] == 0:
         assert nslots == 0 or sp[-1] == 0
         return
-    s_lo, s_hi, z_lo, z_hi = (bd[:, i].astype(np.int64) for i in range(4))
-    assert np.all(z_hi - z_lo <= NT - 3) and np.all(z_hi >= z_lo)
-    assert np.all(s_hi - s_lo <= 4 * wg) and np.all(s_hi >= s_lo)
-    assert s_lo[0] == 0 and s_hi[-1] == nslots and np.all(s_lo[1:] == s_hi[:-1])
-    assert z_lo[0] == 0 and z_hi[-1] == sp[-1] and np.all(z_lo[1:] == z_hi[:-1])
-    # a slot starting in a block starts inside its nonzero range
-    for b in range(bd.shape[0]):
-        st = sp[s_lo[b]:s_hi[b]]
-        assert np.all((st >= z_lo[b]) & (st <= z_hi[b]))
-    assert tiles.shape[0] % (inf["wg_size"] // 64) == 0
-    tiles = tiles[tiles[:, 1] > tiles[:, 0]]  # drop the padding of workgroups
+    s = 0  # next slot to cover
+    nlong = 0
+    b = 0
+    nb = bd.shape[0]
+    while b < nb:
+        s_lo, s_hi, z_lo, z_hi = (int(v) for v in bd[b])
+        assert s_lo == s, (b, s_lo, s)
+        if s_hi < 0:
+            # segments of long slot number nlong: one load round each, in order
+            assert s_hi == -1 - nlong and z_lo == sp[s_lo]
+            while b < nb and bd[b, 1] == s_hi:
+                assert bd[b, 0] == s_lo and bd[b, 2] == z_lo and bd[b, 3] > bd[b, 2]
+                assert bd[b, 3] - (bd[b, 2] & ~3) <= NT
+                assert bd[b, 3] == sp[s_lo + 1] or bd[b, 3] % 4 == 0
+                z_lo = int(bd[b, 3])
+                b += 1
+            assert z_lo == sp[s_lo + 1]
+            ln = sp[s_lo + 1] - sp[s_lo]
+            assert ln > NT - 3 or (ln + 63) // 64 > it
+            nlong += 1
+            s = s_lo + 1
+            continue
+        assert s_hi > s_lo and z_lo == sp[s_lo] and z_hi == sp[s_hi]
+        assert z_hi - (z_lo & ~3) <= NT and s_hi - s_lo <= wg
+        lens = np.diff(sp[s_lo:s_hi + 1])
+        g = lanes_per_row(wg, s_hi - s_lo)
+        assert (int(lens.max()) + g - 1) // g <= it
+        s = s_hi
+        b += 1
+    assert s == nslots
+    assert inf["nlong_rows"] == nlong
     assert tiles[0, 0] == 0 and tiles[-1, 1] == inf["nblocks"]
-    assert np.all(tiles[1:, 0] == tiles[:-1, 1])
-    ends = tiles[:, 1] - 1
-    assert np.all(sp[s_hi[ends]] <= z_hi[ends])
+    assert np.all(tiles[1:, 0] == tiles[:-1, 1]) and np.all(tiles[:, 1] > tiles[:, 0])
+    assert np.all(tiles[:, 1] - tiles[:, 0] <= max(1, inf["blocks_per_tile"]))
     assert np.all(tiles[:, 3] >= 0) and np.all(tiles[:, 2] + tiles[:, 3] <= inf["n"])
     assert np.all(tiles[:, 3] <= max(inf["window_entries"], 0))
+    if inf["form"] == 3 and inf["nleaves"] > 0:
+        # a block never crosses a leaf
+        lsp = ex["leaf_slot_ptr"]
+        leaf_of = np.searchsorted(lsp, bd[:, 0], side="right") - 1
+        last = np.where(bd[:, 1] < 0, bd[:, 0], bd[:, 1] - 1)
+        assert np.all(leaf_of == np.searchsorted(lsp, last, side="right") - 1)
 
 
 @pytest.mark.parametrize("K", [1, 2, 8])
@@ -276,3 +319,34 @@ def test_empty_and_degenerate(orc):
         assert P.info()["nnz"] == 0
     P = spx.plan_plain(E)
     check_schedule(P)
+
+
+def long_row_csr(lens, n, seed=0):
+    """Rows of the given lengths with sorted distinct random columns."""
+    rng = np.random.default_rng(seed)
+    rp = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    cols = np.concatenate([np.sort(rng.choice(n, k, replace=False)) for k in lens]).astype(np.int32)
+    return CSR(len(lens), n, rp, cols, rng.uniform(-1, 1, int(rp[-1])))
+
+
+@pytest.mark.parametrize("tune", [None, dict(wg_size=64), dict(wg_size=128, nnz_per_block=1024),
+                                  dict(wg_size=256), dict(wg_size=512), dict(reduce_iters=1),
+                                  dict(reduce_iters=64), dict(blocks_per_tile=5),
+                                  dict(window_entries=4096, blocks_per_tile=8)])
+def test_schedule_rules(tune):
+    """Schedules of matrices mixing empty, short, long and multi-segment rows
+    obey the block rules for every tune."""
+    lens = [0, 3, 1, 1021, 1022, 0, 5, 2045, 70000, 7, 140000, 2, 300, 299, 64, 65] + [0, 1, 2, 3] * 50
+    A = long_row_csr(lens, 150000)
+    M = spx.from_csr(A, device=False)
+    P = spx.plan_plain(M, tune=tune)
+    check_schedule(P)
+    assert P.info()["nlong_rows"] >= 2
+    P = spx.split(M, 4, 0, 1, tune=tune)[0]
+    check_schedule(P)
+    A = gen_uniform_zipf(33, 5000, 60000, 400)
+    M = spx.from_csr(A, device=False)
+    for P in (spx.plan_plain(M, tune=tune), spx.reorder_db(M, 8, 2048 * 8, 2, tune=tune)[0],
+              spx.split(M, 8, 2048 * 8, 2, tune=tune)[0]):
+        check_schedule(P)

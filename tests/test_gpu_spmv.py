@@ -44,11 +44,12 @@ def run_reordered(A, x, form, K, window_bytes=0, tune=None, seed=0):
 
 
 TUNES = [None,
-         dict(wg_size=64, blocks_per_tile=1),
-         dict(wg_size=128, blocks_per_tile=3),
-         dict(wg_size=256, blocks_per_tile=32),
-         dict(wg_size=256, blocks_per_tile=2, xcd_remap=-1),
-         dict(wg_size=64, blocks_per_tile=200)]
+         dict(wg_size=64),
+         dict(wg_size=512, blocks_per_tile=3),
+         dict(reduce_iters=1, wg_size=256),
+         dict(blocks_per_tile=2, xcd_remap=-1),
+         dict(wg_size=128, nnz_per_block=1024, reduce_iters=7, blocks_per_tile=200),
+         dict(wg_size=128, nnz_per_block=1024, xcd_remap=-1)]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -83,19 +84,28 @@ def test_reordered_c1_integer_exact(orc, form):
     assert np.array_equal(y, orc.spmv(A, x)[rp])
 
 
+WINDOW_TUNES = [dict(window_entries=4096, blocks_per_tile=64, wg_size=128),
+                dict(window_entries=4096, blocks_per_tile=64, wg_size=256),
+                dict(window_entries=8192, blocks_per_tile=32),
+                dict(window_entries=16384, blocks_per_tile=16),
+                dict(window_entries=16384, wg_size=512, blocks_per_tile=32)]
+
+
 @pytest.mark.parametrize("form", ["sb", "db", "split"])
-@pytest.mark.parametrize("wb", [4096 * 8, 8192 * 8, 12288 * 8])
-def test_windows_c1(orc, form, wb):
-    """LDS windows (leaves refined to the window budget, tiles of several
+@pytest.mark.parametrize("wi", range(len(WINDOW_TUNES)))
+def test_windows_c1(orc, form, wi):
+    """LDS x windows (leaves refined to the window budget, tiles of several
     blocks) give the same products."""
     A = gen_c1()
     x = gen_vectors(103, A.n)[0]
-    y, rp, cp, part, P = run_reordered(A, x, form, 4, window_bytes=wb)
+    t = WINDOW_TUNES[wi]
+    wb = t["window_entries"] * 8
+    y, rp, cp, part, P = run_reordered(A, x, form, 4, window_bytes=wb, tune=t)
     inf = P.info()
-    assert inf["window_entries"] > 0
+    assert inf["window_entries"] > 0 and inf["window_nnz"] > 0
     assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], f"{form} window")
     Ai, xi = integer_problem(A, 4)
-    yi, rp, _, _, _ = run_reordered(Ai, xi, form, 4, window_bytes=wb)
+    yi, rp, _, _, _ = run_reordered(Ai, xi, form, 4, window_bytes=wb, tune=t)
     assert np.array_equal(yi, orc.spmv(Ai, xi)[rp])
 
 
@@ -201,8 +211,45 @@ def test_larger_irregular(orc):
     assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), "zipf 200k")
     y, rp, cp, part, P = run_reordered(A, x, "split", 16)
     assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], "zipf 200k split")
-    y, rp, cp, part, P = run_reordered(A, x, "db", 16, window_bytes=8192 * 8)
+    y, rp, cp, part, P = run_reordered(A, x, "db", 16, window_bytes=8192 * 8,
+                                       tune=dict(window_entries=8192, blocks_per_tile=16))
     assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], "zipf 200k db window")
+
+
+def test_rows_cut_into_segments(orc):
+    """Rows longer than one block are summed by several workgroups whose
+    partial sums the last one adds up, in plain, split and accumulating split
+    products, twice in a row (the arrival counters reset themselves)."""
+    lens = [3, 70000, 0, 1, 140000, 65536, 65537, 2, 1021, 5]
+    n = 150000
+    rng = np.random.default_rng(5)
+    cols = np.concatenate([np.sort(rng.choice(n, d, replace=False)) for d in lens])
+    rp = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    A = CSR(len(lens), n, rp, cols.astype(np.int32), rng.uniform(-1, 1, cols.size))
+    x = gen_vectors(110, n)[0]
+    ref, den = orc.spmv(A, x), orc.abs_rowsum(A, x)
+    for t in (None, dict(wg_size=64), dict(wg_size=512), dict(blocks_per_tile=3)):
+        M = spx.from_csr(A)
+        P = spx.plan_plain(M, tune=t)
+        assert P.info()["nlong_rows"] >= 4
+        xd = dev(x)
+        for rep in range(2):
+            yd = torch.full((A.m,), 7.0, dtype=torch.float64, device="cuda")
+            spx.spmv(P, xd, yd)
+            assert_close_rowwise(host(yd), ref, den, f"segments plain {t} {rep}")
+        y, rp, cp, part, P = run_reordered(A, x, "split", 2, tune=t)
+        assert_close_rowwise(y, ref[rp], den[rp], f"segments split {t}")
+        xh = torch.empty_like(xd)
+        spx.permute_x(P, xd, xh)
+        yh = dev(np.full(A.m, 0.5))
+        spx.spmv_split(P, xh, yh, accumulate=1)
+        assert_close_rowwise(host(yh) - 0.5, ref[rp], den[rp] + 1.0, f"segments split acc {t}")
+        yh.fill_(np.nan)
+        spx.split_prepare_y(P, yh)
+        spx.spmv_split(P, xh, yh, accumulate=2)
+        # rows owned by one leaf are stored, so no NaN survives
+        assert_close_rowwise(host(yh), ref[rp], den[rp], f"segments split prezeroed {t}")
 
 
 def test_stream_probe():
