@@ -111,6 +111,25 @@ def cpu_baseline(A, xs_host, budget_s=15.0, max_products=100):
             "gflops": round(2 * A.nnz / dt / 1e9, 3)}
 
 
+def measured_traffic(form, nnz):
+    """HBM bytes per launch of the SpMV kernel of this form from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
+    known size), or None when the summary is missing, is for another matrix,
+    or the kernel source changed after the counters were taken."""
+    from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256
+    path = os.path.join(ROOT, "profiles", f"spmv_blocks_c2_{form}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and parts[0].endswith(":"):
+            kv[parts[0][:-1]] = parts[1]
+    if kv.get("kernel_source_sha256") != kernel_source_sha256() or int(kv.get("nnz", -1)) != nnz:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def load_c2(n):
     from synth import gen_c2
     cache = os.environ.get("SPX_C2_CACHE")
@@ -133,17 +152,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--forms", default="plain,db,split")
     ap.add_argument("--K", type=int, default=64)
-    ap.add_argument("--window-bytes", type=int, default=0)
+    ap.add_argument("--window-bytes", type=int, default=131072,
+                    help="leaf window budget of the split (x plus y entries, bytes)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tune", default="", help="wg,nnz_per_block[,blocks_per_tile,window_entries]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--only-stream", action="store_true",
+                    help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: a run over several GPUs is not supported "
+              "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -152,6 +174,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only_stream:
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        sink = torch.empty(spx.stream_sink_len(nbytes), dtype=torch.float64, device="cuda")
+        for _ in range(5):
+            spx.stream_read(src, nbytes, sink)
+            spx.stream_copy(src, dst, nbytes)
+        torch.cuda.synchronize()
+        print(json.dumps({"stream_read_GBs": round(stream_ceiling(spx, torch), 1), "bytes": nbytes}))
+        return
     spx.set_num_threads(min(16, os.cpu_count() or 1))
 
     t = time.time()
@@ -180,7 +213,8 @@ def main():
             xf = xs
         else:
             fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
-            P, rp, cp, _ = fn(M, args.K, args.window_bytes, args.seed, tune=tune)
+            wb = args.window_bytes if form == "split" else 0
+            P, rp, cp, _ = fn(M, args.K, wb, args.seed, tune=tune)
             xf = torch.empty_like(xs)
             for i in range(npool):
                 spx.permute_x(P, xs[i], xf[i])
@@ -231,8 +265,8 @@ def main():
         out["speedup_vs_plain"] = round(results["plain"]["ms_per_step"] / hb["ms_per_step"], 3)
     out["roofline"] = {"bound": "hbm", "achieved": hb["kernel_GBs"], "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": round(hb["kernel_GBs"] / PEAK_HBM_GBS, 4),
-                       "traffic": None,
-                       "kernel": f"spmv_tiles ({best})",
+                       "traffic": measured_traffic(best, A.nnz),
+                       "kernel": f"spmv_blocks ({best})",
                        "alg_bytes_per_launch": nb}
     if not args.no_stream:
         out["stream_read_GBs"] = round(stream_ceiling(spx, torch), 1)
