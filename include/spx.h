@@ -199,14 +199,17 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info);
  *   spx_spmv_split with accumulate = 0.  x has n entries, y has m.
  * spx_spmv_split: y <- y + A^k x for k = 1..K (Section 4) in the split's
  *   reordered space.  accumulate = 0: y starts at zero (the call zeroes the
- *   rows shared by several leaves itself and stores the others);
- *   accumulate = 1: the products are added to the incoming y;
- *   accumulate = 2: as 0, but the caller has already zeroed the shared rows
- *   [row_border_begin, m) (spx_split_prepare_y), so only the product kernel
- *   runs.  Partial results of shared rows are added with binary64 atomics,
- *   so the rounding of those rows varies from run to run within the error
- *   bound of reordered summation.
- * spx_split_prepare_y: y[i] = 0 for the shared rows i >= row_border_begin.
+ *   rows shared by several leaves and the rows without nonzeros, then stores
+ *   the rows owned by one leaf and adds the per-leaf sums of shared rows
+ *   with binary64 atomics); accumulate = 1: the products are added to the
+ *   incoming y; accumulate = 2: as 0, but the caller has already zeroed the
+ *   rows [row_border_begin, m) (spx_split_prepare_y), so only the product
+ *   kernel runs.  The atomic adds make the rounding of shared rows vary from
+ *   run to run within the error bound of reordered summation.
+ * spx_split_prepare_y: y[i] = 0 for the rows i >= row_border_begin.
+ * Products of one plan use the plan's scratch memory (partial sums and
+ * arrival counters of rows too long for one block): products of the same
+ * plan must not overlap in time; order them on one stream.
  * spx_permute_x: x_hat[j'] = x[col_perm[j']] (Section 3).
  * spx_unpermute_y: y[row_perm[i']] = y_hat[i'].
  *   Both return SPX_EUNSUPPORTED for the plain form.

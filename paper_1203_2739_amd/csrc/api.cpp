@@ -166,18 +166,22 @@ void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream) {
         if (!P.col_perm.empty())
             P.d_col_perm = dev_upload(P.col_perm.data(), P.col_perm.size() * 4, 0, stream);
     }
+    upload_schedule(P, stream);
+    P.on_device = true;
+}
+
+// Device copies of the schedule and of the long-slot scratch (partial sums
+// and arrival counters, which start at zero).
+void upload_schedule(spx_plan_s &P, void *stream) {
     P.d_blk_desc = dev_upload(P.blk_desc.data(), P.blk_desc.size() * 4, 16, stream);
     P.d_tiles = dev_upload(P.tiles.data(), P.tiles.size() * 4, 16, stream);
     P.d_long_seg_ptr = dev_upload(P.long_seg_ptr.data(), P.long_seg_ptr.size() * 4, 16, stream);
-    {
-        size_t nlong = P.long_seg_ptr.empty() ? 0 : P.long_seg_ptr.size() - 1;
-        size_t nseg = nlong ? (size_t)P.long_seg_ptr.back() : 0;
-        P.d_partials = dev_alloc(nseg * 8 + 16);
-        P.d_counters = dev_alloc(nlong * 4 + 16);
-        hip_check(hipMemsetAsync(P.d_counters->ptr, 0, nlong * 4 + 16, (hipStream_t)stream), "counter init");
-    }
+    size_t nlong = P.long_seg_ptr.empty() ? 0 : P.long_seg_ptr.size() - 1;
+    size_t nseg = nlong ? (size_t)P.long_seg_ptr.back() : 0;
+    P.d_partials = dev_alloc(nseg * 8 + 16);
+    P.d_counters = dev_alloc(nlong * 4 + 16);
+    hip_check(hipMemsetAsync(P.d_counters->ptr, 0, nlong * 4 + 16, (hipStream_t)stream), "counter init");
     hip_check(hipStreamSynchronize((hipStream_t)stream), "plan upload");
-    P.on_device = true;
 }
 }  // namespace spx
 
@@ -242,7 +246,7 @@ static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t
     if (split) {
         a.shared_begin = P.row_border_begin;
         a.accumulate = accumulate == 1 ? 1 : 0;
-        if (accumulate == 0) {
+        if (accumulate == 0) {  // shared rows and rows without nonzeros
             hipError_t e = launch_fill(y, P.row_border_begin, P.m, 0.0, s);
             if (e != hipSuccess) return e;
         }
@@ -330,9 +334,8 @@ spx_status spx_plan_retune(spx_plan P, const spx_tune *tune) {
         P->tune = r;
         build_schedule(*P);
         if (P->on_device) {
-            P->d_blk_desc = dev_upload(P->blk_desc.data(), P->blk_desc.size() * 4, 16, nullptr);
-            P->d_tiles = dev_upload(P->tiles.data(), P->tiles.size() * 4, 16, nullptr);
-            hip_check(hipStreamSynchronize(nullptr), "retune upload");
+            hip_check(hipDeviceSynchronize(), "retune");  // no product of the old schedule in flight
+            upload_schedule(*P, nullptr);
         }
     });
 }

@@ -20,8 +20,10 @@
 //    XCD and share its x entries in that XCD's L2, the GPU counterpart of a
 //    part that fits into the cache (Section 3, Theorem 1).
 //  * Split products (y <- y + A^k x, Section 4) store rows owned by a single
-//    leaf directly and add rows shared by several leaves with binary64
-//    atomics after the shared range was zeroed.
+//    leaf directly and add the per-leaf sums of rows shared by several leaves
+//    with binary64 atomics onto the zeroed shared range (measured faster than
+//    writing per-leaf sums and folding them in a second kernel, whose reads
+//    of the sums are scattered).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -74,17 +76,16 @@ __device__ __forceinline__ int remap_tile(int bid, int ntiles, int on) {
     return x * per + (x < rem ? x : rem) + i;
 }
 
-// Writes the sum of one slot: an atomic add for rows shared by several
-// leaves of a split, an add for a split product that accumulates, a plain
-// store otherwise.
+// Writes the sum of one slot: an atomic add for a row shared by several
+// leaves of a split (onto the zeroed entry), an add for a split product that
+// accumulates, a plain store otherwise.
 template <bool SPLIT>
-__device__ __forceinline__ void store_row(double *__restrict__ y, const int32_t *__restrict__ slot_row,
-                                          int32_t slot, double v, int32_t shared_begin,
-                                          int32_t accumulate) {
-    const int32_t row = SPLIT ? slot_row[slot] : slot;
-    if (SPLIT && row >= shared_begin) {
+__device__ __forceinline__ void store_row(const SpmvArgs &a, int32_t slot, double v) {
+    double *__restrict__ y = a.y;
+    const int32_t row = SPLIT ? a.slot_row[slot] : slot;
+    if (SPLIT && row >= a.shared_begin) {
         unsafeAtomicAdd(&y[row], v);
-    } else if (SPLIT && accumulate) {
+    } else if (SPLIT && a.accumulate) {
         y[row] += v;
     } else {
         y[row] = v;
@@ -150,7 +151,7 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgs &a, const v4i d, 
         for (int k = sptr[grp] + lane; k < k1; k += g) sum += sprod[k];
     }
     sum = group_sum_unrolled(sum, g);
-    if (grp < nr && lane == 0) store_row<SPLIT>(a.y, a.slot_row, d.x + grp, sum, a.shared_begin, a.accumulate);
+    if (grp < nr && lane == 0) store_row<SPLIT>(a, d.x + grp, sum);
 }
 
 // One segment [d.z, d.w) of long slot d.x: one load round like a multi-row
@@ -197,7 +198,7 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgs &a, const v4i d,
         const int32_t base = a.long_seg_ptr[lr];
         const int32_t nseg = a.long_seg_ptr[lr + 1] - base;
         if (nseg == 1) {
-            store_row<SPLIT>(a.y, a.slot_row, d.x, part, a.shared_begin, a.accumulate);
+            store_row<SPLIT>(a, d.x, part);
         } else {
             const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / (NPT * WG);
             // The partial goes to the device-coherent level (an agent-scope
@@ -214,7 +215,7 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgs &a, const v4i d,
                 for (int32_t k = 0; k < nseg; ++k)
                     sum += __hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&a.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                store_row<SPLIT>(a.y, a.slot_row, d.x, sum, a.shared_begin, a.accumulate);
+                store_row<SPLIT>(a, d.x, sum);
             }
         }
     }

@@ -127,6 +127,7 @@ namespace spx {
 // plan.cpp
 void build_schedule(spx_plan_s &P);
 void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream);
+void upload_schedule(spx_plan_s &P, void *stream);
 void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &r, bool db);
 void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r);
 void plan_plain(spx_plan_s &P, const CsrHost &A);

@@ -261,3 +261,26 @@ def test_stream_probe():
     dst = torch.zeros_like(src)
     spx.stream_copy(src, dst, nbytes)
     assert torch.equal(dst, src)
+
+
+def test_split_deterministic_and_retune(orc):
+    """Split products stay within tolerance after retunes that change which
+    slots are long (the long-slot scratch is rebuilt), over repeated calls
+    (the arrival counters reset themselves)."""
+    A = gen_uniform_zipf(41, 30_000, 600_000, 3000, diagonal=True)
+    x = gen_vectors(111, A.n)[0]
+    M = spx.from_csr(A)
+    P, rp, cp, part = spx.split(M, 8, 0, 4)
+    xd = dev(x)
+    xh = torch.empty_like(xd)
+    spx.permute_x(P, xd, xh)
+    ref, den = orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp]
+    for t in (None, dict(wg_size=512), dict(wg_size=64), dict(reduce_iters=2, wg_size=256)):
+        spx.plan_retune(P, t)
+        outs = []
+        for rep in range(3):
+            yh = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
+            spx.spmv_split(P, xh, yh)
+            outs.append(host(yh))
+        for o in outs:
+            assert_close_rowwise(o, ref, den, f"split retune {t}")
