@@ -145,6 +145,87 @@ def load_c2(n):
     return A
 
 
+def time_calls(torch, fn, warmup, steps):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def main_precision(args, torch, spx):
+    """Precision mode on the SPD matrix A = offdiag(B + B^T) + diag(row sums + 1)
+    built from the block generator at n = 5*10^5: product rates per stored
+    precision, product errors against the binary64 oracle, and the refined CG
+    solve of A x = A 1 to relative residual 1e-10."""
+    import oracle as orc
+    from synth import gen_c3_spd, gen_vectors
+    torch.cuda.set_device(0)
+    t = time.time()
+    A = gen_c3_spd(seed=3, n=500_000)
+    log(f"SPD matrix n={A.n} nnz={A.nnz} ({time.time() - t:.1f} s)")
+    M = spx.from_csr(A)
+    P = spx.plan_plain(M)
+    spx.plan_add_lowp(P, "f32")
+    spx.plan_add_lowp(P, "bf16")
+    x64 = gen_vectors(3000, A.n, 1)[0]
+    xd = torch.from_numpy(x64).cuda()
+    x32 = xd.float()
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    y32 = torch.empty(A.m, dtype=torch.float32, device="cuda")
+    ref = orc.spmv(A, x64)
+    den = orc.abs_rowsum(A, x64)
+    out = {"products": {}, "solves": {}}
+    vb = {"f64": 8, "f32": 4, "bf16": 2}
+    for prec in ("f64", "f32", "bf16"):
+        if prec == "f64":
+            ms = time_calls(torch, lambda: spx.spmv(P, xd, y), args.warmup, args.steps)
+            got = y.cpu().numpy()
+            xb = 8
+        else:
+            ms = time_calls(torch, lambda: spx.spmv_lowp(P, prec, x32, y32), args.warmup, args.steps)
+            got = y32.double().cpu().numpy()
+            xb = 4
+        nb = A.nnz * (4 + vb[prec]) + 4 * (A.m + 1) + xb * (A.n + A.m)
+        err = np.abs(got - ref) / np.maximum(den, 1e-300)
+        out["products"][prec] = {"ms": round(ms, 5), "GBs": round(nb / (ms * 1e-3) / 1e9, 1),
+                                 "bytes": nb, "max_rel_err_vs_f64_oracle": float(err.max()),
+                                 "median_rel_err_vs_f64_oracle": float(np.median(err))}
+        log(prec, json.dumps(out["products"][prec]))
+    b = orc.spmv(A, np.ones(A.n))
+    bd = torch.from_numpy(b).cuda()
+    for prec, itol in (("f64", 1e-10), ("f32", 1e-3), ("bf16", 1e-2)):
+        xs = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        st = spx.cg_ir(P, prec, bd, xs, tol=1e-10, inner_tol=itol, max_outer=60, max_inner=5000)
+        xh = xs.cpu().numpy()
+        res = np.linalg.norm(b - orc.spmv(A, xh)) / np.linalg.norm(b)
+        st.update({"inner_tol": itol, "oracle_rel_residual": float(res),
+                   "max_abs_err_vs_ones": float(np.max(np.abs(xh - 1.0)))})
+        out["solves"][prec] = st
+        log(prec, json.dumps(st))
+    f64 = out["products"]["f64"]["ms"]
+    line = {
+        "metric": "precision-mode SpMV GB/s and refined-CG time to 1e-10",
+        "value": out["products"]["f32"]["GBs"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["products"]["f32"]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"SPD n={A.n} from the block generator, nnz={A.nnz}; "
+                               "binary32 values, binary32 accumulation"},
+        "speedup_vs_f64_product": {p: round(f64 / out["products"][p]["ms"], 3) for p in ("f32", "bf16")},
+        "speedup_vs_f64_cg": {p: round(out["solves"]["f64"]["seconds"] / out["solves"][p]["seconds"], 3)
+                              for p in ("f32", "bf16")},
+        **out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +240,9 @@ def main():
     ap.add_argument("--tune", default="", help="wg,nnz_per_block[,blocks_per_tile,window_entries]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision"],
+                    help="spmv: repeated products on the n=10^6 matrix (default); precision: "
+                         "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
     ap.add_argument("--only-stream", action="store_true",
                     help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()
@@ -174,6 +258,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "precision":
+        return main_precision(args, torch, spx)
     if args.only_stream:
         nbytes = 1 << 30
         src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()

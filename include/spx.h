@@ -222,6 +222,53 @@ spx_status spx_permute_x(spx_plan P, const double *x, double *x_hat, void *strea
 spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *stream);
 
 /* ----------------------------------------------------------------------
+ * Precision mode.  Not part of the paper, whose products are binary64
+ * throughout: values are stored in binary32 or bfloat16, indices stay
+ * int32, x, y and the accumulation are binary32.  A conjugate-gradient solve
+ * on that product is wrapped in binary64 iterative refinement, in which only
+ * the residual r = b - A x (with the binary64 values) and the update
+ * x <- x + d are binary64.
+ *
+ * spx_plan_add_lowp: rounds the plan's stored values to binary32 (nearest,
+ *   ties to even) and, for SPX_PREC_BF16, the binary32 values further to
+ *   bfloat16 (nearest, ties to even, NaN kept quiet); keeps a host copy and,
+ *   for a device plan, a device copy.  Plain, SB and DB plans only
+ *   (SPX_EUNSUPPORTED for a split).
+ * spx_plan_export_lowp: the rounded values (float[nnz] or uint16_t[nnz]
+ *   bfloat16 bit patterns) in the plan's storage order.
+ * spx_spmv_lowp: y <- A_low x with binary32 device vectors x[n], y[m], in the
+ *   plan's (reordered) space; untiled schedules only.  Each row is summed in
+ *   binary32 in a tree order, so against the exact sum of the rounded
+ *   products a row of length m_i errs by at most about m_i 2^-24 times
+ *   sum_j |a_ij x_j|.
+ * spx_cg_ir: solves A x = b for a symmetric positive definite square plan
+ *   (b, x device binary64 vectors in the plan's space).  x <- 0, r <- b; while
+ *   ||r|| / ||b|| > tol and fewer than max_outer refinements: run CG in the
+ *   given precision on A_low d = r / ||r|| to relative residual inner_tol
+ *   (at most max_inner iterations), x <- x + ||r|| d, r <- b - A x.
+ *   SPX_PREC_F64 runs the inner CG in binary64 with the binary64 product.
+ *   Returns SPX_ENOTCONV (with stats filled and x the last iterate) if the
+ *   tolerance was not reached.  Allocates its workspace on every call.
+ */
+#define SPX_PREC_F64 0
+#define SPX_PREC_F32 1
+#define SPX_PREC_BF16 2
+
+typedef struct spx_cg_stats_s {
+    int32_t outer;        /* refinement steps                          */
+    int32_t inner;        /* CG iterations over all refinement steps    */
+    double rel_residual;  /* final ||b - A x|| / ||b||, binary64        */
+    double seconds;       /* wall time of the solve                     */
+} spx_cg_stats;
+
+spx_status spx_plan_add_lowp(spx_plan P, int32_t precision);
+spx_status spx_plan_export_lowp(spx_plan P, int32_t precision, void *vals);
+spx_status spx_spmv_lowp(spx_plan P, int32_t precision, const float *x, float *y, void *stream);
+spx_status spx_cg_ir(spx_plan P, int32_t precision, const double *b, double *x, double tol,
+                     double inner_tol, int32_t max_outer, int32_t max_inner, spx_cg_stats *stats,
+                     void *stream);
+
+/* ----------------------------------------------------------------------
  * Inspection (host arrays, caller-allocated; any pointer may be NULL).
  *
  * spx_plan_export_csr: the stored matrix of a plain/SB/DB plan in CSR:

@@ -83,7 +83,19 @@ _SIGS = {
     "spx_stream_sink_len": ([_I64], _I64),
     "spx_stream_read": ([_VP, _I64, _VP, _VP], _I32),
     "spx_stream_copy": ([_VP, _VP, _I64, _VP], _I32),
+    "spx_plan_add_lowp": ([_VP, _I32], _I32),
+    "spx_plan_export_lowp": ([_VP, _I32, _VP], _I32),
+    "spx_spmv_lowp": ([_VP, _I32, _VP, _VP, _VP], _I32),
+    "spx_cg_ir": ([_VP, _I32, _VP, _VP, ctypes.c_double, ctypes.c_double, _I32, _I32, _VP, _VP], _I32),
 }
+
+PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
+_PREC = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16}
+
+
+class CgStats(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 def declared_symbols():
@@ -289,6 +301,14 @@ class Plan:
         _check(lib().spx_plan_export_split(self._h, _hp(lsp), _hp(sr), _hp(sp), _hp(ci), _hp(v)))
         return dict(leaf_slot_ptr=lsp, slot_row=sr[:S], slot_ptr=sp, colidx=ci[:nnz], vals=v[:nnz])
 
+    def export_lowp(self, precision):
+        """Rounded values: float32 array (f32) or uint16 bfloat16 bit patterns (bf16)."""
+        prec = _PREC.get(precision, precision)
+        nnz = self.info()["nnz"]
+        out = np.empty(max(nnz, 1), np.float32 if prec == PREC_F32 else np.uint16)
+        _check(lib().spx_plan_export_lowp(self._h, int(prec), _hp(out)))
+        return out[:nnz]
+
     def export_parts(self):
         inf = self.info()
         size = inf["nnz"] if inf["form"] == FORM_SPLIT else inf["m"]
@@ -404,3 +424,34 @@ def stream_read(src, nbytes, sink, stream=None):
 
 def stream_copy(src, dst, nbytes, stream=None):
     _check(lib().spx_stream_copy(_dev(src), _dev(dst), int(nbytes), _stream(stream)))
+
+
+# ---------------------------------------------------------------- precision mode
+
+def plan_add_lowp(P: Plan, precision):
+    """Store the plan's values rounded to binary32 ("f32") or bfloat16 ("bf16")."""
+    _check(lib().spx_plan_add_lowp(P.handle, int(_PREC.get(precision, precision))))
+
+
+def spmv_lowp(P: Plan, precision, x, y, stream=None):
+    """y <- A_low x with binary32 device vectors (binary32 accumulation)."""
+    import torch
+    m, n, _ = P.mat_dims
+    _check(lib().spx_spmv_lowp(P.handle, int(_PREC.get(precision, precision)), _dev(x, torch.float32, n),
+                               _dev(y, torch.float32, m), _stream(stream)))
+
+
+def cg_ir(P: Plan, precision, b, x, tol=1e-10, inner_tol=1e-3, max_outer=50, max_inner=1000,
+          stream=None):
+    """Solve A x = b by CG in the given precision inside binary64 iterative
+    refinement.  Returns a dict of statistics with "converged"."""
+    import torch
+    m, n, _ = P.mat_dims
+    st = CgStats()
+    rc = lib().spx_cg_ir(P.handle, int(_PREC.get(precision, precision)), _dev(b, torch.float64, n),
+                         _dev(x, torch.float64, n), float(tol), float(inner_tol), int(max_outer),
+                         int(max_inner), ctypes.byref(st), _stream(stream))
+    if rc not in (0, -4):
+        _check(rc)
+    return {"outer": st.outer, "inner": st.inner, "rel_residual": st.rel_residual,
+            "seconds": st.seconds, "converged": rc == 0}

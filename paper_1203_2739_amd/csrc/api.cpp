@@ -7,8 +7,8 @@
 #include <new>
 #include <string>
 
+#include "api_internal.h"
 #include "kernels.h"
-#include "spx_internal.h"
 
 namespace spx {
 
@@ -18,7 +18,7 @@ void set_last_error(const std::string &msg) { g_err = msg; }
 
 [[noreturn]] void fail(spx_status code, const std::string &msg) { throw Error{code, msg}; }
 
-static void hip_check(hipError_t e, const char *what) {
+void hip_check(hipError_t e, const char *what) {
     if (e != hipSuccess) fail(SPX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
@@ -78,27 +78,6 @@ Tune resolve_tune(const spx_tune *t, int form) {
 }  // namespace spx
 
 using namespace spx;
-
-template <class F>
-static spx_status guarded(F f) {
-    try {
-        f();
-        return SPX_OK;
-    } catch (const Error &e) {
-        set_last_error(e.msg);
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        set_last_error("host allocation failed");
-        return SPX_ENOMEM;
-    } catch (const std::exception &e) {
-        set_last_error(e.what());
-        return SPX_EINVAL;
-    } catch (...) {
-        set_last_error("unknown error");
-        return SPX_EINVAL;
-    }
-}
-
 
 static constexpr size_t kPadEntries = 16;
 
@@ -224,8 +203,7 @@ static spx_status build_reordered(spx_mat A, int32_t K, int64_t window_bytes, ui
     });
 }
 
-static hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t accumulate,
-                              hipStream_t s) {
+hipError_t spx::run_product(spx_plan_s &P, const double *x, double *y, int32_t accumulate, hipStream_t s) {
     SpmvArgs a{};
     a.slot_ptr = (const int32_t *)P.d_slot_ptr->ptr;
     a.slot_row = P.d_slot_row ? (const int32_t *)P.d_slot_row->ptr : nullptr;

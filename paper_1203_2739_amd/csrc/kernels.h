@@ -9,32 +9,56 @@
 
 namespace spx {
 
-// Arguments of the tiled CSR kernel.  Slots are rows (plain/SB/DB) or the
-// (leaf, row) pairs of a split; slot_row maps a split slot to its row.
-struct SpmvArgs {
+// Arguments of the row-block kernel.  Slots are rows (plain/SB/DB) or the
+// (leaf, row) pairs of a split; slot_row maps a split slot to its row.  V is
+// the stored value type (double, float, or uint16_t bfloat16 bit patterns),
+// A the type of x, y and the accumulation.
+template <class V, class A>
+struct SpmvArgsT {
     const int32_t *slot_ptr;  // [nslots+1] nonzero offsets
     const int32_t *slot_row;  // [nslots]   split only
     const int32_t *colidx;    // padded to a multiple of 4 plus 16
-    const double *vals;       // padded likewise
-    const double *x;
-    double *y;
+    const V *vals;            // padded likewise
+    const A *x;
+    A *y;
     const int32_t *blk_desc;  // 4 per block: first slot, end slot, first nonzero, end nonzero
     const int32_t *tiles;     // 4 per tile: first block, end block, window lo, window len
     int32_t ntiles;           // workgroups: tiles, or blocks when not tiled
     int32_t shared_begin;     // split: rows >= this are accumulated atomically
     int32_t accumulate;       // split: add to y for rows owned by one leaf
     int32_t xcd_remap;
-    int32_t n;                // columns (no gathers when 0)
+    int32_t n;                // columns
     const int32_t *long_seg_ptr;  // [nlong+1] partial-sum entries of each long slot
     double *partials;             // one per long-slot segment
     uint32_t *counters;           // one per long slot, zero between products
 };
+using SpmvArgs = SpmvArgsT<double, double>;
 
 // One workgroup of wg threads per tile (tiled) or per block (not tiled);
 // ntiles counts workgroups.  npt = nonzeros staged per thread.
 bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out);
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
                        hipStream_t s);
+// Low-precision products (binary32 or bfloat16 values, binary32 x, y and
+// accumulation), untiled schedules only.
+bool spmv_lowp_variant_exists(int wg, int npt, int window_entries);
+hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s);
+hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s);
+// Precision-mode vector kernels (see spx_cg_ir).  Dot products write their
+// result to *out (device) using part[dot_groups(n)] as scratch.
+int dot_groups(int64_t n);
+template <class T>
+hipError_t launch_dot(const T *a, const T *b, int64_t n, T *part, T *out, hipStream_t s);
+template <class T>
+hipError_t launch_cg_start(const double *r, double inv_scale, T *rl, T *p, T *d, int64_t n, hipStream_t s);
+template <class T>
+hipError_t launch_cg_update(const T *rr, const T *pq, T *d, T *r, const T *p, const T *q, int64_t n, hipStream_t s);
+template <class T>
+hipError_t launch_cg_direction(const T *rr, const T *rr_new, T *p, const T *r, int64_t n, hipStream_t s);
+template <class T>
+hipError_t launch_ir_update(double *x, const T *d, double scale, int64_t n, hipStream_t s);
+hipError_t launch_residual(const double *b, const double *ax, double *r, int64_t n, hipStream_t s);
+hipError_t launch_to_f32(const double *x, float *out, int64_t n, hipStream_t s);
 hipError_t launch_fill(double *y, int64_t lo, int64_t hi, double v, hipStream_t s);
 hipError_t launch_gather(const double *x, const int32_t *perm, double *out, int64_t n, hipStream_t s);
 hipError_t launch_scatter(const double *yhat, const int32_t *perm, double *y, int64_t m, hipStream_t s);

@@ -26,6 +26,7 @@
 //    of the sums are scattered).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -34,39 +35,31 @@ namespace spx {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 namespace {
 
-__device__ __forceinline__ double xor_lanes(double v, int off) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
+// Value of the lane `off` positions away in an xor pattern (off a power of two
+// up to 32): DPP quad permutes for 1 and 2, ds_swizzle for 4 to 16, a
+// cross-half permute for 32.
+__device__ __forceinline__ int xor_lanes_i(int v, int off) {
     switch (off) {
-    case 1:
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
-        break;
-    case 2:
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
-        break;
-    case 4:
-        lo = __builtin_amdgcn_ds_swizzle(lo, 0x101F);
-        hi = __builtin_amdgcn_ds_swizzle(hi, 0x101F);
-        break;
-    case 8:
-        lo = __builtin_amdgcn_ds_swizzle(lo, 0x201F);
-        hi = __builtin_amdgcn_ds_swizzle(hi, 0x201F);
-        break;
-    case 16:
-        lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
-        hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
-        break;
-    default: {
-        int src = ((int)(threadIdx.x & 63) ^ 32) << 2;
-        lo = __builtin_amdgcn_ds_bpermute(src, lo);
-        hi = __builtin_amdgcn_ds_bpermute(src, hi);
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+    case 8: return __builtin_amdgcn_ds_swizzle(v, 0x201F);
+    case 16: return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+    default: return __builtin_amdgcn_ds_bpermute(((int)(threadIdx.x & 63) ^ 32) << 2, v);
     }
-    }
-    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double xor_lanes(double v, int off) {
+    return __hiloint2double(xor_lanes_i(__double2hiint(v), off), xor_lanes_i(__double2loint(v), off));
+}
+
+__device__ __forceinline__ float xor_lanes(float v, int off) {
+    return __int_as_float(xor_lanes_i(__float_as_int(v), off));
 }
 
 __device__ __forceinline__ int remap_tile(int bid, int ntiles, int on) {
@@ -79,9 +72,9 @@ __device__ __forceinline__ int remap_tile(int bid, int ntiles, int on) {
 // Writes the sum of one slot: an atomic add for a row shared by several
 // leaves of a split (onto the zeroed entry), an add for a split product that
 // accumulates, a plain store otherwise.
-template <bool SPLIT>
-__device__ __forceinline__ void store_row(const SpmvArgs &a, int32_t slot, double v) {
-    double *__restrict__ y = a.y;
+template <bool SPLIT, class V, class A>
+__device__ __forceinline__ void store_row(const SpmvArgsT<V, A> &a, int32_t slot, A v) {
+    A *__restrict__ y = a.y;
     const int32_t row = SPLIT ? a.slot_row[slot] : slot;
     if (SPLIT && row >= a.shared_begin) {
         unsafeAtomicAdd(&y[row], v);
@@ -92,9 +85,8 @@ __device__ __forceinline__ void store_row(const SpmvArgs &a, int32_t slot, doubl
     }
 }
 
-template <int WMAX>
-__device__ __forceinline__ double xval(const double *__restrict__ x, const double *sw, int32_t c,
-                                       int32_t wlo, int32_t wlen) {
+template <int WMAX, class A>
+__device__ __forceinline__ A xval(const A *__restrict__ x, const A *sw, int32_t c, int32_t wlo, int32_t wlen) {
     if (WMAX > 0) {
         uint32_t o = (uint32_t)(c - wlo);
         if (o < (uint32_t)wlen) return sw[o];
@@ -102,11 +94,37 @@ __device__ __forceinline__ double xval(const double *__restrict__ x, const doubl
     return x[c];
 }
 
+// Four consecutive stored values starting at the 4-aligned nonzero k0,
+// widened to the accumulation type: binary64 (two 16-byte loads), binary32
+// (one 16-byte load) or bfloat16 bit patterns (one 8-byte load; a bfloat16
+// is the upper half of the binary32 with the same bits).
+struct Vals4d { double v[4]; };
+struct Vals4f { float v[4]; };
+
+__device__ __forceinline__ Vals4d load4(const double *vals, int32_t k0) {
+    const v2d *v2 = reinterpret_cast<const v2d *>(vals);
+    const v2d a = __builtin_nontemporal_load(&v2[k0 >> 1]);
+    const v2d b = __builtin_nontemporal_load(&v2[(k0 >> 1) + 1]);
+    return {{a.x, a.y, b.x, b.y}};
+}
+
+__device__ __forceinline__ Vals4f load4(const float *vals, int32_t k0) {
+    const v4f a = __builtin_nontemporal_load(&reinterpret_cast<const v4f *>(vals)[k0 >> 2]);
+    return {{a.x, a.y, a.z, a.w}};
+}
+
+__device__ __forceinline__ Vals4f load4(const uint16_t *vals, int32_t k0) {
+    const v2u a = __builtin_nontemporal_load(&reinterpret_cast<const v2u *>(vals)[k0 >> 2]);
+    return {{__uint_as_float(a.x << 16), __uint_as_float(a.x & 0xFFFF0000u), __uint_as_float(a.y << 16),
+             __uint_as_float(a.y & 0xFFFF0000u)}};
+}
+
 }  // namespace
 
 // Sum over aligned groups of g lanes (g a power of two, at most 64); every
 // lane of the group receives the total.  Must be reached by the whole wave.
-__device__ __forceinline__ double group_sum_unrolled(double v, int g) {
+template <class A>
+__device__ __forceinline__ A group_sum_unrolled(A v, int g) {
     if (g > 1) v += xor_lanes(v, 1);
     if (g > 2) v += xor_lanes(v, 2);
     if (g > 4) v += xor_lanes(v, 4);
@@ -117,12 +135,11 @@ __device__ __forceinline__ double group_sum_unrolled(double v, int g) {
 }
 
 // One multi-row block: whole slots [d.x, d.y) with nonzeros [d.z, d.w).
-template <int WG, int NPT, bool SPLIT, int WMAX>
-__device__ __forceinline__ void multi_row_block(const SpmvArgs &a, const v4i d, double *sprod, int32_t *sptr,
-                                                const double *swin, int32_t wlo, int32_t wlen) {
+template <int WG, int NPT, bool SPLIT, int WMAX, class V, class A>
+__device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const v4i d, A *sprod, int32_t *sptr,
+                                                const A *swin, int32_t wlo, int32_t wlen) {
     const int tid = threadIdx.x;
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
-    const v2d *__restrict__ v2 = reinterpret_cast<const v2d *>(a.vals);
     const int32_t zb = d.z & ~3;
     const int32_t nr = d.y - d.x;
     const int32_t G = (d.w - zb + 3) >> 2;
@@ -131,11 +148,12 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgs &a, const v4i d, 
         const int gi = tid + u * WG;
         if (gi < G) {
             const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
-            const v2d va = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi]);
-            const v2d vb = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi + 1]);
-            v2d *sp = reinterpret_cast<v2d *>(&sprod[4 * gi]);
-            sp[0] = v2d{va.x * xval<WMAX>(a.x, swin, cc.x, wlo, wlen), va.y * xval<WMAX>(a.x, swin, cc.y, wlo, wlen)};
-            sp[1] = v2d{vb.x * xval<WMAX>(a.x, swin, cc.z, wlo, wlen), vb.y * xval<WMAX>(a.x, swin, cc.w, wlo, wlen)};
+            const auto vv = load4(a.vals, zb + 4 * gi);
+            A *sp = &sprod[4 * gi];
+            sp[0] = vv.v[0] * xval<WMAX>(a.x, swin, cc.x, wlo, wlen);
+            sp[1] = vv.v[1] * xval<WMAX>(a.x, swin, cc.y, wlo, wlen);
+            sp[2] = vv.v[2] * xval<WMAX>(a.x, swin, cc.z, wlo, wlen);
+            sp[3] = vv.v[3] * xval<WMAX>(a.x, swin, cc.w, wlo, wlen);
         }
     }
     for (int i = tid; i <= nr; i += WG) sptr[i] = a.slot_ptr[d.x + i] - zb;
@@ -145,7 +163,7 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgs &a, const v4i d, 
     const int lg = q >= 64 ? 6 : 31 - __builtin_clz(q);
     const int g = 1 << lg;
     const int grp = tid >> lg, lane = tid & (g - 1);
-    double sum = 0.0;
+    A sum = 0;
     if (grp < nr) {
         const int k1 = sptr[grp + 1];
         for (int k = sptr[grp] + lane; k < k1; k += g) sum += sprod[k];
@@ -160,38 +178,36 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgs &a, const v4i d, 
 // partial sum, and the workgroup that arrives last (counted by an atomic
 // counter) adds the partials in segment order, writes the slot and resets
 // the counter for the next product.
-template <int WG, int NPT, bool SPLIT, int WMAX>
-__device__ __forceinline__ void long_row_segment(const SpmvArgs &a, const v4i d, double *swave,
-                                                 const double *swin, int32_t wlo, int32_t wlen) {
+template <int WG, int NPT, bool SPLIT, int WMAX, class V, class A>
+__device__ __forceinline__ void long_row_segment(const SpmvArgsT<V, A> &a, const v4i d, A *swave, const A *swin,
+                                                 int32_t wlo, int32_t wlen) {
     const int tid = threadIdx.x;
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
-    const v2d *__restrict__ v2 = reinterpret_cast<const v2d *>(a.vals);
     const int32_t zb = d.z & ~3;
     const int32_t G = (d.w - zb + 3) >> 2;
-    double acc = 0.0;
+    A acc = 0;
 #pragma unroll
     for (int u = 0; u < NPT / 4; ++u) {
         const int gi = tid + u * WG;
         if (gi < G) {
             const int32_t k0 = zb + 4 * gi;
             const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
-            const v2d va = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi]);
-            const v2d vb = __builtin_nontemporal_load(&v2[(zb >> 1) + 2 * gi + 1]);
-            const double p0 = va.x * xval<WMAX>(a.x, swin, cc.x, wlo, wlen);
-            const double p1 = va.y * xval<WMAX>(a.x, swin, cc.y, wlo, wlen);
-            const double p2 = vb.x * xval<WMAX>(a.x, swin, cc.z, wlo, wlen);
-            const double p3 = vb.y * xval<WMAX>(a.x, swin, cc.w, wlo, wlen);
-            acc += (k0 >= d.z) ? p0 : 0.0;
-            acc += (k0 + 1 >= d.z && k0 + 1 < d.w) ? p1 : 0.0;
-            acc += (k0 + 2 >= d.z && k0 + 2 < d.w) ? p2 : 0.0;
-            acc += (k0 + 3 >= d.z && k0 + 3 < d.w) ? p3 : 0.0;
+            const auto vv = load4(a.vals, k0);
+            const A p0 = vv.v[0] * xval<WMAX>(a.x, swin, cc.x, wlo, wlen);
+            const A p1 = vv.v[1] * xval<WMAX>(a.x, swin, cc.y, wlo, wlen);
+            const A p2 = vv.v[2] * xval<WMAX>(a.x, swin, cc.z, wlo, wlen);
+            const A p3 = vv.v[3] * xval<WMAX>(a.x, swin, cc.w, wlo, wlen);
+            acc += (k0 >= d.z) ? p0 : A(0);
+            acc += (k0 + 1 >= d.z && k0 + 1 < d.w) ? p1 : A(0);
+            acc += (k0 + 2 >= d.z && k0 + 2 < d.w) ? p2 : A(0);
+            acc += (k0 + 3 >= d.z && k0 + 3 < d.w) ? p3 : A(0);
         }
     }
     acc = group_sum_unrolled(acc, 64);
     if ((tid & 63) == 0) swave[tid >> 6] = acc;
     __syncthreads();
     if (tid == 0) {
-        double part = 0.0;
+        A part = 0;
 #pragma unroll
         for (int w = 0; w < WG / 64; ++w) part += swave[w];
         const int32_t lr = -1 - d.y;
@@ -206,14 +222,14 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgs &a, const v4i d,
             // before the counter moves: wait for the store to complete.  An
             // acquire/release fence would also write back and invalidate the
             // whole L2 of the XCD, discarding the cached x entries.
-            __hip_atomic_store(&a.partials[base + seg], part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.partials[base + seg], (double)part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): expcnt and lgkmcnt left unconstrained
             const uint32_t done =
                 __hip_atomic_fetch_add(&a.counters[lr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (done == (uint32_t)nseg - 1) {
-                double sum = 0.0;
+                A sum = 0;
                 for (int32_t k = 0; k < nseg; ++k)
-                    sum += __hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    sum += (A)__hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&a.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 store_row<SPLIT>(a, d.x, sum);
             }
@@ -223,12 +239,12 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgs &a, const v4i d,
 
 // TILED = false: workgroup i runs block remap(i), no window.  TILED = true:
 // workgroup i runs the blocks of tile remap(i) with the tile's LDS window.
-template <int WG, int NPT, bool SPLIT, int WMAX, bool TILED>
-__global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgs a) {
-    __shared__ double sprod[NPT * WG];
+template <int WG, int NPT, bool SPLIT, int WMAX, bool TILED, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
+    __shared__ A sprod[NPT * WG];
     __shared__ int32_t sptr[WG + 1];
-    __shared__ double swave[WG / 64];
-    __shared__ double swin[WMAX > 0 ? WMAX : 1];
+    __shared__ A swave[WG / 64];
+    __shared__ A swin[WMAX > 0 ? WMAX : 1];
     const int tid = threadIdx.x;
     const int id = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
     if (!TILED) {
@@ -250,6 +266,98 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgs a) {
         else long_row_segment<WG, NPT, SPLIT, WMAX>(a, d, swave, swin, wlo, wlen);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------- CG vectors
+// Conjugate-gradient vector operations of the precision mode.  Dot products
+// are summed per workgroup in a fixed order and the workgroup sums by one
+// more workgroup in index order, so they are reproducible.
+
+constexpr int kDotWG = 256;
+constexpr int kDotMaxGroups = 1024;
+
+template <class T>
+__global__ __launch_bounds__(kDotWG) void dot_partial_kernel(const T *__restrict__ a, const T *__restrict__ b,
+                                                             int64_t n, T *__restrict__ part) {
+    __shared__ T sw[kDotWG / 64];
+    T acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kDotWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kDotWG)
+        acc += a[i] * b[i];
+    acc = group_sum_unrolled(acc, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T s = 0;
+        for (int w = 0; w < kDotWG / 64; ++w) s += sw[w];
+        part[blockIdx.x] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kDotWG) void sum_kernel(const T *__restrict__ part, int n, T *__restrict__ out) {
+    __shared__ T sw[kDotWG / 64];
+    T acc = 0;
+    for (int i = threadIdx.x; i < n; i += kDotWG) acc += part[i];
+    acc = group_sum_unrolled(acc, 64);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T s = 0;
+        for (int w = 0; w < kDotWG / 64; ++w) s += sw[w];
+        *out = s;
+    }
+}
+
+// r_low = r / scale; p = r_low; d = 0
+template <class T>
+__global__ void cg_start_kernel(const double *__restrict__ r, double inv_scale, T *__restrict__ rl,
+                                T *__restrict__ p, T *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        T v = (T)(r[i] * inv_scale);
+        rl[i] = v;
+        p[i] = v;
+        d[i] = 0;
+    }
+}
+
+// alpha = rr / pq; d += alpha p; r -= alpha q
+template <class T>
+__global__ void cg_update_kernel(const T *__restrict__ rr, const T *__restrict__ pq, T *__restrict__ d,
+                                 T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const T alpha = *rr / *pq;
+        d[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+    }
+}
+
+// beta = rr_new / rr; p = r + beta p
+template <class T>
+__global__ void cg_direction_kernel(const T *__restrict__ rr, const T *__restrict__ rr_new, T *__restrict__ p,
+                                    const T *__restrict__ r, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = r[i] + (*rr_new / *rr) * p[i];
+}
+
+// x += scale * d (binary64 update)
+template <class T>
+__global__ void ir_update_kernel(double *__restrict__ x, const T *__restrict__ d, double scale, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += scale * (double)d[i];
+}
+
+// r = b - Ax (binary64 residual)
+__global__ void residual_kernel(const double *__restrict__ b, const double *__restrict__ ax, double *__restrict__ r,
+                                int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = b[i] - ax[i];
+}
+
+__global__ void to_f32_kernel(const double *__restrict__ x, float *__restrict__ out, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)x[i];
 }
 
 __global__ void fill_kernel(double *__restrict__ y, int64_t lo, int64_t hi, double v) {
@@ -314,47 +422,70 @@ __global__ __launch_bounds__(kStreamWG) void stream_copy_kernel(const v2d *__res
 // ----------------------------------------------------------------- launchers
 
 namespace {
-template <int WG, int NPT, int WMAX>
-hipError_t launch_variant(const SpmvArgs &a, bool split, bool tiled, hipStream_t s) {
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_variant(const SpmvArgsT<V, A> &a, bool split, bool tiled, hipStream_t s) {
     if (a.ntiles <= 0) return hipSuccess;
     if (WMAX == 0 && !tiled) {
         if (split)
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, 0, false>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, 0, false, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
         else
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, 0, false>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, 0, false, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
     } else {
         if (split)
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, WMAX, true>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, WMAX, true, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
         else
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, WMAX, true>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, WMAX, true, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
     }
     return hipGetLastError();
 }
-}  // namespace
 
+template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
-    hipError_t (*fn)(const SpmvArgs &, bool, bool, hipStream_t);
+    hipError_t (*fn)(const SpmvArgsT<V, A> &, bool, bool, hipStream_t);
 };
 
-static const Variant kVariants[] = {
-    {64, 8, 0, launch_variant<64, 8, 0>},
-    {128, 4, 0, launch_variant<128, 4, 0>},
-    {128, 8, 0, launch_variant<128, 8, 0>},
-    {256, 4, 0, launch_variant<256, 4, 0>},
-    {512, 4, 0, launch_variant<512, 4, 0>},
-    {128, 4, 4096, launch_variant<128, 4, 4096>},
-    {128, 4, 8192, launch_variant<128, 4, 8192>},
-    {128, 4, 16384, launch_variant<128, 4, 16384>},
-    {256, 4, 4096, launch_variant<256, 4, 4096>},
-    {256, 4, 8192, launch_variant<256, 4, 8192>},
-    {256, 4, 16384, launch_variant<256, 4, 16384>},
-    {512, 4, 16384, launch_variant<512, 4, 16384>},
+// binary64: every schedule shape; low precision: the untiled shapes
+template <class V, class A>
+struct Table;
+
+template <>
+struct Table<double, double> {
+    static constexpr Variant<double, double> v[] = {
+        {64, 8, 0, launch_variant<64, 8, 0, double, double>},
+        {128, 4, 0, launch_variant<128, 4, 0, double, double>},
+        {128, 8, 0, launch_variant<128, 8, 0, double, double>},
+        {256, 4, 0, launch_variant<256, 4, 0, double, double>},
+        {512, 4, 0, launch_variant<512, 4, 0, double, double>},
+        {128, 4, 4096, launch_variant<128, 4, 4096, double, double>},
+        {128, 4, 8192, launch_variant<128, 4, 8192, double, double>},
+        {128, 4, 16384, launch_variant<128, 4, 16384, double, double>},
+        {256, 4, 4096, launch_variant<256, 4, 4096, double, double>},
+        {256, 4, 8192, launch_variant<256, 4, 8192, double, double>},
+        {256, 4, 16384, launch_variant<256, 4, 16384, double, double>},
+        {512, 4, 16384, launch_variant<512, 4, 16384, double, double>},
+    };
 };
 
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out) {
+template <class V>
+struct LowTable {
+    static constexpr Variant<V, float> v[] = {
+        {64, 8, 0, launch_variant<64, 8, 0, V, float>},
+        {128, 4, 0, launch_variant<128, 4, 0, V, float>},
+        {128, 8, 0, launch_variant<128, 8, 0, V, float>},
+        {256, 4, 0, launch_variant<256, 4, 0, V, float>},
+        {512, 4, 0, launch_variant<512, 4, 0, V, float>},
+    };
+};
+template <>
+struct Table<float, float> : LowTable<float> {};
+template <>
+struct Table<uint16_t, float> : LowTable<uint16_t> {};
+
+template <class V, class A>
+bool find_variant(int wg, int npt, int window_entries, int *wmax_out) {
     int best = -1;
-    for (const Variant &v : kVariants) {
+    for (const auto &v : Table<V, A>::v) {
         if (v.wg != wg || v.npt != npt) continue;
         if (window_entries <= 0 ? v.wmax == 0 : v.wmax >= window_entries) {
             if (best < 0 || v.wmax < best) best = v.wmax;
@@ -365,13 +496,96 @@ bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out) {
     return true;
 }
 
-hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s) {
+template <class V, class A>
+hipError_t launch_any(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entries, bool tiled, bool split,
+                      hipStream_t s) {
     int wmax = 0;
-    if (!spmv_variant_exists(wg, npt, window_entries, &wmax)) return hipErrorInvalidValue;
-    for (const Variant &v : kVariants)
+    if (!find_variant<V, A>(wg, npt, window_entries, &wmax)) return hipErrorInvalidValue;
+    for (const auto &v : Table<V, A>::v)
         if (v.wg == wg && v.npt == npt && v.wmax == wmax) return v.fn(a, split, tiled, s);
     return hipErrorInvalidValue;
+}
+}  // namespace
+
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out) {
+    return find_variant<double, double>(wg, npt, window_entries, wmax_out);
+}
+
+bool spmv_lowp_variant_exists(int wg, int npt, int window_entries) {
+    return find_variant<float, float>(wg, npt, window_entries, nullptr);
+}
+
+hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
+                       hipStream_t s) {
+    return launch_any(a, wg, npt, window_entries, tiled, split, s);
+}
+
+hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s) {
+    return launch_any(a, wg, npt, -1, false, split, s);
+}
+
+hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s) {
+    return launch_any(a, wg, npt, -1, false, split, s);
+}
+
+static inline unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+int dot_groups(int64_t n) { return (int)std::min<int64_t>(kDotMaxGroups, std::max<int64_t>(1, (n + kDotWG - 1) / kDotWG)); }
+
+template <class T>
+hipError_t launch_dot(const T *a, const T *b, int64_t n, T *part, T *out, hipStream_t s) {
+    const int g = dot_groups(n);
+    hipLaunchKernelGGL(dot_partial_kernel<T>, dim3(g), dim3(kDotWG), 0, s, a, b, n, part);
+    hipLaunchKernelGGL(sum_kernel<T>, dim3(1), dim3(kDotWG), 0, s, part, g, out);
+    return hipGetLastError();
+}
+template hipError_t launch_dot<float>(const float *, const float *, int64_t, float *, float *, hipStream_t);
+template hipError_t launch_dot<double>(const double *, const double *, int64_t, double *, double *, hipStream_t);
+
+template <class T>
+hipError_t launch_cg_start(const double *r, double inv_scale, T *rl, T *p, T *d, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cg_start_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, r, inv_scale, rl, p, d, n);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_start<float>(const double *, double, float *, float *, float *, int64_t, hipStream_t);
+template hipError_t launch_cg_start<double>(const double *, double, double *, double *, double *, int64_t, hipStream_t);
+
+template <class T>
+hipError_t launch_cg_update(const T *rr, const T *pq, T *d, T *r, const T *p, const T *q, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cg_update_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, rr, pq, d, r, p, q, n);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_update<float>(const float *, const float *, float *, float *, const float *,
+                                            const float *, int64_t, hipStream_t);
+template hipError_t launch_cg_update<double>(const double *, const double *, double *, double *, const double *,
+                                             const double *, int64_t, hipStream_t);
+
+template <class T>
+hipError_t launch_cg_direction(const T *rr, const T *rr_new, T *p, const T *r, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cg_direction_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, rr, rr_new, p, r, n);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_direction<float>(const float *, const float *, float *, const float *, int64_t,
+                                               hipStream_t);
+template hipError_t launch_cg_direction<double>(const double *, const double *, double *, const double *, int64_t,
+                                                hipStream_t);
+
+template <class T>
+hipError_t launch_ir_update(double *x, const T *d, double scale, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(ir_update_kernel<T>, dim3(grid_of(n)), dim3(256), 0, s, x, d, scale, n);
+    return hipGetLastError();
+}
+template hipError_t launch_ir_update<float>(double *, const float *, double, int64_t, hipStream_t);
+template hipError_t launch_ir_update<double>(double *, const double *, double, int64_t, hipStream_t);
+
+hipError_t launch_residual(const double *b, const double *ax, double *r, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(residual_kernel, dim3(grid_of(n)), dim3(256), 0, s, b, ax, r, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double *x, float *out, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(n)), dim3(256), 0, s, x, out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(double *y, int64_t lo, int64_t hi, double v, hipStream_t s) {

@@ -114,10 +114,13 @@ struct spx_plan_s {
     std::vector<int32_t> blk_desc;              // 4 per block: slot range, nonzero range
     std::vector<int32_t> tiles;                 // 4 per tile
     std::vector<int32_t> long_seg_ptr;          // [nlong+1] first partial-sum entry of each long slot
+    std::vector<float> vals32;                  // precision mode: values rounded to binary32
+    std::vector<uint16_t> vals16;               // precision mode: binary32 values rounded to bfloat16
     int64_t window_nnz = 0, window_bytes_fill = 0;
     // device copies
     spx::DevPtr d_slot_ptr, d_slot_row, d_colidx, d_vals, d_row_perm, d_col_perm;
     spx::DevPtr d_blk_desc, d_tiles, d_long_seg_ptr, d_partials, d_counters;
+    spx::DevPtr d_vals32, d_vals16;
     // statistics
     int64_t sum_lambda_col = 0, sum_lambda_row = 0, border_row_nnz = 0, cut = 0;
     double partition_seconds = 0.0, plan_seconds = 0.0;

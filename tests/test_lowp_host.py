@@ -1,0 +1,52 @@
+"""Precision mode on the host: the library's rounding of the stored values
+to binary32 and bfloat16 equals the oracle's bit for bit, in every form's
+storage order, including ties, subnormals, overflow and NaN."""
+import numpy as np
+import pytest
+
+import paper_1203_2739_amd as spx
+from synth import CSR, gen_c1
+
+
+def special_csr():
+    rng = np.random.default_rng(12)
+    m = n = 40
+    rp = np.arange(0, 4 * m + 1, 4, dtype=np.int64)
+    cols = np.concatenate([np.sort(rng.choice(n, 4, replace=False)) for _ in range(m)]).astype(np.int32)
+    special = [1 + 2.0**-8, 1 + 3 * 2.0**-8, -(1 + 2.0**-8), 1e-40, -1e-45, 3.5e38, -1e300, 1e300,
+               np.nan, np.inf, -np.inf, 0.0, -0.0, 1 + 2.0**-24, 1 + 3 * 2.0**-24, 1.0 + 2.0**-25,
+               65504.0, 2.0**-126, 2.0**-149, 1.00390625]
+    v = np.concatenate([special, rng.standard_normal(4 * m - len(special)) * 10.0 ** rng.integers(-30, 30, 4 * m - len(special))])
+    return CSR(m, n, rp, cols, v)
+
+
+@pytest.mark.parametrize("which", ["special", "c1"])
+def test_rounding_matches_oracle(orc, which):
+    A = special_csr() if which == "special" else gen_c1()
+    M = spx.from_csr(A, device=False)
+    plans = [(spx.plan_plain(M), None)]
+    if which == "c1":
+        plans += [(spx.reorder_sb(M, 8, 0, 1)[0], "sb"), (spx.reorder_db(M, 8, 0, 1)[0], "db")]
+    for P, form in plans:
+        vals = A.vals if form is None else P.export_csr()[2]
+        for prec in ("f32", "bf16"):
+            spx.plan_add_lowp(P, prec)
+            got = P.export_lowp(prec)
+            f = orc.to_f32(vals)
+            ref = f if prec == "f32" else orc.f32_to_bf16(f)
+            assert np.array_equal(got.view(np.uint32 if prec == "f32" else np.uint16),
+                                  ref.view(np.uint32 if prec == "f32" else np.uint16)), (form, prec)
+
+
+def test_lowp_errors():
+    A = gen_c1()
+    M = spx.from_csr(A, device=False)
+    P = spx.plan_plain(M)
+    with pytest.raises(spx.SpxError):
+        P.export_lowp("f32")          # not added yet
+    with pytest.raises(spx.SpxError):
+        spx.plan_add_lowp(P, 7)
+    S = spx.split(M, 2, 0, 0)[0]
+    with pytest.raises(spx.SpxError) as e:
+        spx.plan_add_lowp(S, "f32")
+    assert e.value.code == -5
