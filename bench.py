@@ -226,6 +226,75 @@ def main_precision(args, torch, spx):
     print(json.dumps(line), flush=True)
 
 
+def main_batched(args, torch, spx):
+    """The uneven batch: 256 matrices (n log-uniform in [10^3, 2*10^5], mean
+    degree U[5, 50], Zipf(2.2) rows) with 1, 8 or 32 right-hand sides each,
+    run as one persistent launch replayed from a HIP graph with the
+    autotuned schedule, against one plain SpMV launch per matrix and
+    right-hand side."""
+    import oracle as orc
+    from synth import gen_c4_one
+    count = 256
+    t = time.time()
+    mats, ks = [], []
+    for j in range(count):
+        A, k = gen_c4_one(j)
+        mats.append(A)
+        ks.append(k)
+        if j % 32 == 31:
+            log(f"generated {j + 1}/{count} ({time.time() - t:.0f} s)")
+    tot_nnz = sum(A.nnz for A in mats)
+    plans = [spx.plan_plain(spx.from_csr(A)) for A in mats]
+    rng = np.random.default_rng(4444)
+    X, Y, Xc, Yc = [], [], [], []
+    for A, k in zip(mats, ks):
+        x = torch.from_numpy(rng.uniform(-1, 1, (A.n, k))).cuda()
+        X.append(x[:, 0].contiguous() if k == 1 else x)
+        Y.append(torch.empty((A.m,) if k == 1 else (A.m, k), dtype=torch.float64, device="cuda"))
+        Xc.append(x.t().contiguous())  # columns for the plain launches
+        Yc.append(torch.empty((k, A.m), dtype=torch.float64, device="cuda"))
+    log(f"batch of {count}: nnz={tot_nnz}, right-hand sides {sum(ks)} ({time.time() - t:.0f} s)")
+    B = spx.Batch(plans, ks)
+    B.bind(X, Y)
+    best = B.autotune(reps=3)
+    log("autotune", json.dumps(best))
+    inf = B.info()
+    B.capture()
+    ms_graph = time_calls(torch, B.replay, args.warmup, args.steps)
+    ms_run = time_calls(torch, B.run, args.warmup, args.steps)
+
+    def plain_all():
+        for P, xc, yc, k in zip(plans, Xc, Yc, ks):
+            for c in range(k):
+                spx.spmv(P, xc[c], yc[c])
+    ms_plain = time_calls(torch, plain_all, 1, max(3, args.steps // 10))
+    # parity on a sample of members (every 32nd), against the oracle
+    B.replay()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for j in range(0, count, 32):
+        A = mats[j]
+        x = X[j].cpu().numpy().reshape(A.n, -1)
+        y = Y[j].cpu().numpy().reshape(A.m, -1)
+        ref = orc.spmm(A, x)
+        bound = orc.spmm(type(A)(A.m, A.n, A.rowptr, A.colidx, np.abs(A.vals)), np.abs(x))
+        worst = max(worst, float(np.max(np.abs(y - ref) / np.maximum(bound, 1e-300))))
+    gbs = inf["bytes"] / (ms_graph * 1e-3) / 1e9
+    line = {
+        "metric": "batched SpMV effective GB/s, one persistent graph launch vs plain CSR launches",
+        "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_graph, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"256 uneven matrices, nnz={tot_nnz}, 1/8/32 right-hand sides"},
+        "speedup_vs_plain": round(ms_plain / ms_graph, 3),
+        "ms_plain_launches": round(ms_plain, 4), "ms_single_launch": round(ms_run, 4),
+        "plain_launches": int(sum(ks)), "items": inf["nitems"], "grid": inf["grid"],
+        "bytes": inf["bytes"], "autotune": best,
+        "sample_max_rel_err": worst, "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,7 +309,7 @@ def main():
     ap.add_argument("--tune", default="", help="wg,nnz_per_block[,blocks_per_tile,window_entries]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
-    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision"],
+    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched"],
                     help="spmv: repeated products on the n=10^6 matrix (default); precision: "
                          "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
     ap.add_argument("--only-stream", action="store_true",
@@ -260,6 +329,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "precision":
         return main_precision(args, torch, spx)
+    if args.workload == "batched":
+        return main_batched(args, torch, spx)
     if args.only_stream:
         nbytes = 1 << 30
         src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()

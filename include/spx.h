@@ -269,6 +269,54 @@ spx_status spx_cg_ir(spx_plan P, int32_t precision, const double *b, double *x, 
                      void *stream);
 
 /* ----------------------------------------------------------------------
+ * Batched products.  Not part of the paper: Y_i = A_i X_i for many plain, SB
+ * or DB plans at once, X_i n_i x k_i and Y_i m_i x k_i row-major binary64
+ * device arrays (leading dimensions ldx[i] >= k_i, ldy[i] >= k_i; k_i = 1
+ * needs unit strides), 1 <= k_i <= 64.  One persistent launch runs every
+ * block of every matrix: workgroups take items from a queue (reset by a
+ * kernel, so the launch can be captured in a HIP graph and replayed).  Each
+ * entry of Y is a sum over its row's nonzeros in a fixed tree order, so the
+ * binary64 bound of spx_spmv applies per column.
+ *
+ * spx_batch_create: the batch over count plans with nrhs[i] right-hand
+ *   sides; the plans must outlive the batch.
+ * spx_batch_bind: the device arrays X[i], Y[i] and their leading dimensions
+ *   (copied; rebinding drops a captured graph).
+ * spx_batch_run: one launch on the stream.  Runs of one batch must not
+ *   overlap in time (they share the queue and the long-row scratch).
+ * spx_batch_capture / spx_batch_replay: capture one run in a HIP graph on
+ *   the batch's own stream, then launch the graph on any stream.
+ * spx_batch_autotune: times every schedule candidate (item order, block
+ *   capacity divisor for several right-hand sides, reduction bound for one)
+ *   on the bound arrays, `reps` runs each, keeps the fastest and reports it.
+ *   It overwrites Y.
+ * spx_batch_configure: sets a schedule explicitly.
+ * spx_spmv_batched: create, bind, run, wait and destroy in one call.
+ */
+typedef struct spx_batch_s *spx_batch;
+
+typedef struct spx_batch_config_s {
+    int32_t order;        /* 0: matrices by decreasing work; 1: all blocks by decreasing work */
+    int32_t span_div;     /* k > 1: block capacity 1024 / (k * span_div) nonzeros, 1..64      */
+    int32_t reduce_iters; /* k = 1: per-row reduction loop bound, 1..64                        */
+    float ms;             /* autotune: mean time of one run of the chosen schedule             */
+} spx_batch_config;
+
+spx_status spx_batch_create(int32_t count, const spx_plan *plans, const int32_t *nrhs, spx_batch *out);
+void spx_batch_destroy(spx_batch B);
+spx_status spx_batch_bind(spx_batch B, const double *const *X, const int64_t *ldx, double *const *Y,
+                          const int64_t *ldy);
+spx_status spx_batch_run(spx_batch B, void *stream);
+spx_status spx_batch_capture(spx_batch B);
+spx_status spx_batch_replay(spx_batch B, void *stream);
+spx_status spx_batch_autotune(spx_batch B, int32_t reps, spx_batch_config *best, void *stream);
+spx_status spx_batch_configure(spx_batch B, const spx_batch_config *cfg);
+spx_status spx_batch_info(spx_batch B, int32_t *nitems, int64_t *bytes, int32_t *grid);
+spx_status spx_spmv_batched(int32_t count, const spx_plan *plans, const int32_t *nrhs,
+                            const double *const *X, const int64_t *ldx, double *const *Y,
+                            const int64_t *ldy, void *stream);
+
+/* ----------------------------------------------------------------------
  * Inspection (host arrays, caller-allocated; any pointer may be NULL).
  *
  * spx_plan_export_csr: the stored matrix of a plain/SB/DB plan in CSR:

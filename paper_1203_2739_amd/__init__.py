@@ -87,7 +87,22 @@ _SIGS = {
     "spx_plan_export_lowp": ([_VP, _I32, _VP], _I32),
     "spx_spmv_lowp": ([_VP, _I32, _VP, _VP, _VP], _I32),
     "spx_cg_ir": ([_VP, _I32, _VP, _VP, ctypes.c_double, ctypes.c_double, _I32, _I32, _VP, _VP], _I32),
+    "spx_batch_create": ([_I32, _VP, _VP, _VP], _I32),
+    "spx_batch_destroy": ([_VP], None),
+    "spx_batch_bind": ([_VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_batch_run": ([_VP, _VP], _I32),
+    "spx_batch_capture": ([_VP], _I32),
+    "spx_batch_replay": ([_VP, _VP], _I32),
+    "spx_batch_autotune": ([_VP, _I32, _VP, _VP], _I32),
+    "spx_batch_configure": ([_VP, _VP], _I32),
+    "spx_batch_info": ([_VP, _VP, _VP, _VP], _I32),
+    "spx_spmv_batched": ([_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
 }
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("span_div", ctypes.c_int32),
+                ("reduce_iters", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 _PREC = {"f64": PREC_F64, "f32": PREC_F32, "bf16": PREC_BF16}
@@ -455,3 +470,87 @@ def cg_ir(P: Plan, precision, b, x, tol=1e-10, inner_tol=1e-3, max_outer=50, max
         _check(rc)
     return {"outer": st.outer, "inner": st.inner, "rel_residual": st.rel_residual,
             "seconds": st.seconds, "converged": rc == 0}
+
+
+# ---------------------------------------------------------------- batched products
+
+def _vec_table(tensors, ks):
+    """Pointer and leading-dimension tables of row-major (rows, k) tensors."""
+    import torch
+    n = len(tensors)
+    ptrs = (ctypes.c_void_p * max(n, 1))()
+    lds = (ctypes.c_int64 * max(n, 1))()
+    for i, (t, k) in enumerate(zip(tensors, ks)):
+        if not t.is_cuda or t.dtype != torch.float64:
+            raise ValueError("batched vectors must be float64 device tensors")
+        if t.dim() == 1:
+            if k != 1 or t.stride(0) != 1:
+                raise ValueError("a 1-D tensor needs k = 1 and unit stride")
+            lds[i] = 1
+        else:
+            if t.shape[1] != k or t.stride(1) != 1:
+                raise ValueError("expected a (rows, k) tensor with unit column stride")
+            lds[i] = t.stride(0)
+        ptrs[i] = t.data_ptr()
+    return ptrs, lds
+
+
+class Batch:
+    """Y_i = A_i X_i for many plans in one persistent launch."""
+
+    def __init__(self, plans, nrhs):
+        self.plans = list(plans)  # kept alive: the batch uses their device arrays
+        self.nrhs = [int(k) for k in nrhs]
+        arr = (ctypes.c_void_p * max(len(self.plans), 1))(*[p.handle.value for p in self.plans])
+        ks = np.ascontiguousarray(self.nrhs, dtype=np.int32)
+        h = _VP()
+        _check(lib().spx_batch_create(len(self.plans), arr, _hp(ks), ctypes.byref(h)))
+        self._h = h
+        self._bound = None
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().spx_batch_destroy(self._h)
+        except Exception:
+            pass
+
+    def bind(self, X, Y):
+        xp, xl = _vec_table(X, self.nrhs)
+        yp, yl = _vec_table(Y, self.nrhs)
+        _check(lib().spx_batch_bind(self._h, xp, xl, yp, yl))
+        self._bound = (list(X), list(Y))
+
+    def run(self, stream=None):
+        _check(lib().spx_batch_run(self._h, _stream(stream)))
+
+    def capture(self):
+        _check(lib().spx_batch_capture(self._h))
+
+    def replay(self, stream=None):
+        _check(lib().spx_batch_replay(self._h, _stream(stream)))
+
+    def autotune(self, reps=3, stream=None):
+        c = BatchConfig()
+        _check(lib().spx_batch_autotune(self._h, int(reps), ctypes.byref(c), _stream(stream)))
+        return {"order": c.order, "span_div": c.span_div, "reduce_iters": c.reduce_iters, "ms": c.ms}
+
+    def configure(self, order=0, span_div=1, reduce_iters=64):
+        c = BatchConfig(order, span_div, reduce_iters, 0.0)
+        _check(lib().spx_batch_configure(self._h, ctypes.byref(c)))
+
+    def info(self):
+        ni, gr = ctypes.c_int32(), ctypes.c_int32()
+        nb = ctypes.c_int64()
+        _check(lib().spx_batch_info(self._h, ctypes.byref(ni), ctypes.byref(nb), ctypes.byref(gr)))
+        return {"nitems": ni.value, "bytes": nb.value, "grid": gr.value}
+
+
+def spmv_batched(plans, nrhs, X, Y, stream=None):
+    """One-shot batched products (create, bind, run, wait, destroy)."""
+    arr = (ctypes.c_void_p * max(len(plans), 1))(*[p.handle.value for p in plans])
+    ks = [int(k) for k in nrhs]
+    kk = np.ascontiguousarray(ks, dtype=np.int32)
+    xp, xl = _vec_table(X, ks)
+    yp, yl = _vec_table(Y, ks)
+    _check(lib().spx_spmv_batched(len(plans), arr, _hp(kk), xp, xl, yp, yl, _stream(stream)))

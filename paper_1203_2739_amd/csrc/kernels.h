@@ -34,6 +34,32 @@ struct SpmvArgsT {
 };
 using SpmvArgs = SpmvArgsT<double, double>;
 
+// Batched products: one matrix of the batch (device pointers).  X is n x k
+// row-major with leading dimension ldx, Y m x k with ldy.
+struct BatchMat {
+    const int32_t *slot_ptr;
+    const int32_t *colidx;
+    const double *vals;
+    const double *X;
+    double *Y;
+    int64_t ldx, ldy;
+    int32_t k;                    // right-hand sides, 1..64
+    int32_t span;                 // nonzeros per long-row segment (k > 1 items)
+    const int32_t *long_seg_ptr;  // per long row: first partial index
+    double *partials;             // k per long-row segment
+    uint32_t *counters;           // per long row, zero between launches
+};
+struct BatchArgs {
+    const BatchMat *mats;
+    const int32_t *items;  // 5 per item: matrix, first slot, end slot (or -1 - long row), first nz, end nz
+    int32_t nitems;
+    uint32_t *queue;       // reset by launch_batch before the persistent kernel
+};
+constexpr int kBatchWG = 256;
+// Queue reset then the persistent kernel on `grid` workgroups.
+hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s);
+int batch_grid();  // workgroups that are resident at once on the device
+
 // One workgroup of wg threads per tile (tiled) or per block (not tiled);
 // ntiles counts workgroups.  npt = nonzeros staged per thread.
 bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out);

@@ -268,6 +268,115 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
     }
 }
 
+// ------------------------------------------------------------------ batched
+// One persistent launch over the blocks of many matrices.  Each workgroup
+// takes the next item from a queue counter (items are sorted by decreasing
+// work on the host, so the queue ends with small items) until the queue is
+// empty.  An item is one block or long-row segment of one matrix; a matrix
+// with one right-hand side and unit strides runs the row-block SpMV code,
+// any other matrix the multiple-right-hand-side code below: lanes form
+// groups of k (one lane per right-hand side), groups take the block's
+// nonzeros in turn and leave a_z * X[col_z, j] in LDS, then every (row,
+// right-hand side) pair of the block is summed by one thread.
+
+template <int WG>
+__device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it, double *prod) {
+    const int tid = threadIdx.x;
+    const int k = M.k;
+    const int32_t s_lo = it[1], s_hi = it[2], z_lo = it[3], z_hi = it[4];
+    const int ngroups = WG / k;
+    const int g = tid / k, j = tid - g * k;
+    const int32_t nz = z_hi - z_lo;
+    if (g < ngroups)
+        for (int32_t z = g; z < nz; z += ngroups) {
+            const int32_t c = M.colidx[z_lo + z];
+            prod[z * k + j] = M.vals[z_lo + z] * M.X[(int64_t)c * M.ldx + j];
+        }
+    __syncthreads();
+    if (s_hi >= 0) {
+        const int32_t nr = s_hi - s_lo;
+        for (int p = tid; p < nr * k; p += WG) {
+            const int32_t r = p / k, jj = p - r * k;
+            const int32_t a0 = M.slot_ptr[s_lo + r] - z_lo, a1 = M.slot_ptr[s_lo + r + 1] - z_lo;
+            double sum = 0.0;
+            for (int32_t z = a0; z < a1; ++z) sum += prod[z * k + jj];
+            M.Y[(int64_t)(s_lo + r) * M.ldy + jj] = sum;
+        }
+        return;
+    }
+    // a segment of a long row: one sum per right-hand side, combined by the
+    // segment that arrives last (see long_row_segment)
+    __shared__ uint32_t last;
+    double sum = 0.0;
+    if (tid < k)
+        for (int32_t z = 0; z < nz; ++z) sum += prod[z * k + tid];
+    const int32_t lr = -1 - s_hi;
+    const int32_t base = M.long_seg_ptr[lr], nseg = M.long_seg_ptr[lr + 1] - base;
+    if (nseg == 1) {
+        if (tid < k) M.Y[(int64_t)s_lo * M.ldy + tid] = sum;
+        return;
+    }
+    const int32_t seg = (z_lo - M.slot_ptr[s_lo]) / M.span;
+    if (tid < k) {
+        __hip_atomic_store(&M.partials[(int64_t)(base + seg) * k + tid], sum, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the partial has landed
+    }
+    __syncthreads();
+    if (tid == 0)
+        last = __hip_atomic_fetch_add(&M.counters[lr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+               (uint32_t)nseg - 1;
+    __syncthreads();
+    if (last) {
+        if (tid < k) {
+            double tot = 0.0;
+            for (int32_t q = 0; q < nseg; ++q)
+                tot += __hip_atomic_load(&M.partials[(int64_t)(base + q) * k + tid], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+            M.Y[(int64_t)s_lo * M.ldy + tid] = tot;
+        }
+        if (tid == 0) __hip_atomic_store(&M.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void batch_kernel(BatchArgs b) {
+    __shared__ double lds[4 * WG];
+    __shared__ int32_t sptr[WG + 1];
+    __shared__ double swave[WG / 64];
+    __shared__ int32_t item_sh;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0)
+            item_sh = (int32_t)__hip_atomic_fetch_add(b.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int32_t item = item_sh;
+        __syncthreads();
+        if (item >= b.nitems) break;
+        const int32_t *it = &b.items[5 * (int64_t)item];
+        const BatchMat &M = b.mats[it[0]];
+        if (M.k == 1 && M.ldx == 1 && M.ldy == 1) {
+            SpmvArgs a{};
+            a.slot_ptr = M.slot_ptr;
+            a.colidx = M.colidx;
+            a.vals = M.vals;
+            a.x = M.X;
+            a.y = M.Y;
+            a.long_seg_ptr = M.long_seg_ptr;
+            a.partials = M.partials;
+            a.counters = M.counters;
+            const v4i d = {it[1], it[2], it[3], it[4]};
+            if (d.y >= 0) multi_row_block<WG, 4, false, 0>(a, d, lds, sptr, lds, 0, 0);
+            else long_row_segment<WG, 4, false, 0>(a, d, swave, lds, 0, 0);
+        } else {
+            spmm_block<WG>(M, it, lds);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void queue_reset_kernel(uint32_t *q) { *q = 0u; }
+
 // ---------------------------------------------------------------- CG vectors
 // Conjugate-gradient vector operations of the precision mode.  Dot products
 // are summed per workgroup in a fixed order and the workgroup sums by one
@@ -526,6 +635,21 @@ hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bo
 
 hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s) {
     return launch_any(a, wg, npt, -1, false, split, s);
+}
+
+hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(1), 0, s, b.queue);
+    if (b.nitems > 0 && grid > 0)
+        hipLaunchKernelGGL(batch_kernel<kBatchWG>, dim3(grid), dim3(kBatchWG), 0, s, b);
+    return hipGetLastError();
+}
+
+int batch_grid() {
+    int dev = 0, cus = 256, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_kernel<kBatchWG>, kBatchWG, 0) != hipSuccess || per < 1)
+        per = 4;
+    return cus * per;
 }
 
 static inline unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }

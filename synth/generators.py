@@ -100,7 +100,33 @@ def _dedupe(rows, cols, n, redraw, forbid_diag=False, max_iter=200):
         if idx.size == 0:
             return cols
         cols[idx] = redraw(idx, it)
-    raise RuntimeError("could not draw distinct columns")
+    return _fill_from_complement(rows, cols, n, forbid_diag)
+
+
+def _fill_from_complement(rows, cols, n, forbid_diag):
+    """Last resort for rows so dense that redrawing duplicates does not
+    converge: their duplicate entries take columns the row does not use yet,
+    drawn without replacement from a generator seeded by (n, row)."""
+    key = rows.astype(np.int64) * np.int64(n) + cols.astype(np.int64)
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    dup = np.zeros(rows.size, dtype=bool)
+    dup[order[1:][ks[1:] == ks[:-1]]] = True
+    if forbid_diag:
+        dup |= rows == cols
+    for r in np.unique(rows[dup]):
+        pos = np.flatnonzero(rows == r)
+        bad = pos[dup[pos]]
+        used = np.zeros(n, dtype=bool)
+        used[cols[pos[~dup[pos]]]] = True
+        if forbid_diag and r < n:
+            used[r] = True
+        free = np.flatnonzero(~used)
+        if free.size < bad.size:
+            raise RuntimeError("row degree exceeds the number of columns")
+        rng = np.random.default_rng([int(n), int(r), 0x5EED])
+        cols[bad] = rng.choice(free, size=bad.size, replace=False)
+    return cols
 
 
 def _to_csr(m, n, rows, cols, vals, info=None) -> CSR:

@@ -50,3 +50,14 @@ def test_lowp_errors():
     with pytest.raises(spx.SpxError) as e:
         spx.plan_add_lowp(S, "f32")
     assert e.value.code == -5
+
+
+def test_generator_dense_rows():
+    """Members of the uneven batch with rows as long as the matrix is wide
+    still get distinct, sorted columns in every row."""
+    from synth import gen_c4_one
+    for j in (4, 5, 6):
+        A, k = gen_c4_one(j, base_seed=7001, n_hi=20_000)
+        for i in range(A.m):
+            c = A.colidx[A.rowptr[i]:A.rowptr[i + 1]]
+            assert np.all(np.diff(c) > 0) and (c.size == 0 or (c[0] >= 0 and c[-1] < A.n))
