@@ -297,7 +297,7 @@ typedef struct spx_batch_s *spx_batch;
 
 typedef struct spx_batch_config_s {
     int32_t order;        /* 0: matrices by decreasing work; 1: all blocks by decreasing work */
-    int32_t span_div;     /* k > 1: block capacity 1024 / (k * span_div) nonzeros, 1..64      */
+    int32_t span_div;     /* k > 1: item capacity max(64, 4096 / span_div) nonzeros, 1..64    */
     int32_t reduce_iters; /* k = 1: per-row reduction loop bound, 1..64                        */
     float ms;             /* autotune: mean time of one run of the chosen schedule             */
 } spx_batch_config;

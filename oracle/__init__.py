@@ -547,3 +547,63 @@ def adam_step(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1.0 - b1 ** t)
     vh = v / (1.0 - b2 ** t)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# Selector features (a reading: the 40 inputs of the selector network are
+# log1p(n), log1p(nnz), a 16-bin histogram of row degrees, a 16-bin histogram
+# of column degrees and six structure statistics; the paper defines none of
+# them, they describe what its Section 3-4 methods exploit: how far nonzeros
+# lie from the diagonal and how much block structure there is).
+
+def degree_bin(d):
+    """Bin 0: degree 0; bin b in 1..15: 2^(b-1) <= d < 2^b; bin 15 also takes
+    every degree >= 2^14."""
+    d = np.asarray(d, dtype=np.int64)
+    b = np.zeros(d.shape, dtype=np.int64)
+    pos = d > 0
+    b[pos] = np.minimum(np.floor(np.log2(d[pos])).astype(np.int64) + 1, 15)
+    return b
+
+
+def features(A):
+    """The 40 features of an m x n CSR matrix, binary64 (to be stored in
+    binary32):
+
+      0 log1p(n)           1 log1p(nnz)
+      2..17  fraction of rows in each degree bin (degree_bin)
+      18..33 fraction of columns in each degree bin
+      with u = |i/m - j/n| over the nonzeros (i, j):
+      34 mean u            35 max u
+      36 fraction of nonzeros with u <= 1/64
+      37 fraction of nonzeros in a diagonal block of the 8 x 8 grid,
+         floor(8 i / m) == floor(8 j / n)
+      38 mean over non-empty rows of (last column - first column) / n
+      39 coefficient of variation of the row degrees (std / mean; 0 when
+         the mean is 0)
+    Empty matrices give zeros for every statistic over nonzeros or rows.
+    """
+    m, n, nnz = A.m, A.n, A.nnz
+    f = np.zeros(40)
+    f[0] = np.log1p(n)
+    f[1] = np.log1p(nnz)
+    rdeg = np.diff(_i64(A.rowptr))
+    cdeg = np.bincount(_i64(A.colidx), minlength=n) if n else np.zeros(0, np.int64)
+    if m:
+        f[2:18] = np.bincount(degree_bin(rdeg), minlength=16) / m
+    if n:
+        f[18:34] = np.bincount(degree_bin(cdeg), minlength=16) / n
+    if nnz:
+        i = np.repeat(np.arange(m, dtype=np.int64), rdeg)
+        j = _i64(A.colidx)
+        u = np.abs(i / m - j / n)
+        f[34] = u.mean()
+        f[35] = u.max()
+        f[36] = np.mean(u <= 1.0 / 64.0)
+        f[37] = np.mean((8 * i) // m == (8 * j) // n)
+        ne = np.flatnonzero(rdeg > 0)
+        rp = _i64(A.rowptr)
+        f[38] = np.mean((j[rp[ne + 1] - 1] - j[rp[ne]]) / n)
+    if m and rdeg.mean() > 0:
+        f[39] = rdeg.std() / rdeg.mean()
+    return f

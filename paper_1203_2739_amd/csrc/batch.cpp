@@ -14,9 +14,11 @@
 
 using namespace spx;
 
+constexpr int32_t kMultiSpan = 4096;
+
 struct BatchTune {
     int32_t order = 0;         // 0: matrices by decreasing work, blocks in order; 1: all items by decreasing work
-    int32_t span_div = 1;      // k > 1: block capacity 4 * WG / (k * span_div) nonzeros
+    int32_t span_div = 1;      // k > 1: item capacity kMultiSpan / span_div nonzeros
     int32_t reduce_iters = kReduceIters;
 };
 
@@ -102,7 +104,9 @@ void build_items(spx_batch_s &B) {
     for (int32_t i = 0; i < cnt; ++i) {
         const spx_plan_s &P = *B.plans[i];
         const int32_t k = B.k[i];
-        const int32_t span = k == 1 ? 4 * kBatchWG : std::max(1, 4 * kBatchWG / (k * B.tune.span_div));
+        // k > 1: items of about kMultiSpan nonzeros (rows longer than that are
+        // cut into segments of that length)
+        const int32_t span = k == 1 ? 4 * kBatchWG : std::max(64, kMultiSpan / B.tune.span_div);
         matrix_items(i, P.slot_ptr, k, span, B.tune.reduce_iters, its[i], lsps[i]);
         B.mats[i].span = span;
     }

@@ -275,41 +275,42 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
 // empty.  An item is one block or long-row segment of one matrix; a matrix
 // with one right-hand side and unit strides runs the row-block SpMV code,
 // any other matrix the multiple-right-hand-side code below: lanes form
-// groups of k (one lane per right-hand side), groups take the block's
-// nonzeros in turn and leave a_z * X[col_z, j] in LDS, then every (row,
-// right-hand side) pair of the block is summed by one thread.
+// groups of k (one lane per right-hand side) and each group sums whole rows,
+// reading one contiguous row of X per nonzero.
 
 template <int WG>
-__device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it, double *prod) {
+__device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it, double *red) {
     const int tid = threadIdx.x;
     const int k = M.k;
     const int32_t s_lo = it[1], s_hi = it[2], z_lo = it[3], z_hi = it[4];
     const int ngroups = WG / k;
     const int g = tid / k, j = tid - g * k;
-    const int32_t nz = z_hi - z_lo;
-    if (g < ngroups)
-        for (int32_t z = g; z < nz; z += ngroups) {
-            const int32_t c = M.colidx[z_lo + z];
-            prod[z * k + j] = M.vals[z_lo + z] * M.X[(int64_t)c * M.ldx + j];
-        }
-    __syncthreads();
     if (s_hi >= 0) {
-        const int32_t nr = s_hi - s_lo;
-        for (int p = tid; p < nr * k; p += WG) {
-            const int32_t r = p / k, jj = p - r * k;
-            const int32_t a0 = M.slot_ptr[s_lo + r] - z_lo, a1 = M.slot_ptr[s_lo + r + 1] - z_lo;
-            double sum = 0.0;
-            for (int32_t z = a0; z < a1; ++z) sum += prod[z * k + jj];
-            M.Y[(int64_t)(s_lo + r) * M.ldy + jj] = sum;
-        }
+        // a group of k lanes per row: lane j sums a_z * X[col_z, j] over the
+        // row; the k lanes read one contiguous row of X per nonzero
+        if (g < ngroups)
+            for (int32_t r = s_lo + g; r < s_hi; r += ngroups) {
+                const int32_t a0 = M.slot_ptr[r], a1 = M.slot_ptr[r + 1];
+                double sum = 0.0;
+                for (int32_t z = a0; z < a1; ++z) sum += M.vals[z] * M.X[(int64_t)M.colidx[z] * M.ldx + j];
+                M.Y[(int64_t)r * M.ldy + j] = sum;
+            }
         return;
     }
-    // a segment of a long row: one sum per right-hand side, combined by the
-    // segment that arrives last (see long_row_segment)
+    // a segment of a long row: the groups share its nonzeros, their sums meet
+    // in LDS, and the segments are combined by the one that arrives last
+    // (see long_row_segment)
     __shared__ uint32_t last;
     double sum = 0.0;
-    if (tid < k)
-        for (int32_t z = 0; z < nz; ++z) sum += prod[z * k + tid];
+    if (g < ngroups)
+        for (int32_t z = z_lo + g; z < z_hi; z += ngroups)
+            sum += M.vals[z] * M.X[(int64_t)M.colidx[z] * M.ldx + j];
+    if (g < ngroups) red[g * k + j] = sum;
+    __syncthreads();
+    if (tid < k) {
+        sum = 0.0;
+        for (int q = 0; q < ngroups; ++q) sum += red[q * k + tid];
+    }
     const int32_t lr = -1 - s_hi;
     const int32_t base = M.long_seg_ptr[lr], nseg = M.long_seg_ptr[lr + 1] - base;
     if (nseg == 1) {

@@ -451,3 +451,39 @@ def test_mlp_forward_and_adam_vs_torch(orc):
                          net[2].weight.detach().numpy().ravel(), net[2].bias.detach().numpy(),
                          net[4].weight.detach().numpy().ravel(), net[4].bias.detach().numpy()])
     assert np.allclose(th, tp, rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------- features
+
+def test_features_closed_forms(orc):
+    from synth import CSR
+    n = 64
+    eye = CSR(n, n, np.arange(n + 1), np.arange(n, dtype=np.int32), np.ones(n))
+    f = orc.features(eye)
+    assert f[0] == np.log1p(64) and f[1] == np.log1p(64)
+    assert f[3] == 1.0 and f[19] == 1.0 and f[2:18].sum() == 1.0  # every degree is 1: bin 1
+    assert f[34] == 0.0 and f[35] == 0.0 and f[36] == 1.0 and f[37] == 1.0 and f[38] == 0.0 and f[39] == 0.0
+    # anti-diagonal: u = |i - (n-1-i)| / n = |2i - n + 1| / n, mean (n/2) / n for even n
+    anti = CSR(n, n, np.arange(n + 1), np.arange(n - 1, -1, -1, dtype=np.int32), np.ones(n))
+    g = orc.features(anti)
+    assert abs(g[34] - 0.5) < 1e-15 and abs(g[35] - (n - 1) / n) < 1e-15
+    assert g[36] == 2 / 64  # |2i - 63| <= 1 only for i = 31, 32
+    # diagonal 8x8 grid blocks: i in block i//8, j = 63 - i in block 7 - i//8: never equal
+    assert g[37] == 0.0
+    # one dense row of 64 plus empty rows: row degrees [64, 0 x 63]
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = n
+    dense = CSR(n, n, rp, np.arange(n, dtype=np.int32), np.ones(n))
+    h = orc.features(dense)
+    assert h[2] == 63 / 64 and h[2 + 7] == 1 / 64  # 64 = 2^6 -> bin 7
+    assert h[19] == 1.0                            # every column has degree 1
+    assert abs(h[38] - 63 / 64) < 1e-15             # one non-empty row spanning columns 0..63
+    assert abs(h[39] - np.sqrt(63.0)) < 1e-12       # std/mean of [64, 0 x 63] = sqrt(63)
+    # empty matrix
+    e = orc.features(CSR(5, 3, np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0)))
+    assert e[1] == 0.0 and e[2] == 1.0 and e[18] == 1.0 and np.all(e[34:] == 0.0)
+
+
+def test_degree_bins_edges(orc):
+    d = np.array([0, 1, 2, 3, 4, 7, 8, 2**13, 2**14 - 1, 2**14, 10**6])
+    assert list(orc.degree_bin(d)) == [0, 1, 2, 2, 3, 3, 4, 14, 14, 15, 15]
