@@ -125,12 +125,26 @@ def declared_symbols():
     return sorted(names)
 
 
+def _device_first():
+    """PyTorch for ROCm carries its own HIP runtime beside the one libspx
+    links; the device must be opened by PyTorch's runtime before libspx makes
+    its first HIP call, or that call finds no device."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+        torch.empty(1, device="cuda")
+
+
 def lib():
     """Load libspx.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1203_2739_amd.build.build()")
+        _device_first()
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             fn = getattr(L, name)
