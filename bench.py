@@ -295,6 +295,67 @@ def main_batched(args, torch, spx):
     print(json.dumps(line), flush=True)
 
 
+def main_selector(args, torch, spx):
+    """Learned selector: every one of the 24 choices timed on matrices of the
+    four families (n log-uniform in [n_lo, n_hi]); the network is trained on
+    the training matrices with the library's kernels and judged on held-out
+    ones by regret against exhaustive timing, beside the best fixed choice."""
+    from paper_1203_2739_amd import selector
+    from synth import gen_family
+    rng = np.random.default_rng(5555)
+    N = args.train + args.test
+    fams = ["F1", "F2", "F3", "F4"]
+    mats, T, tpart = [], [], []
+    t = time.time()
+    for i in range(N):
+        n = int(round(np.exp(rng.uniform(np.log(args.n_lo), np.log(args.n_hi)))))
+        A = gen_family(fams[i % 4], 9000 + i, n)
+        times, tp = selector.measure(A, seed=i)
+        mats.append(A)
+        T.append(times)
+        tpart.append(tp)
+        if i % 10 == 9:
+            log(f"measured {i + 1}/{N} ({time.time() - t:.0f} s)")
+    T = np.stack(T)
+    F = selector.feature_matrix(mats)
+    tr, te = np.arange(args.train), np.arange(args.train, N)
+    norm = selector.Normalizer(F[tr])
+    labels = T.argmin(axis=1)
+    t0 = time.time()
+    theta, curve = selector.train(norm(F[tr]), labels[tr], epochs=400, batch=32, lr=3e-3)
+    ttrain = time.time() - t0
+    chosen = selector.predict(theta, norm(F[te]))
+    fixed = selector.best_fixed(T[tr])
+    r_net = selector.regret(T[te], chosen)
+    r_fix = selector.regret(T[te], np.full(te.size, fixed))
+    r_plain = selector.regret(T[te], np.zeros(te.size, int))
+
+    def stats(r):
+        return {"mean": round(float(r.mean()), 4), "median": round(float(np.median(r)), 4),
+                "p90": round(float(np.quantile(r, 0.9)), 4)}
+    nb = np.array([alg_bytes(mats[i].m, mats[i].n, mats[i].nnz) for i in te])
+    gbs = lambda tt: float(np.mean(nb / (tt * 1e-3) / 1e9))  # noqa: E731
+    sel_t = T[te, chosen]
+    line = {
+        "metric": "learned selector regret vs exhaustive autotune (held-out), end-to-end GB/s",
+        "value": round(gbs(sel_t), 1), "unit": "GB/s", "n_gpus": 1, "steps": 10, "warmup": 2,
+        "ms_per_step": round(float(sel_t.mean()), 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.train} training + {args.test} held-out matrices of families F1-F4, "
+                               f"n in [{args.n_lo}, {args.n_hi}], 24 choices"},
+        "regret_network": stats(r_net), "regret_best_fixed": stats(r_fix),
+        "best_fixed_choice": selector.choice_name(fixed), "regret_plain_default": stats(r_plain),
+        "GBs_exhaustive": round(gbs(T[te].min(axis=1)), 1), "GBs_best_fixed": round(gbs(T[te, fixed]), 1),
+        "GBs_plain": round(gbs(T[te, 0]), 1),
+        "train_accuracy": round(float(np.mean(selector.predict(theta, norm(F[tr])) == labels[tr])), 3),
+        "test_accuracy": round(float(np.mean(chosen == labels[te])), 3),
+        "label_counts": {selector.choice_name(c): int(k) for c, k in zip(*np.unique(labels, return_counts=True))},
+        "loss_first_last": [round(curve[0], 4), round(curve[-1], 4)], "train_seconds": round(ttrain, 1),
+        "partition_seconds_mean": round(float(np.mean(tpart)), 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,9 +370,13 @@ def main():
     ap.add_argument("--tune", default="", help="wg,nnz_per_block[,blocks_per_tile,window_entries]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
-    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched"],
+    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched", "selector"],
                     help="spmv: repeated products on the n=10^6 matrix (default); precision: "
                          "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
+    ap.add_argument("--train", type=int, default=160, help="selector: training matrices")
+    ap.add_argument("--test", type=int, default=40, help="selector: held-out matrices")
+    ap.add_argument("--n-lo", type=int, default=5000, help="selector: smallest n")
+    ap.add_argument("--n-hi", type=int, default=40000, help="selector: largest n")
     ap.add_argument("--only-stream", action="store_true",
                     help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()
@@ -331,6 +396,8 @@ def main():
         return main_precision(args, torch, spx)
     if args.workload == "batched":
         return main_batched(args, torch, spx)
+    if args.workload == "selector":
+        return main_selector(args, torch, spx)
     if args.only_stream:
         nbytes = 1 << 30
         src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()

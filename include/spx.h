@@ -187,6 +187,15 @@ spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
 
 /* Rebuild the kernel schedule (row blocks, tiles, windows) of a plan without
  * repartitioning.  Not thread-safe against products running on the plan. */
+/* spx_plan_from_parts: the SB, DB or split form for a partition given by the
+ * caller instead of the library's partitioner (the leaves are the parts):
+ * SB parts[m] in 0..K-1 (row i in row slice parts[i]); DB parts[m] in 0..K
+ * (K = the row border R_B); split parts[nnz] in 0..K-1 (the part of each
+ * nonzero, in A's CSR order).  row_perm / col_perm as for spx_reorder_sb
+ * (may be NULL).  SPX_EINVAL for an index out of range. */
+spx_status spx_plan_from_parts(spx_mat A, int32_t form, int32_t K, const int32_t *parts,
+                               const spx_tune *tune, int32_t *row_perm, int32_t *col_perm,
+                               spx_plan *out);
 spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
 void spx_plan_destroy(spx_plan P);
 spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info);
@@ -315,6 +324,40 @@ spx_status spx_batch_info(spx_batch B, int32_t *nitems, int64_t *bytes, int32_t 
 spx_status spx_spmv_batched(int32_t count, const spx_plan *plans, const int32_t *nrhs,
                             const double *const *X, const int64_t *ldx, double *const *Y,
                             const int64_t *ldy, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Learned selector.  Not part of the paper, which picks the form by
+ * measurement: a 40 -> 64 -> 64 -> 24 perceptron (ReLU hidden layers,
+ * softmax over 24 choices of form, K and schedule) predicts the fastest
+ * choice from 40 matrix features.
+ *
+ * spx_features: out[40] (host) for a matrix: log1p(n), log1p(nnz), the
+ *   fractions of rows (out[2..17]) and of columns (out[18..33]) whose degree
+ *   falls in bin 0 (degree 0) or bin b = floor(log2 d) + 1 (capped at 15),
+ *   and, with u = |i/m - j/n| over the nonzeros: mean u, max u, the fraction
+ *   with u <= 1/64, the fraction inside the diagonal blocks of an 8 x 8 grid
+ *   (floor(8i/m) = floor(8j/n)), the mean over non-empty rows of (last
+ *   column - first column)/n, and std/mean of the row degrees.
+ * spx_mlp_forward: logits[B x 24] for features X[B x 40] (device, binary32,
+ *   row-major); theta[8344] holds W1 (64 x 40), b1, W2 (64 x 64), b2,
+ *   W3 (24 x 64), b3, each row-major, in that order.
+ * spx_mlp_loss_grad: mean softmax cross-entropy of labels[B] (device int32
+ *   in 0..23) into *loss and its gradient into grad[8344] (device).
+ * spx_mlp_adam: one Adam step (Kingma and Ba) on theta with moments m, v
+ *   (device, 8344 each), step number t >= 1.
+ * The network calls keep a per-thread device workspace sized for the
+ * largest B seen.
+ */
+#define SPX_NFEATURES 40
+#define SPX_NCHOICES 24
+#define SPX_MLP_PARAMS 8344
+
+spx_status spx_features(spx_mat A, float *out);
+spx_status spx_mlp_forward(const float *theta, const float *X, int32_t B, float *logits, void *stream);
+spx_status spx_mlp_loss_grad(const float *theta, const float *X, const int32_t *labels, int32_t B,
+                             float *loss, float *grad, void *stream);
+spx_status spx_mlp_adam(float *theta, const float *grad, float *m, float *v, int32_t t, float lr,
+                        float beta1, float beta2, float eps, void *stream);
 
 /* ----------------------------------------------------------------------
  * Inspection (host arrays, caller-allocated; any pointer may be NULL).

@@ -97,7 +97,15 @@ _SIGS = {
     "spx_batch_configure": ([_VP, _VP], _I32),
     "spx_batch_info": ([_VP, _VP, _VP, _VP], _I32),
     "spx_spmv_batched": ([_I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_features": ([_VP, _VP], _I32),
+    "spx_plan_from_parts": ([_VP, _I32, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_mlp_forward": ([_VP, _VP, _I32, _VP, _VP], _I32),
+    "spx_mlp_loss_grad": ([_VP, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
+    "spx_mlp_adam": ([_VP, _VP, _VP, _VP, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, _VP], _I32),
 }
+
+NFEATURES, NCHOICES, MLP_PARAMS = 40, 24, 8344
 
 
 class BatchConfig(ctypes.Structure):
@@ -568,3 +576,48 @@ def spmv_batched(plans, nrhs, X, Y, stream=None):
     xp, xl = _vec_table(X, ks)
     yp, yl = _vec_table(Y, ks)
     _check(lib().spx_spmv_batched(len(plans), arr, _hp(kk), xp, xl, yp, yl, _stream(stream)))
+
+
+# ---------------------------------------------------------------- selector network
+
+def features(A: Mat):
+    """The 40 selector features of a matrix (host computation, float32)."""
+    out = np.empty(NFEATURES, np.float32)
+    _check(lib().spx_features(A.handle, _hp(out)))
+    return out
+
+
+def mlp_forward(theta, X, logits, stream=None):
+    import torch
+    B = X.shape[0]
+    _check(lib().spx_mlp_forward(_dev(theta, torch.float32, MLP_PARAMS), _dev(X, torch.float32, B * NFEATURES),
+                                 int(B), _dev(logits, torch.float32, B * NCHOICES), _stream(stream)))
+
+
+def mlp_loss_grad(theta, X, labels, loss, grad, stream=None):
+    import torch
+    B = X.shape[0]
+    _check(lib().spx_mlp_loss_grad(_dev(theta, torch.float32, MLP_PARAMS), _dev(X, torch.float32, B * NFEATURES),
+                                   _dev(labels, torch.int32, B), int(B), _dev(loss, torch.float32, 1),
+                                   _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
+
+
+def mlp_adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+    _check(lib().spx_mlp_adam(_dev(theta, torch.float32, MLP_PARAMS), _dev(grad, torch.float32, MLP_PARAMS),
+                              _dev(m, torch.float32, MLP_PARAMS), _dev(v, torch.float32, MLP_PARAMS), int(t),
+                              float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def plan_from_parts(A: Mat, form, K, parts, tune=None):
+    """Plan of form "sb", "db" or "split" for a given partition (SB: parts[m]
+    in 0..K-1; DB: 0..K with K the row border; split: parts[nnz]).  Returns
+    (plan, row_perm, col_perm)."""
+    f = {"sb": FORM_SB, "db": FORM_DB, "split": FORM_SPLIT}[form]
+    pa = np.ascontiguousarray(parts, dtype=np.int32)
+    rp = np.empty(max(A.m, 1), np.int32)
+    cp = np.empty(max(A.n, 1), np.int32)
+    h = _VP()
+    _check(lib().spx_plan_from_parts(A.handle, f, int(K), _hp(pa), _tune_ptr(tune), _hp(rp), _hp(cp),
+                                     ctypes.byref(h)))
+    return Plan(h.value, A), rp[:A.m], cp[:A.n]

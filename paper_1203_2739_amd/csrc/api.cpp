@@ -279,6 +279,36 @@ spx_status spx_plan_plain(spx_mat A, const spx_tune *tune, spx_plan *out) {
     });
 }
 
+spx_status spx_plan_from_parts(spx_mat A, int32_t form, int32_t K, const int32_t *parts, const spx_tune *tune,
+                               int32_t *row_perm, int32_t *col_perm, spx_plan *out) {
+    return guarded([&] {
+        if (!A || !out || !parts) fail(SPX_EINVAL, "NULL argument");
+        if (K < 1) fail(SPX_EINVAL, "K must be >= 1");
+        if (form != SPX_FORM_SB && form != SPX_FORM_DB && form != SPX_FORM_SPLIT)
+            fail(SPX_EINVAL, "form must be SB, DB or split");
+        *out = nullptr;
+        const CsrHost &h = A->h;
+        const int64_t cnt = form == SPX_FORM_SPLIT ? h.nnz : h.m;
+        const int32_t hi = form == SPX_FORM_DB ? K : K - 1;
+        PartitionResult r;
+        r.part.assign(parts, parts + cnt);
+        r.leaf.resize(cnt);
+        for (int64_t i = 0; i < cnt; ++i) {
+            if (parts[i] < 0 || parts[i] > hi) fail(SPX_EINVAL, "part index out of range");
+            r.leaf[i] = parts[i] < K ? parts[i] : 0;
+        }
+        r.nleaves = K;
+        std::unique_ptr<spx_plan_s> P(new spx_plan_s());
+        P->K = K;
+        if (form == SPX_FORM_SPLIT) plan_from_split(*P, h, r);
+        else plan_from_rowparts(*P, h, r, form == SPX_FORM_DB);
+        apply_tune(*P, tune, 0);
+        upload_plan(*P, *A, nullptr);
+        write_outputs(*P, row_perm, col_perm);
+        *out = P.release();
+    });
+}
+
 spx_status spx_reorder_sb(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
                           int32_t *row_perm, int32_t *col_perm, int32_t *part_ptr,
                           const spx_tune *tune, spx_plan *out) {

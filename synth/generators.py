@@ -354,7 +354,7 @@ def gen_family(family: str, seed: int, n: int) -> CSR:
     mu = float(rng.uniform(5.0, 30.0))
     sub = int(rng.integers(1 << 62))
     if family == "F1":
-        A = gen_block_hidden(sub, n, mu, 1, 0.0)
+        A = gen_block_hidden(sub, n, mu, 1, 0.0, dmax=min(5000, n))
     elif family == "F2":
         beta = int(round(np.exp(rng.uniform(np.log(2), np.log(1000)))))
         frac = float(rng.uniform(0.0, 0.2))

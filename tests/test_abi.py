@@ -350,3 +350,34 @@ def test_schedule_rules(tune):
     for P in (spx.plan_plain(M, tune=tune), spx.reorder_db(M, 8, 2048 * 8, 2, tune=tune)[0],
               spx.split(M, 8, 2048 * 8, 2, tune=tune)[0]):
         check_schedule(P)
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_plan_from_parts_reproduces_partitioner_plans(orc, form):
+    """A plan built from the partition the library's partitioner produced
+    (no leaf refinement) equals the partitioner's plan bit for bit; a coarser
+    partition made by cutting the bisection tree is a valid form too."""
+    A = gen_c1()
+    M = spx.from_csr(A, device=False)
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P, rp, cp, pp = fn(M, 16, 0, 3)
+    a, _ = P.export_parts()
+    Q, rq, cq = spx.plan_from_parts(M, form, 16, a)
+    assert np.array_equal(rp, rq) and np.array_equal(cp, cq)
+    if form == "split":
+        ea, eb = P.export_split(), Q.export_split()
+        for k in ("slot_ptr", "slot_row", "colidx", "vals"):
+            assert np.array_equal(ea[k], eb[k])
+    else:
+        for u, v in zip(P.export_csr(), Q.export_csr()):
+            assert np.array_equal(u, v)
+    # K = 4 from the K = 16 tree: part p -> p >> 2 (the border stays the border)
+    coarse = np.where(a >= 16, 4, a >> 2) if form == "db" else a >> 2
+    R, rr, cr = spx.plan_from_parts(M, form, 4, coarse)
+    if form == "split":
+        check_split(orc, A, R, rr, cr, coarse, 4)
+    else:
+        c = orc.canonical_rowcol(A, coarse, coarse % 4 if form == "db" else coarse, 4, nleaves=4)
+        check_rowparts(orc, A, R, rr, cr, c["part_ptr"][: 4 + (2 if form == "db" else 1)], 4, form == "db")
+    with pytest.raises(spx.SpxError):
+        spx.plan_from_parts(M, form, 4, np.full(a.size, 7, np.int32))

@@ -61,3 +61,23 @@ def test_generator_dense_rows():
         for i in range(A.m):
             c = A.colidx[A.rowptr[i]:A.rowptr[i + 1]]
             assert np.all(np.diff(c) > 0) and (c.size == 0 or (c[0] >= 0 and c[-1] < A.n))
+
+
+@pytest.mark.parametrize("which", ["c1", "zipf", "family", "empty"])
+def test_features_match_oracle(orc, which):
+    """The library's selector features equal the oracle's: histograms and
+    counted fractions exactly, sums within binary32 rounding."""
+    from synth import gen_family, gen_uniform_zipf
+    if which == "c1":
+        A = gen_c1()
+    elif which == "zipf":
+        A = gen_uniform_zipf(5, 3000, 40000, 900)
+    elif which == "family":
+        A = gen_family("F3", 9, 5000)
+    else:
+        A = CSR(6, 4, np.array([0, 0, 2, 2, 3, 3, 3]), np.array([1, 3, 0], np.int32), np.ones(3))
+    M = spx.from_csr(A, device=False)
+    got = spx.features(M).astype(np.float64)
+    ref = orc.features(A)
+    assert np.array_equal(got[2:34], ref[2:34].astype(np.float32).astype(np.float64))
+    assert np.allclose(got, ref.astype(np.float32), rtol=2e-7, atol=1e-30)
