@@ -305,25 +305,34 @@ def main_selector(args, torch, spx):
     rng = np.random.default_rng(5555)
     N = args.train + args.test
     fams = ["F1", "F2", "F3", "F4"]
-    mats, T, tpart = [], [], []
-    t = time.time()
-    for i in range(N):
-        n = int(round(np.exp(rng.uniform(np.log(args.n_lo), np.log(args.n_hi)))))
-        A = gen_family(fams[i % 4], 9000 + i, n)
-        times, tp = selector.measure(A, seed=i)
-        mats.append(A)
-        T.append(times)
-        tpart.append(tp)
-        if i % 10 == 9:
-            log(f"measured {i + 1}/{N} ({time.time() - t:.0f} s)")
-    T = np.stack(T)
-    F = selector.feature_matrix(mats)
+    sizes = [int(round(np.exp(rng.uniform(np.log(args.n_lo), np.log(args.n_hi))))) for _ in range(N)]
+    if args.selector_data:
+        z = np.load(args.selector_data)
+        F, T, tpart, nbytes = z["F"], z["T"], z["tpart"], z["nbytes"]
+        assert F.shape[0] == N
+    else:
+        mats, T, tpart = [], [], []
+        t = time.time()
+        for i in range(N):
+            A = gen_family(fams[i % 4], 9000 + i, sizes[i])
+            times, tp = selector.measure(A, seed=i)
+            mats.append(A)
+            T.append(times)
+            tpart.append(tp)
+            if i % 10 == 9:
+                log(f"measured {i + 1}/{N} ({time.time() - t:.0f} s)")
+        T = np.stack(T)
+        F = selector.feature_matrix(mats)
+        nbytes = np.array([alg_bytes(A.m, A.n, A.nnz) for A in mats])
+        if args.save_selector_data:
+            np.savez(args.save_selector_data, F=F, T=T, tpart=np.array(tpart), nbytes=nbytes)
     tr, te = np.arange(args.train), np.arange(args.train, N)
     norm = selector.Normalizer(F[tr])
     labels = T.argmin(axis=1)
     t0 = time.time()
-    theta, curve = selector.train(norm(F[tr]), labels[tr], epochs=400, batch=32, lr=3e-3)
+    theta, epochs, vcurve = selector.fit(norm(F[tr]), T[tr])
     ttrain = time.time() - t0
+    curve = [v for _, v in vcurve]
     chosen = selector.predict(theta, norm(F[te]))
     fixed = selector.best_fixed(T[tr])
     r_net = selector.regret(T[te], chosen)
@@ -333,7 +342,7 @@ def main_selector(args, torch, spx):
     def stats(r):
         return {"mean": round(float(r.mean()), 4), "median": round(float(np.median(r)), 4),
                 "p90": round(float(np.quantile(r, 0.9)), 4)}
-    nb = np.array([alg_bytes(mats[i].m, mats[i].n, mats[i].nnz) for i in te])
+    nb = nbytes[te]
     gbs = lambda tt: float(np.mean(nb / (tt * 1e-3) / 1e9))  # noqa: E731
     sel_t = T[te, chosen]
     line = {
@@ -350,7 +359,8 @@ def main_selector(args, torch, spx):
         "train_accuracy": round(float(np.mean(selector.predict(theta, norm(F[tr])) == labels[tr])), 3),
         "test_accuracy": round(float(np.mean(chosen == labels[te])), 3),
         "label_counts": {selector.choice_name(c): int(k) for c, k in zip(*np.unique(labels, return_counts=True))},
-        "loss_first_last": [round(curve[0], 4), round(curve[-1], 4)], "train_seconds": round(ttrain, 1),
+        "epochs_chosen": epochs, "validation_regret_first_last": [round(curve[0], 4), round(curve[-1], 4)],
+        "train_seconds": round(ttrain, 1),
         "partition_seconds_mean": round(float(np.mean(tpart)), 2),
     }
     print(json.dumps(line), flush=True)
@@ -377,6 +387,9 @@ def main():
     ap.add_argument("--test", type=int, default=40, help="selector: held-out matrices")
     ap.add_argument("--n-lo", type=int, default=5000, help="selector: smallest n")
     ap.add_argument("--n-hi", type=int, default=40000, help="selector: largest n")
+    ap.add_argument("--selector-data", default="",
+                    help="selector: load features and timings from this .npz instead of measuring")
+    ap.add_argument("--save-selector-data", default="", help="selector: save features and timings here")
     ap.add_argument("--only-stream", action="store_true",
                     help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()

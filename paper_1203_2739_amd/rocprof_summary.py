@@ -2,6 +2,12 @@
 
   python -m paper_1203_2739_amd.rocprof_summary stats  <kernel_stats.csv>
   python -m paper_1203_2739_amd.rocprof_summary pmc    <counter_collection.csv> [name filter]
+  python -m paper_1203_2739_amd.rocprof_summary traffic <out dir> <form> <kernel filter> <nnz> <alg bytes>
+
+``traffic`` writes the summary that ``bench.py`` reads for roofline.traffic:
+<out dir> holds the five runs listed in the summary (prof, pmcf, pmcw, calf,
+calw); FETCH_SIZE and WRITE_SIZE of the SpMV kernel are scaled by what they
+read for a copy kernel of 1 GiB.
 
 ``stats`` lists kernels by total time with call count and mean duration.
 ``pmc`` lists, per kernel and grid size, the mean per-dispatch value of each
@@ -50,7 +56,63 @@ def pmc(path: str, filt: str = ""):
         print(f"{short(k)} grid={g}: " + ", ".join(parts))
 
 
+def _mean_by_kernel(path, filt):
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if filt in r["Kernel_Name"]:
+            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic(out, form, filt, nnz, alg):
+    copy_kib = (1 << 30) / 1024
+    calf = list(_mean_by_kernel(os.path.join(out, "calf", "pmc_counter_collection.csv"), "stream_copy").values())[0]
+    calw = list(_mean_by_kernel(os.path.join(out, "calw", "pmc_counter_collection.csv"), "stream_copy").values())[0]
+    ff, fw = copy_kib / calf, copy_kib / calw
+    fe = _mean_by_kernel(os.path.join(out, "pmcf", "pmc_counter_collection.csv"), filt)
+    wr = _mean_by_kernel(os.path.join(out, "pmcw", "pmc_counter_collection.csv"), filt)
+    (kname, f_kib), = fe.items()
+    w_kib = wr[kname]
+    st = [r for r in csv.DictReader(open(os.path.join(out, "prof", "run_kernel_stats.csv"))) if filt in r["Name"]][0]
+    fb, wb = f_kib * 1024 * ff, w_kib * 1024 * fw
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                        f"spmv_blocks_c2_{form}_traffic.txt")
+    with open(path, "w") as o:
+        o.write(f"""SpMV kernel spmv_blocks ({form} form) on the n=10^6 irregular matrix (nnz={nnz}), K=64,
+default schedule (128 threads, 4 nonzeros per thread).
+
+Commands (run from /tmp with TMPDIR=/tmp; R = repository root, OUT = output directory):
+  rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- python3 R/bench.py --forms {form} --steps 20 --warmup 3 --no-cpu-baseline --no-stream
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pmcf -o pmc -- python3 R/bench.py --forms {form} --steps 5 --warmup 1 --no-cpu-baseline --no-stream
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmcw -o pmc -- python3 R/bench.py --forms {form} --steps 5 --warmup 1 --no-cpu-baseline --no-stream
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/calf -o pmc -- python3 R/bench.py --only-stream
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/calw -o pmc -- python3 R/bench.py --only-stream
+  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg}
+
+Kernel trace (--stats): {st['Name'][:90]}
+  calls {st['Calls']}, mean {float(st['AverageNs']) / 1e3:.2f} us, min {float(st['MinNs']) / 1e3:.2f} us, max {float(st['MaxNs']) / 1e3:.2f} us
+
+Calibration on stream_copy_kernel of 1 GiB (reads 1 GiB, writes 1 GiB):
+  FETCH_SIZE {calf:.1f} KiB per dispatch -> factor {ff:.4f}
+  WRITE_SIZE {calw:.1f} KiB per dispatch -> factor {fw:.4f}
+
+Counters per dispatch of the SpMV kernel (mean over dispatches):
+  FETCH_SIZE {f_kib:.1f} KiB -> {fb / 1e6:.1f} MB calibrated
+  WRITE_SIZE {w_kib:.1f} KiB -> {wb / 1e6:.1f} MB calibrated
+  algorithmic bytes per product (12 nnz + 4 (m+1) + 8 n + 8 m): {alg / 1e6:.1f} MB
+  traffic / algorithmic = {(fb + wb) / alg:.2f}
+
+nnz: {nnz}
+kernel_source_sha256: {kernel_source_sha256()}
+traffic_bytes_per_launch: {int(fb + wb)}
+""")
+    print(open(path).read())
+
+
 if __name__ == "__main__":
+    if len(sys.argv) >= 7 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]))
+        sys.exit(0)
     if len(sys.argv) < 3 or sys.argv[1] not in ("stats", "pmc"):
         print(__doc__)
         sys.exit(2)

@@ -162,3 +162,38 @@ def best_fixed(times):
     """The single choice with the lowest mean regret on these matrices."""
     r = times / times.min(axis=1, keepdims=True) - 1.0
     return int(np.argmin(r.mean(axis=0)))
+
+
+def augment(F, T, tol=0.02):
+    """Training pairs for every choice within (1 + tol) of a matrix's fastest
+    time, so that near-ties teach the set of good choices rather than one
+    noisy argmin."""
+    Xs, ls = [], []
+    for i in range(T.shape[0]):
+        good = np.flatnonzero(T[i] <= (1.0 + tol) * T[i].min())
+        Xs.append(np.repeat(F[i:i + 1], good.size, axis=0))
+        ls.append(good)
+    return np.concatenate(Xs), np.concatenate(ls).astype(np.int32)
+
+
+def fit(Fn, T, epochs=400, check_every=20, val_frac=0.2, tol=0.02, lr=3e-3, batch=32, seed=0):
+    """Train on near-optimal labels with early stopping: a held-back fifth of
+    the training matrices picks the epoch count (lowest mean regret), then
+    the network is trained again on every training matrix for that many
+    epochs.  Returns (theta, chosen epochs, validation regret curve)."""
+    rng = np.random.default_rng(seed)
+    N = T.shape[0]
+    perm = rng.permutation(N)
+    nv = max(1, int(round(val_frac * N)))
+    va, tr = perm[:nv], perm[nv:]
+    X, lab = augment(Fn[tr], T[tr], tol)
+    best_ep, best_r, curve = check_every, np.inf, []
+    for ep in range(check_every, epochs + 1, check_every):
+        theta, _ = train(X, lab, epochs=ep, batch=batch, lr=lr, seed=seed)
+        r = float(regret(T[va], predict(theta, Fn[va])).mean())
+        curve.append((ep, r))
+        if r < best_r:
+            best_ep, best_r = ep, r
+    X, lab = augment(Fn, T, tol)
+    theta, _ = train(X, lab, epochs=best_ep, batch=batch, lr=lr, seed=seed)
+    return theta, best_ep, curve
