@@ -330,9 +330,8 @@ def main_selector(args, torch, spx):
     norm = selector.Normalizer(F[tr])
     labels = T.argmin(axis=1)
     t0 = time.time()
-    theta, epochs, vcurve = selector.fit(norm(F[tr]), T[tr])
+    theta, chosen_settings, tried = selector.fit(norm(F[tr]), T[tr])
     ttrain = time.time() - t0
-    curve = [v for _, v in vcurve]
     chosen = selector.predict(theta, norm(F[te]))
     fixed = selector.best_fixed(T[tr])
     r_net = selector.regret(T[te], chosen)
@@ -359,7 +358,8 @@ def main_selector(args, torch, spx):
         "train_accuracy": round(float(np.mean(selector.predict(theta, norm(F[tr])) == labels[tr])), 3),
         "test_accuracy": round(float(np.mean(chosen == labels[te])), 3),
         "label_counts": {selector.choice_name(c): int(k) for c, k in zip(*np.unique(labels, return_counts=True))},
-        "epochs_chosen": epochs, "validation_regret_first_last": [round(curve[0], 4), round(curve[-1], 4)],
+        "settings_chosen_on_validation": chosen_settings,
+        "validation_regret_best": min(t["val_regret"] for t in tried),
         "train_seconds": round(ttrain, 1),
         "partition_seconds_mean": round(float(np.mean(tpart)), 2),
     }

@@ -176,24 +176,28 @@ def augment(F, T, tol=0.02):
     return np.concatenate(Xs), np.concatenate(ls).astype(np.int32)
 
 
-def fit(Fn, T, epochs=400, check_every=20, val_frac=0.2, tol=0.02, lr=3e-3, batch=32, seed=0):
-    """Train on near-optimal labels with early stopping: a held-back fifth of
-    the training matrices picks the epoch count (lowest mean regret), then
-    the network is trained again on every training matrix for that many
-    epochs.  Returns (theta, chosen epochs, validation regret curve)."""
+def fit(Fn, T, epochs=300, check_every=20, val_frac=0.2, tols=(0.0, 0.02), lrs=(1e-3, 3e-3), batch=32, seed=0):
+    """Train on near-optimal labels with early stopping.  A held-back fifth of
+    the training matrices picks the label tolerance, the learning rate and
+    the epoch count (lowest mean regret); the network is then trained again
+    on every training matrix with that choice.  Returns (theta, settings,
+    validation regret of every setting tried)."""
     rng = np.random.default_rng(seed)
     N = T.shape[0]
     perm = rng.permutation(N)
     nv = max(1, int(round(val_frac * N)))
     va, tr = perm[:nv], perm[nv:]
-    X, lab = augment(Fn[tr], T[tr], tol)
-    best_ep, best_r, curve = check_every, np.inf, []
-    for ep in range(check_every, epochs + 1, check_every):
-        theta, _ = train(X, lab, epochs=ep, batch=batch, lr=lr, seed=seed)
-        r = float(regret(T[va], predict(theta, Fn[va])).mean())
-        curve.append((ep, r))
-        if r < best_r:
-            best_ep, best_r = ep, r
+    best, tried = None, []
+    for tol in tols:
+        X, lab = augment(Fn[tr], T[tr], tol)
+        for lr in lrs:
+            for ep in range(check_every, epochs + 1, check_every):
+                theta, _ = train(X, lab, epochs=ep, batch=batch, lr=lr, seed=seed)
+                r = float(regret(T[va], predict(theta, Fn[va])).mean())
+                tried.append({"tol": tol, "lr": lr, "epochs": ep, "val_regret": round(r, 5)})
+                if best is None or r < best[0]:
+                    best = (r, tol, lr, ep)
+    _, tol, lr, ep = best
     X, lab = augment(Fn, T, tol)
-    theta, _ = train(X, lab, epochs=best_ep, batch=batch, lr=lr, seed=seed)
-    return theta, best_ep, curve
+    theta, _ = train(X, lab, epochs=ep, batch=batch, lr=lr, seed=seed)
+    return theta, {"tol": tol, "lr": lr, "epochs": ep}, tried
