@@ -75,11 +75,14 @@ def traffic(out, form, filt, nnz, alg):
     w_kib = wr[kname]
     st = [r for r in csv.DictReader(open(os.path.join(out, "prof", "run_kernel_stats.csv"))) if filt in r["Name"]][0]
     fb, wb = f_kib * 1024 * ff, w_kib * 1024 * fw
+    # workgroup size and nonzeros per thread from the kernel's template arguments
+    targs = kname.split("<", 1)[1].split(",")
+    sched = f"{int(targs[0])}x{int(targs[1])}"
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
                         f"spmv_blocks_c2_{form}_traffic.txt")
     with open(path, "w") as o:
         o.write(f"""SpMV kernel spmv_blocks ({form} form) on the n=10^6 irregular matrix (nnz={nnz}), K=64,
-default schedule (128 threads, 4 nonzeros per thread).
+schedule picked by bench.py's autotuning ({sched}: threads per workgroup x nonzeros per thread).
 
 Commands (run from /tmp with TMPDIR=/tmp; R = repository root, OUT = output directory):
   rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- python3 R/bench.py --forms {form} --steps 20 --warmup 3 --no-cpu-baseline --no-stream
@@ -103,6 +106,7 @@ Counters per dispatch of the SpMV kernel (mean over dispatches):
   traffic / algorithmic = {(fb + wb) / alg:.2f}
 
 nnz: {nnz}
+schedule: {sched}
 kernel_source_sha256: {kernel_source_sha256()}
 traffic_bytes_per_launch: {int(fb + wb)}
 """)
