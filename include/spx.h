@@ -250,8 +250,9 @@ spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *str
  *   binary32 in a tree order, so against the exact sum of the rounded
  *   products a row of length m_i errs by at most about m_i 2^-24 times
  *   sum_j |a_ij x_j|.
- * spx_cg_ir: solves A x = b for a symmetric positive definite square plan
- *   (b, x device binary64 vectors in the plan's space).  x <- 0, r <- b; while
+ * spx_cg_ir: solves A x = b for a symmetric positive definite matrix in a
+ *   plain plan (SPX_EUNSUPPORTED for other forms, whose row and column
+ *   permutations differ); b, x are device binary64 vectors.  x <- 0, r <- b; while
  *   ||r|| / ||b|| > tol and fewer than max_outer refinements: run CG in the
  *   given precision on A_low d = r / ||r|| to relative residual inner_tol
  *   (at most max_inner iterations), x <- x + ||r|| d, r <- b - A x.

@@ -208,7 +208,9 @@ spx_status spx_cg_ir(spx_plan P, int32_t precision, const double *b, double *x, 
     spx_cg_stats st{};
     spx_status rc = guarded([&] {
         if (!P) fail(SPX_EINVAL, "NULL handle");
-        if (P->form == SPX_FORM_SPLIT) fail(SPX_EUNSUPPORTED, "the solve takes plain, SB or DB plans");
+        // CG needs a symmetric operator: SB/DB permute rows and columns
+        // differently, so only the plain form keeps A symmetric
+        if (P->form != SPX_FORM_PLAIN) fail(SPX_EUNSUPPORTED, "the solve takes a plain plan");
         if (P->m != P->n) fail(SPX_EINVAL, "the matrix must be square");
         if (precision != SPX_PREC_F64) check_lowp_plan(*P, precision, true);
         if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");

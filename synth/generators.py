@@ -286,7 +286,7 @@ def gen_c3_spd(seed: int = 3, n: int = 500_000, mean_deg: float = 20.0):
     strictly diagonally dominant with margin 1 (hence SPD, smallest eigenvalue
     at least 1 by Gershgorin).
     """
-    B = gen_block_hidden(seed, n, mean_deg, 64, 0.30)
+    B = gen_block_hidden(seed, n, mean_deg, 64, 0.30, dmax=min(5000, n), col_cap=min(5000, n))
     rows = np.repeat(np.arange(n, dtype=np.int64), B.row_degrees())
     cols = B.colidx.astype(np.int64)
     r = np.concatenate([rows, cols])

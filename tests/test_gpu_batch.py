@@ -137,3 +137,38 @@ def test_batch_errors():
         B.run()  # not bound
     with pytest.raises(spx.SpxError):
         B.replay()  # not captured
+
+
+@pytest.mark.parametrize("form", ["sb", "db"])
+def test_batch_of_reordered_plans(orc, form):
+    """Batched products of SB/DB plans run in each plan's reordered space."""
+    import torch
+    mats, ks = make_batch(3)
+    mats, ks = mats[:6], ks[:6]
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db}[form]
+    res = [fn(spx.from_csr(A), 4, 0, 1) for A in mats]
+    P = [r[0] for r in res]
+    X, Y, Xh = vectors(mats, ks, 1, 9)
+    Xr = []
+    for (p, rp, cp, _), x, k in zip(res, X, ks):
+        Xr.append(x[torch.from_numpy(cp.astype(np.int64)).cuda()].contiguous())
+    B = spx.Batch(P, ks)
+    B.bind(Xr, Y)
+    B.run()
+    for i, (A, x) in enumerate(zip(mats, Xh)):
+        rp = res[i][1]
+        y = host(Y[i]).reshape(A.m, -1)
+        ref = orc.spmm(A, x)[rp]
+        bound = orc.spmm(CSR(A.m, A.n, A.rowptr, A.colidx, np.abs(A.vals)), np.abs(x))[rp]
+        assert np.all(np.abs(y - ref) <= TOL * bound), f"{form} matrix {i}"
+
+
+def test_batch_rejects_strided_single_rhs():
+    import torch
+    A = gen_uniform_zipf(4, 200, 1000, 20)
+    P = plans_of([A])
+    B = spx.Batch(P, [1])
+    X = torch.zeros((A.n, 2), dtype=torch.float64, device="cuda")[:, :1]
+    Y = torch.zeros((A.m, 1), dtype=torch.float64, device="cuda")
+    with pytest.raises((spx.SpxError, ValueError)):
+        B.bind([X], [Y])

@@ -39,7 +39,7 @@ def plans(A, form):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("form", ["plain", "db"])
+@pytest.mark.parametrize("form", ["plain", "sb", "db"])
 @pytest.mark.parametrize("tune", [None, dict(wg_size=64), dict(wg_size=512), dict(reduce_iters=2, wg_size=256)])
 def test_lowp_integer_exact(orc, prec, form, tune):
     A0 = gen_uniform_zipf(51, 20_000, 300_000, 4000, diagonal=True)
@@ -114,3 +114,15 @@ def test_cg_ir_not_converged_reports():
     xd = torch.zeros_like(b)
     st = spx.cg_ir(P, "bf16", b, xd, tol=1e-14, inner_tol=1e-2, max_outer=1, max_inner=3)
     assert not st["converged"] and st["outer"] == 1 and st["inner"] <= 3
+
+
+def test_cg_ir_rejects_reordered_plans():
+    import torch
+    A = gen_c3_spd(seed=5, n=3_000)
+    M = spx.from_csr(A)
+    P = spx.reorder_sb(M, 4, 0, 0)[0]
+    spx.plan_add_lowp(P, "f32")
+    b = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(spx.SpxError) as e:
+        spx.cg_ir(P, "f32", b, torch.zeros_like(b))
+    assert e.value.code == -5
