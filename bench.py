@@ -300,7 +300,7 @@ def main_batched(args, torch, spx):
 def main_selector(args, torch, spx):
     """Learned selector: every one of the 24 choices timed on matrices of the
     four families (n log-uniform in [n_lo, n_hi]); the network is trained on
-    the training matrices with the library's kernels and judged on held-out
+    the training matrices with the library's kernels and evaluated on held-out
     ones by regret against exhaustive timing, beside the best fixed choice."""
     from paper_1203_2739_amd import selector
     from synth import gen_family

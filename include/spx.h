@@ -23,9 +23,11 @@
  *   - Streams are hipStream_t passed as void* (NULL = the null stream).
  *     Products are asynchronous on that stream; a launch failure is reported
  *     by the call that launches (SPX_EHIP).
- *   - Handles are immutable after creation apart from spx_plan_retune, so
- *     products with one plan may run concurrently on different streams as
- *     long as their output vectors differ.
+ *   - Handles are immutable after creation apart from spx_plan_retune,
+ *     spx_plan_add_lowp and the batch calls that change a batch.  A plan
+ *     owns a little scratch memory (partial sums and arrival counters of rows
+ *     too long for one block), so products of one plan must not overlap in
+ *     time: order them on one stream.  Different plans run independently.
  *   - Input and output vectors of one call must not overlap.
  */
 #ifndef SPX_H
@@ -185,10 +187,9 @@ spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
                      int32_t *row_perm, int32_t *col_perm, int32_t *nz_part,
                      const spx_tune *tune, spx_plan *out);
 
-/* Rebuild the kernel schedule (row blocks, tiles, windows) of a plan without
- * repartitioning.  Not thread-safe against products running on the plan. */
-/* spx_plan_from_parts: the SB, DB or split form for a partition given by the
- * caller instead of the library's partitioner (the leaves are the parts):
+/* spx_plan_from_parts: the SB form (Section 3.1, Eq. 1), DB form (Section
+ * 3.2, Eq. 5) or split (Section 4) for a partition given by the caller
+ * instead of the library's partitioner (the leaves are the parts):
  * SB parts[m] in 0..K-1 (row i in row slice parts[i]); DB parts[m] in 0..K
  * (K = the row border R_B); split parts[nnz] in 0..K-1 (the part of each
  * nonzero, in A's CSR order).  row_perm / col_perm as for spx_reorder_sb
@@ -196,6 +197,8 @@ spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
 spx_status spx_plan_from_parts(spx_mat A, int32_t form, int32_t K, const int32_t *parts,
                                const spx_tune *tune, int32_t *row_perm, int32_t *col_perm,
                                spx_plan *out);
+/* Rebuild the kernel schedule (row blocks, tiles, windows) of a plan without
+ * repartitioning.  Not thread-safe against products running on the plan. */
 spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
 void spx_plan_destroy(spx_plan P);
 spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info);
