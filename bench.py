@@ -309,25 +309,28 @@ def main_selector(args, torch, spx):
     fams = ["F1", "F2", "F3", "F4"]
     sizes = [int(round(np.exp(rng.uniform(np.log(args.n_lo), np.log(args.n_hi))))) for _ in range(N)]
     if args.selector_data:
-        z = np.load(args.selector_data)
-        F, T, tpart, nbytes = z["F"], z["T"], z["tpart"], z["nbytes"]
+        zs = [np.load(f) for f in args.selector_data.split(",")]
+        F, T, tpart, nbytes = (np.concatenate([z[k] for z in zs]) for k in ("F", "T", "tpart", "nbytes"))
         assert F.shape[0] == N
     else:
+        lo, hi = (int(v) for v in args.index_range.split(":")) if args.index_range else (0, N)
         mats, T, tpart = [], [], []
         t = time.time()
-        for i in range(N):
+        for i in range(lo, hi):
             A = gen_family(fams[i % 4], 9000 + i, sizes[i])
             times, tp = selector.measure(A, seed=i)
             mats.append(A)
             T.append(times)
             tpart.append(tp)
-            if i % 10 == 9:
+            if i % 5 == 4:
                 log(f"measured {i + 1}/{N} ({time.time() - t:.0f} s)")
         T = np.stack(T)
         F = selector.feature_matrix(mats)
         nbytes = np.array([alg_bytes(A.m, A.n, A.nnz) for A in mats])
         if args.save_selector_data:
             np.savez(args.save_selector_data, F=F, T=T, tpart=np.array(tpart), nbytes=nbytes)
+        if args.index_range:
+            return
     tr, te = np.arange(args.train), np.arange(args.train, N)
     norm = selector.Normalizer(F[tr])
     labels = T.argmin(axis=1)
@@ -393,6 +396,8 @@ def main():
     ap.add_argument("--selector-data", default="",
                     help="selector: load features and timings from this .npz instead of measuring")
     ap.add_argument("--save-selector-data", default="", help="selector: save features and timings here")
+    ap.add_argument("--index-range", default="",
+                    help="selector: measure only matrices a:b of the sequence (with --save-selector-data)")
     ap.add_argument("--only-stream", action="store_true",
                     help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()
