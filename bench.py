@@ -389,10 +389,10 @@ def main():
     ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched", "selector"],
                     help="spmv: repeated products on the n=10^6 matrix (default); precision: "
                          "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
-    ap.add_argument("--train", type=int, default=160, help="selector: training matrices")
-    ap.add_argument("--test", type=int, default=40, help="selector: held-out matrices")
-    ap.add_argument("--n-lo", type=int, default=5000, help="selector: smallest n")
-    ap.add_argument("--n-hi", type=int, default=40000, help="selector: largest n")
+    ap.add_argument("--train", type=int, default=60, help="selector: training matrices")
+    ap.add_argument("--test", type=int, default=30, help="selector: held-out matrices")
+    ap.add_argument("--n-lo", type=int, default=20000, help="selector: smallest n")
+    ap.add_argument("--n-hi", type=int, default=150000, help="selector: largest n")
     ap.add_argument("--selector-data", default="",
                     help="selector: load features and timings from this .npz instead of measuring")
     ap.add_argument("--save-selector-data", default="", help="selector: save features and timings here")

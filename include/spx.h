@@ -115,7 +115,8 @@ const char *spx_last_error(void);
 const char *spx_version(void);
 
 /* Number of host threads the partitioner may use (>= 1).  Results do not
- * depend on it. */
+ * depend on it.  With SPX_DEBUG set in the environment the partitioner
+ * prints the sizes and times of its coarsening levels to stderr. */
 spx_status spx_set_num_threads(int32_t nthreads);
 
 /* ----------------------------------------------------------------------
