@@ -81,3 +81,19 @@ def test_features_match_oracle(orc, which):
     ref = orc.features(A)
     assert np.array_equal(got[2:34], ref[2:34].astype(np.float32).astype(np.float64))
     assert np.allclose(got, ref.astype(np.float32), rtol=2e-7, atol=1e-30)
+
+
+def test_selector_host_logic():
+    """Regret, the best fixed choice, near-optimal label augmentation and the
+    hierarchical coarsening of a bisection tree, on hand-made timings."""
+    from paper_1203_2739_amd import selector
+    T = np.array([[1.0, 2.0, 1.01] + [9.0] * 21,
+                  [3.0, 1.5, 1.0] + [9.0] * 21])
+    assert np.allclose(selector.regret(T, np.array([0, 0])), [0.0, 2.0])
+    assert selector.best_fixed(T) == 2          # regrets 0.01 and 0: the best mean
+    X, lab = selector.augment(np.eye(2, 40, dtype=np.float32), T, tol=0.02)
+    assert sorted(lab[:2]) == [0, 2] and list(lab[2:]) == [2]
+    assert len(selector.CHOICES) == 24 and selector.choice_name(23) == "split256"
+    # part p of a K = 256 tree lies in part p >> (8 - log2 K) of the tree cut at K
+    parts = np.arange(256)
+    assert np.array_equal(np.unique(parts >> 5), np.arange(8))
