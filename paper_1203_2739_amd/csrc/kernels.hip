@@ -141,8 +141,13 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
     const int tid = threadIdx.x;
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
     const int32_t zb = d.z & ~3;
-    const int32_t nr = d.y - d.x;
+    const int32_t nr = d.y - d.x;  // at most WG (schedule)
     const int32_t G = (d.w - zb + 3) >> 2;
+    // row pointers first, so that their latency overlaps the data loads;
+    // nr + 1 <= WG + 1 of them: one per thread, the last one by thread 0
+    // when the block has WG rows
+    const int32_t rp0 = a.slot_ptr[d.x + min(tid, nr)];
+    const int32_t rp1 = (nr == WG && tid == 0) ? a.slot_ptr[d.x + WG] : 0;
 #pragma unroll
     for (int u = 0; u < NPT / 4; ++u) {
         const int gi = tid + u * WG;
@@ -156,7 +161,8 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
             sp[3] = vv.v[3] * xval<WMAX>(a.x, swin, cc.w, wlo, wlen);
         }
     }
-    for (int i = tid; i <= nr; i += WG) sptr[i] = a.slot_ptr[d.x + i] - zb;
+    if (tid <= nr) sptr[tid] = rp0 - zb;
+    if (nr == WG && tid == 0) sptr[WG] = rp1 - zb;
     __syncthreads();
     // lanes per row: the largest power of two <= WG / nr, at most 64
     const int q = WG / nr;
