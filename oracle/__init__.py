@@ -220,7 +220,8 @@ def canonical_rowcol(A, r2p, r2leaf, K, nleaves=None):
     by one leaf goes with that leaf, a column touched by several leaves of one
     part goes after that part's leaf columns, and every other column (touched
     by several parts, or by none) goes to the column border C_B at the end;
-    ties by original index.
+    inside each of these classes columns go by decreasing number of nonzeros
+    (in A), then by original index.
 
     Returns dict(row_perm, col_perm, part_ptr[K+2], col_part_ptr[K+2],
     leaf_row_ptr, leaf_col_lo, leaf_col_hi, row_leaf, col_class).
@@ -243,7 +244,8 @@ def canonical_rowcol(A, r2p, r2leaf, K, nleaves=None):
     ck_leaf = np.where(nleaf_c == 1, leaf_c, 0)
     ck_sub = np.where(ck_part == K, 0, ck_sub)
     ck_leaf = np.where(ck_part == K, 0, ck_leaf)
-    col_perm = np.lexsort((np.arange(n), ck_leaf, ck_sub, ck_part))
+    cdeg = np.bincount(cols, minlength=n)
+    col_perm = np.lexsort((np.arange(n), -cdeg, ck_leaf, ck_sub, ck_part))
     part_ptr = np.searchsorted(grp[row_perm], np.arange(K + 2), side="left")
     part_ptr[K + 1] = m
     col_part_ptr = np.searchsorted(ck_part[col_perm], np.arange(K + 2), side="left")
@@ -271,7 +273,8 @@ def canonical_split(A, nz_part, nz_leaf, K):
     Rows whose nonzeros all lie in one leaf come first, grouped by leaf; rows
     spread over several leaves follow, grouped by part (rows spread over
     several parts last); empty rows close the order.  Columns follow the same
-    rule as :func:`canonical_rowcol`.  Ties by original index.
+    rule as :func:`canonical_rowcol` (classes, then decreasing number of
+    nonzeros); remaining ties by original index.
 
     Returns dict(row_perm, col_perm, row_shared_begin, row_empty_begin,
     col_part_ptr[K+2]).
@@ -295,7 +298,8 @@ def canonical_split(A, nz_part, nz_leaf, K):
     ck_part = np.where(np_c == 1, p_c, K)
     ck_sub = np.where((ck_part < K) & (nl_c > 1), 1, 0)
     ck_leaf = np.where((ck_part < K) & (nl_c == 1), l_c, 0)
-    col_perm = np.lexsort((np.arange(n), ck_leaf, ck_sub, ck_part))
+    cdeg = np.bincount(cols, minlength=n)
+    col_perm = np.lexsort((np.arange(n), -cdeg, ck_leaf, ck_sub, ck_part))
     col_part_ptr = np.searchsorted(ck_part[col_perm], np.arange(K + 2), side="left")
     col_part_ptr[K + 1] = n
     return dict(row_perm=row_perm.astype(np.int64), col_perm=col_perm.astype(np.int64),

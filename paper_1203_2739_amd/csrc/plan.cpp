@@ -56,9 +56,13 @@ struct ColClass {
     std::vector<uint8_t> multi_leaf, multi_part;
 };
 
-std::vector<int32_t> column_order(int32_t n, int32_t K, int32_t nleaves,
+// Columns by class (leaf, part-shared, border), inside a class by decreasing
+// number of nonzeros, then by original index: the x entries gathered most
+// often share cache lines, so the hot part of x stays in L2.
+std::vector<int32_t> column_order(const CsrHost &A, int32_t K, int32_t nleaves,
                                   const std::vector<int32_t> &leaf_lo_of_part,
                                   const ColClass &cc, int32_t &border_begin) {
+    const int32_t n = A.n;
     std::vector<int32_t> bucket(n);
     for (int32_t j = 0; j < n; ++j) {
         int32_t p = cc.first_part[j];
@@ -66,7 +70,17 @@ std::vector<int32_t> column_order(int32_t n, int32_t K, int32_t nleaves,
         else if (cc.multi_leaf[j]) bucket[j] = leaf_lo_of_part[p + 1] + p;
         else bucket[j] = cc.first_leaf[j] + p;
     }
-    std::vector<int32_t> order = counting_order(bucket, nleaves + K + 1);
+    std::vector<int64_t> deg((size_t)n, 0);
+    for (int64_t q = 0; q < A.nnz; ++q) deg[A.colidx[q]]++;
+    std::vector<int32_t> by_deg(n);
+    std::iota(by_deg.begin(), by_deg.end(), 0);
+    std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+    // stable counting sort of the degree order by class
+    std::vector<int64_t> off((size_t)nleaves + K + 2, 0);
+    for (int32_t j = 0; j < n; ++j) off[bucket[j] + 1]++;
+    for (int32_t b = 0; b <= nleaves + K; ++b) off[b + 1] += off[b];
+    std::vector<int32_t> order(n);
+    for (int32_t j : by_deg) order[off[bucket[j]]++] = j;
     border_begin = n;
     for (int32_t t = 0; t < n; ++t)
         if (bucket[order[t]] == nleaves + K) { border_begin = t; break; }
@@ -178,7 +192,7 @@ void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &
         }
     }
     int32_t cb = n;
-    P.col_perm = column_order(n, K, L, leaf_lo_of_part, cc, cb);
+    P.col_perm = column_order(A, K, L, leaf_lo_of_part, cc, cb);
     P.col_border_begin = cb;
     std::vector<int32_t> inv_col(n);
     for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;
@@ -275,7 +289,7 @@ void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) 
         }
     }
     int32_t cb = n;
-    P.col_perm = column_order(n, K, L, leaf_lo_of_part, cc, cb);
+    P.col_perm = column_order(A, K, L, leaf_lo_of_part, cc, cb);
     P.col_border_begin = cb;
     std::vector<int32_t> inv_col(n), inv_row(m);
     for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;

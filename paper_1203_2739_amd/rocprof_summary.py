@@ -21,13 +21,18 @@ import os
 import sys
 from collections import defaultdict
 
-SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+SRCS = [os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f)
+        for f in ("kernels.hip", "plan.cpp", "sched_limits.h")]
 
 
 def kernel_source_sha256() -> str:
-    """Hash of the kernel source: counter figures are valid for this source only."""
-    with open(SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """Hash of the kernel source and of the plan builder that lays out what it
+    reads: counter figures are valid for these sources only."""
+    h = hashlib.sha256()
+    for path in SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def short(name: str, width: int = 70) -> str:

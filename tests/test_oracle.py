@@ -257,24 +257,26 @@ def test_bounds_hand_worked():
 def test_canonical_rowcol_hand_worked(orc):
     """Same 4x5 matrix, SB with parts {row0,row1}, {row2,row3}, one leaf
     per part.  Rows keep their order.  Columns: c1 only in part 0 -> C_1;
-    c3, c4 only in part 1 -> C_2; c0, c2 in both -> C_B.  So the new column
-    order is c1 | c3 c4 | c0 c2."""
+    c3, c4 only in part 1 -> C_2; c0, c2 in both -> C_B.  Inside a class by
+    decreasing column count (c0, c1, c2, c4 have 2 nonzeros, c3 has 1), then
+    by index.  So the new column order is c1 | c4 c3 | c0 c2."""
     D = np.zeros((4, 5))
     for i, cs in enumerate([[0, 1], [1, 2], [2, 3, 4], [0, 4]]):
         D[i, cs] = 1.0
     A = dense_to_csr(D)
     c = orc.canonical_rowcol(A, [0, 0, 1, 1], [0, 0, 1, 1], 2)
     assert list(c["row_perm"]) == [0, 1, 2, 3]
-    assert list(c["col_perm"]) == [1, 3, 4, 0, 2]
+    assert list(c["col_perm"]) == [1, 4, 3, 0, 2]
     assert list(c["part_ptr"]) == [0, 2, 4, 4]
     assert list(c["col_part_ptr"]) == [0, 1, 3, 5]
     orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
     assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2) == []
     # DB with row 3 in the border: c4 is then touched by part 1 only
-    # among part rows, c0 only by part 0 -> c0 c1 | c3 c4 | c2
+    # among part rows, c0 only by part 0 -> c0 c1 | c4 c3 | c2 (counts over
+    # all of A, border rows included)
     c = orc.canonical_rowcol(A, [0, 0, 1, 2], [0, 0, 1, 0], 2)
     assert list(c["row_perm"]) == [0, 1, 2, 3]
-    assert list(c["col_perm"]) == [0, 1, 3, 4, 2]
+    assert list(c["col_perm"]) == [0, 1, 4, 3, 2]
     orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
     assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2, db=True) == []
     assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2, db=False) != []
