@@ -30,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-AUTOTUNE = [dict(wg_size=128), dict(wg_size=64), dict(wg_size=256), dict(wg_size=512)]
+AUTOTUNE = [dict(wg_size=128), dict(wg_size=64), dict(wg_size=256), dict(wg_size=512),
+            dict(wg_size=128, nnz_per_block=1024), dict(wg_size=256, nnz_per_block=2048)]
 
 
 def log(*a):
@@ -466,7 +467,7 @@ def main():
         prep = time.time() - t
         if tune is None and not args.no_autotune:
             # schedule autotuning (as OSKI tunes its kernel): a few products
-            # per workgroup size, then the fastest is kept for the timed run
+            # per workgroup shape, then the fastest is kept for the timed run
             best_t, best_ms = None, None
             for cand in AUTOTUNE:
                 spx.plan_retune(P, cand)

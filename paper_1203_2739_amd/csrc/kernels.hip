@@ -572,6 +572,7 @@ struct Table<double, double> {
         {128, 4, 0, launch_variant<128, 4, 0, double, double>},
         {128, 8, 0, launch_variant<128, 8, 0, double, double>},
         {256, 4, 0, launch_variant<256, 4, 0, double, double>},
+        {256, 8, 0, launch_variant<256, 8, 0, double, double>},
         {512, 4, 0, launch_variant<512, 4, 0, double, double>},
         {128, 4, 4096, launch_variant<128, 4, 4096, double, double>},
         {128, 4, 8192, launch_variant<128, 4, 8192, double, double>},
