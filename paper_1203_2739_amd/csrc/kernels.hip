@@ -591,6 +591,7 @@ struct LowTable {
         {128, 4, 0, launch_variant<128, 4, 0, V, float>},
         {128, 8, 0, launch_variant<128, 8, 0, V, float>},
         {256, 4, 0, launch_variant<256, 4, 0, V, float>},
+        {256, 8, 0, launch_variant<256, 8, 0, V, float>},
         {512, 4, 0, launch_variant<512, 4, 0, V, float>},
     };
 };
