@@ -381,3 +381,34 @@ def test_plan_from_parts_reproduces_partitioner_plans(orc, form):
         check_rowparts(orc, A, R, rr, cr, c["part_ptr"][: 4 + (2 if form == "db" else 1)], 4, form == "db")
     with pytest.raises(spx.SpxError):
         spx.plan_from_parts(M, form, 4, np.full(a.size, 7, np.int32))
+
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=30, deadline=None)
+@given(st.integers(1, 40), st.integers(1, 40), st.integers(1, 6), st.sampled_from(["sb", "db", "split"]),
+       st.integers(0, 2**31))
+def test_plans_from_random_partitions(orc, m, n, K, form, seed):
+    """Any partition, including empty parts, rows, columns and heavy ties in
+    column counts, gives the oracle's canonical orders bit for bit and a
+    valid schedule."""
+    rng = np.random.default_rng(seed)
+    D = rng.random((m, n)) < rng.uniform(0.05, 0.6)
+    r, c = np.nonzero(D)
+    rp = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=m), out=rp[1:])
+    A = CSR(m, n, rp, c.astype(np.int32), rng.uniform(-1, 1, r.size))
+    M = spx.from_csr(A, device=False)
+    if form == "split":
+        parts = rng.integers(0, K, A.nnz).astype(np.int32)
+    else:
+        parts = rng.integers(0, K + (1 if form == "db" else 0), m).astype(np.int32)
+    P, rq, cq = spx.plan_from_parts(M, form, K, parts)
+    if form == "split":
+        check_split(orc, A, P, rq, cq, parts, K)
+    else:
+        leaf = np.where(parts < K, parts, 0)
+        cc = orc.canonical_rowcol(A, parts, leaf, K, nleaves=K)
+        check_rowparts(orc, A, P, rq, cq, cc["part_ptr"][: K + (2 if form == "db" else 1)], K, form == "db")
+    check_schedule(P)

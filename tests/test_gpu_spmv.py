@@ -284,3 +284,25 @@ def test_split_deterministic_and_retune(orc):
             outs.append(host(yh))
         for o in outs:
             assert_close_rowwise(o, ref, den, f"split retune {t}")
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("K", [3, 17])
+def test_products_from_random_partitions(orc, form, K):
+    """Products of plans built from arbitrary partitions (random parts, so
+    borders are large and parts uneven) match the oracle."""
+    A = gen_c1()
+    rng = np.random.default_rng(K)
+    if form == "split":
+        parts = rng.integers(0, K, A.nnz).astype(np.int32)
+    else:
+        parts = rng.integers(0, K + (1 if form == "db" else 0), A.m).astype(np.int32)
+    M = spx.from_csr(A)
+    P, rp, cp = spx.plan_from_parts(M, form, K, parts)
+    x = gen_vectors(112, A.n)[0]
+    xd = dev(x)
+    xh = torch.empty_like(xd)
+    spx.permute_x(P, xd, xh)
+    yh = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
+    spx.spmv(P, xh, yh)
+    assert_close_rowwise(host(yh), orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], f"{form} K={K}")
