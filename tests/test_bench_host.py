@@ -1,0 +1,66 @@
+"""Host-side pieces of the measurement: the algorithmic byte count, the
+lookup of committed counter summaries, the refusal of several GPUs, and the
+rocprofv3 summary tool on small hand-made CSV files."""
+import csv
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_alg_bytes():
+    import bench
+    # 12 bytes per nonzero, 4 per row pointer, x read once and y written once
+    assert bench.alg_bytes(3, 5, 7) == 12 * 7 + 4 * 4 + 8 * 5 + 8 * 3
+
+
+def test_traffic_lookup_checks_source_schedule_and_matrix():
+    import bench
+    from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256
+    path = os.path.join(ROOT, "profiles", "spmv_blocks_c2_db_traffic.txt")
+    kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line and
+              line.split(": ", 1)[0] in ("nnz", "schedule", "kernel_source_sha256", "traffic_bytes_per_launch"))
+    nnz, sched = int(kv["nnz"]), kv["schedule"].strip()
+    got = bench.measured_traffic("db", nnz, sched)
+    if kv["kernel_source_sha256"].strip() == kernel_source_sha256():
+        assert got == int(kv["traffic_bytes_per_launch"])
+    else:
+        assert got is None
+    assert bench.measured_traffic("db", nnz + 1, sched) is None
+    assert bench.measured_traffic("db", nnz, "1x1") is None
+    assert bench.measured_traffic("no_such_form", nnz, sched) is None
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def write_csv(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0].keys()))
+        w.writeheader()
+        w.writerows(rows)
+
+
+def test_rocprof_summary_tool(tmp_path, capsys):
+    from paper_1203_2739_amd import rocprof_summary as rs
+    stats = tmp_path / "k.csv"
+    write_csv(stats, [{"Name": "kernA", "Calls": 2, "TotalDurationNs": 3000, "AverageNs": 1500, "Percentage": 75,
+                       "MinNs": 1000, "MaxNs": 2000},
+                      {"Name": "kernB", "Calls": 1, "TotalDurationNs": 1000, "AverageNs": 1000, "Percentage": 25,
+                       "MinNs": 1000, "MaxNs": 1000}])
+    rs.stats(str(stats))
+    out = capsys.readouterr().out.splitlines()
+    assert out[1].startswith("kernA") and "1.50" in out[1]
+    pmc = tmp_path / "p.csv"
+    write_csv(pmc, [{"Kernel_Name": "kernA", "Grid_Size": 64, "Counter_Name": "FETCH_SIZE", "Counter_Value": 10,
+                     "Dispatch_Id": 1},
+                    {"Kernel_Name": "kernA", "Grid_Size": 64, "Counter_Name": "FETCH_SIZE", "Counter_Value": 30,
+                     "Dispatch_Id": 2}])
+    rs.pmc(str(pmc), "kern")
+    assert "FETCH_SIZE=20.0 (n=2)" in capsys.readouterr().out
