@@ -173,7 +173,8 @@ void spx_mat_destroy(spx_mat A);
  *     nz_part[nnz] (split): part of every nonzero, in A's CSR order.
  *   Orders (the paper leaves them open): rows by part, then leaf, then
  *   original index, R_B last; columns of one leaf, then columns shared by
- *   leaves of one part, then the column border C_B, ties by original index.
+ *   leaves of one part, then the column border C_B; inside each of these
+ *   classes by decreasing number of nonzeros, then by original index.
  *   For the split, rows touched by a single leaf come first (by leaf), rows
  *   shared by leaves follow, empty rows last.
  */
