@@ -19,6 +19,7 @@ Effective bytes per product (each array once):
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -113,11 +114,23 @@ def cpu_baseline(A, xs_host, budget_s=15.0, max_products=100):
             "gflops": round(2 * A.nnz / dt / 1e9, 3)}
 
 
-def measured_traffic(form, nnz, sched):
+def plan_sha256(rp, cp, parts, nleaves):
+    """Hash of the layout a reordered plan hands the kernel: the row and
+    column permutations, the part boundaries (SB, DB) or the part of each
+    nonzero (split), and the number of leaves."""
+    h = hashlib.sha256()
+    for a in (rp, cp, parts):
+        h.update(np.ascontiguousarray(a, dtype=np.int64).tobytes())
+    h.update(str(int(nleaves)).encode())
+    return h.hexdigest()
+
+
+def measured_traffic(form, nnz, sched, plan):
     """HBM bytes per launch of the SpMV kernel of this form from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
-    known size), or None when the summary is missing, is for another matrix
-    or schedule, or the kernel source changed after the counters were taken."""
+    known size), or None when the summary is missing, is for another matrix,
+    schedule or plan layout, or the kernel source changed after the counters
+    were taken."""
     from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256
     path = os.path.join(ROOT, "profiles", f"spmv_blocks_c2_{form}_traffic.txt")
     if not os.path.exists(path):
@@ -128,7 +141,7 @@ def measured_traffic(form, nnz, sched):
         if len(parts) == 2 and parts[0].endswith(":"):
             kv[parts[0][:-1]] = parts[1]
     if (kv.get("kernel_source_sha256") != kernel_source_sha256() or int(kv.get("nnz", -1)) != nnz
-            or kv.get("schedule") != sched):
+            or kv.get("schedule") != sched or kv.get("plan_sha256") != plan):
         return None
     return int(kv["traffic_bytes_per_launch"])
 
@@ -470,7 +483,7 @@ def main():
         else:
             fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
             wb = args.window_bytes if form == "split" else 0
-            P, rp, cp, _ = fn(M, args.K, wb, args.seed, tune=tune)
+            P, rp, cp, parts = fn(M, args.K, wb, args.seed, tune=tune)
             xf = torch.empty_like(xs)
             for i in range(npool):
                 spx.permute_x(P, xs[i], xf[i])
@@ -486,6 +499,7 @@ def main():
                     best_t, best_ms = cand, ms
             spx.plan_retune(P, best_t)
         inf = P.info()
+        plan_key = "identity" if form == "plain" else plan_sha256(rp, cp, parts, inf["nleaves"])
         total_ms, kern_ms = time_form(spx, torch, P, form, xf, y, args.warmup, args.steps)
         r = {"ms_per_step": round(total_ms, 5), "kernel_ms": round(kern_ms, 5),
              "GBs": round(nb / (total_ms * 1e-3) / 1e9, 1),
@@ -496,7 +510,8 @@ def main():
              "sum_lambda_col": inf["sum_lambda_col"], "sum_lambda_row": inf["sum_lambda_row"],
              "border_row_nnz": inf["border_row_nnz"], "bytes_matrix": inf["bytes_matrix"],
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
-                      inf["window_entries"]]}
+                      inf["window_entries"]],
+             "plan_sha256": plan_key}
         results[form] = r
         log(form, json.dumps(r))
         if form != "plain":
@@ -531,7 +546,8 @@ def main():
         out["speedup_vs_plain"] = round(results["plain"]["ms_per_step"] / hb["ms_per_step"], 3)
     out["roofline"] = {"bound": "hbm", "achieved": hb["kernel_GBs"], "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": round(hb["kernel_GBs"] / PEAK_HBM_GBS, 4),
-                       "traffic": measured_traffic(best, A.nnz, f"{hb['tune'][0]}x{hb['tune'][1] // hb['tune'][0]}"),
+                       "traffic": measured_traffic(best, A.nnz, f"{hb['tune'][0]}x{hb['tune'][1] // hb['tune'][0]}",
+                                                  hb["plan_sha256"]),
                        "kernel": f"spmv_blocks ({best})",
                        "alg_bytes_per_launch": nb}
     if not args.no_stream:

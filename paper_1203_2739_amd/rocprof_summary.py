@@ -2,12 +2,14 @@
 
   python -m paper_1203_2739_amd.rocprof_summary stats  <kernel_stats.csv>
   python -m paper_1203_2739_amd.rocprof_summary pmc    <counter_collection.csv> [name filter]
-  python -m paper_1203_2739_amd.rocprof_summary traffic <out dir> <form> <kernel filter> <nnz> <alg bytes>
+  python -m paper_1203_2739_amd.rocprof_summary traffic <out dir> <form> <kernel filter> <nnz> <alg bytes> <plan sha256>
 
 ``traffic`` writes the summary that ``bench.py`` reads for roofline.traffic:
 <out dir> holds the five runs listed in the summary (prof, pmcf, pmcw, calf,
 calw); FETCH_SIZE and WRITE_SIZE of the SpMV kernel are scaled by what they
-read for a copy kernel of 1 GiB.
+read for a copy kernel of 1 GiB.  <plan sha256> is the ``plan_sha256`` that
+the profiled bench runs print for the form: the figures hold for that plan
+layout only.
 
 ``stats`` lists kernels by total time with call count and mean duration.
 ``pmc`` lists, per kernel and grid size, the mean per-dispatch value of each
@@ -69,7 +71,7 @@ def _mean_by_kernel(path, filt):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(out, form, filt, nnz, alg):
+def traffic(out, form, filt, nnz, alg, plan):
     copy_kib = (1 << 30) / 1024
     calf = list(_mean_by_kernel(os.path.join(out, "calf", "pmc_counter_collection.csv"), "stream_copy").values())[0]
     calw = list(_mean_by_kernel(os.path.join(out, "calw", "pmc_counter_collection.csv"), "stream_copy").values())[0]
@@ -95,7 +97,7 @@ Commands (run from /tmp with TMPDIR=/tmp; R = repository root, OUT = output dire
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmcw -o pmc -- python3 R/bench.py --forms {form} --steps 5 --warmup 1 --no-cpu-baseline --no-stream
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/calf -o pmc -- python3 R/bench.py --only-stream
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/calw -o pmc -- python3 R/bench.py --only-stream
-  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg}
+  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg} {plan}
 
 Kernel trace (--stats): {st['Name'][:90]}
   calls {st['Calls']}, mean {float(st['AverageNs']) / 1e3:.2f} us, min {float(st['MinNs']) / 1e3:.2f} us, max {float(st['MaxNs']) / 1e3:.2f} us
@@ -113,14 +115,15 @@ Counters per dispatch of the SpMV kernel (mean over dispatches):
 nnz: {nnz}
 schedule: {sched}
 kernel_source_sha256: {kernel_source_sha256()}
+plan_sha256: {plan}
 traffic_bytes_per_launch: {int(fb + wb)}
 """)
     print(open(path).read())
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 7 and sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]))
+    if len(sys.argv) >= 8 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]), sys.argv[7])
         sys.exit(0)
     if len(sys.argv) < 3 or sys.argv[1] not in ("stats", "pmc"):
         print(__doc__)

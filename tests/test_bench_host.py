@@ -6,6 +6,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -17,21 +19,35 @@ def test_alg_bytes():
     assert bench.alg_bytes(3, 5, 7) == 12 * 7 + 4 * 4 + 8 * 5 + 8 * 3
 
 
-def test_traffic_lookup_checks_source_schedule_and_matrix():
+def test_traffic_lookup_checks_source_schedule_matrix_and_plan():
     import bench
     from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256
-    path = os.path.join(ROOT, "profiles", "spmv_blocks_c2_db_traffic.txt")
-    kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line and
-              line.split(": ", 1)[0] in ("nnz", "schedule", "kernel_source_sha256", "traffic_bytes_per_launch"))
-    nnz, sched = int(kv["nnz"]), kv["schedule"].strip()
-    got = bench.measured_traffic("db", nnz, sched)
-    if kv["kernel_source_sha256"].strip() == kernel_source_sha256():
-        assert got == int(kv["traffic_bytes_per_launch"])
-    else:
-        assert got is None
-    assert bench.measured_traffic("db", nnz + 1, sched) is None
-    assert bench.measured_traffic("db", nnz, "1x1") is None
-    assert bench.measured_traffic("no_such_form", nnz, sched) is None
+    keys = ("nnz", "schedule", "kernel_source_sha256", "plan_sha256", "traffic_bytes_per_launch")
+    for form in ("db", "split"):
+        path = os.path.join(ROOT, "profiles", f"spmv_blocks_c2_{form}_traffic.txt")
+        kv = {k: v.strip() for k, v in (line.split(": ", 1) for line in open(path).read().splitlines()
+                                        if ": " in line and line.split(": ", 1)[0] in keys)}
+        nnz, sched, plan = int(kv["nnz"]), kv["schedule"], kv.get("plan_sha256", "")
+        got = bench.measured_traffic(form, nnz, sched, plan)
+        if kv["kernel_source_sha256"] == kernel_source_sha256() and plan:
+            assert got == int(kv["traffic_bytes_per_launch"])
+        else:
+            assert got is None
+        assert bench.measured_traffic(form, nnz + 1, sched, plan) is None
+        assert bench.measured_traffic(form, nnz, "1x1", plan) is None
+        assert bench.measured_traffic(form, nnz, sched, "0" * 64) is None
+    assert bench.measured_traffic("no_such_form", 1, "1x1", "0" * 64) is None
+
+
+def test_plan_hash_sees_every_part_of_the_layout():
+    import bench
+    rp, cp, parts = np.arange(5), np.array([2, 0, 1]), np.array([0, 2, 5])
+    h = bench.plan_sha256(rp, cp, parts, 1)
+    assert h == bench.plan_sha256(rp.astype(np.int32), cp, parts, 1)
+    assert h != bench.plan_sha256(rp[::-1], cp, parts, 1)
+    assert h != bench.plan_sha256(rp, cp[[1, 0, 2]], parts, 1)
+    assert h != bench.plan_sha256(rp, cp, np.array([0, 3, 5]), 1)
+    assert h != bench.plan_sha256(rp, cp, parts, 2)
 
 
 def test_bench_refuses_several_gpus():
