@@ -792,7 +792,7 @@ static int64_t uncut_rows(const Hypergraph &H, std::vector<uint8_t> &side, doubl
     return cut;
 }
 
-// ------------------------------------------------------------ RB driver
+// ------------------------------------------------- recursive bisection
 
 namespace {
 
