@@ -4,10 +4,11 @@ The n = 10^6 irregular matrix (20 M nonzeros) as plain CSR, DB form at
 K = 64 and split at K = 64 with 128 KB leaves, run through the same calls as
 the benchmark (permute_x, split_prepare_y, accumulate = 2) under every
 schedule its autotuner may pick; the n = 5*10^5 SPD matrix in binary64,
-binary32 and bfloat16 under the same schedules, and one refined CG solve.
-The oracle computes sampled outputs row by row: random rows, the longest
-rows and, for the split, rows whose nonzeros lie in several parts.
-Permutations are checked bit for bit.
+binary32 and bfloat16 under the same schedules, and one refined CG solve;
+every 8th member of the 256-matrix uneven batch with the benchmark's
+schedule search, graph capture and replays.  The oracle computes sampled
+outputs row by row: random rows, the longest rows and, for the split, rows
+whose nonzeros lie in several parts.  Permutations are checked bit for bit.
 """
 import numpy as np
 import pytest
@@ -155,3 +156,49 @@ def test_full_size_refined_cg(orc, spd):
     assert st["converged"] and res <= 2e-10, (st, res)
     # lambda_min(A) >= 1 (diagonal dominance with margin 1): ||x - 1|| <= ||b - A x||
     assert np.linalg.norm(xh - 1.0) <= np.linalg.norm(b - orc.spmv(A, xh)) * (1 + 1e-6)
+
+
+@pytest.mark.timeout(300)
+def test_full_size_batch_members(orc):
+    """Every 8th member of the 256-matrix uneven batch, at full size, with the
+    benchmark's schedule search, graph capture and replays (eager work and
+    waits in between); 512 sampled rows of every member and right-hand side
+    against the oracle."""
+    from synth import gen_c4_one
+    mats, ks = [], []
+    for j in range(0, 256, 8):
+        A, k = gen_c4_one(j)
+        mats.append(A)
+        ks.append(k)
+    assert set(ks) == {1, 8, 32}
+    plans = [spx.plan_plain(spx.from_csr(A)) for A in mats]
+    rng = np.random.default_rng(4444)
+    X, Y, Xh = [], [], []
+    for A, k in zip(mats, ks):
+        x = rng.uniform(-1, 1, (A.n, k))
+        Xh.append(x)
+        X.append(dev(x[:, 0].copy()) if k == 1 else dev(x))
+        Y.append(torch.empty((A.m,) if k == 1 else (A.m, k), dtype=torch.float64, device="cuda"))
+    B = spx.Batch(plans, ks)
+    B.bind(X, Y)
+    B.autotune(reps=3)
+    B.capture()
+    samples = []
+    for i, A in enumerate(mats):
+        rows = np.unique(np.concatenate([np.random.default_rng(i).choice(A.m, min(512, A.m), replace=False),
+                                         np.argsort(np.diff(A.rowptr), kind="stable")[-8:]]))
+        sub = rows_of(A, rows)
+        absub = CSR(sub.m, sub.n, sub.rowptr, sub.colidx, np.abs(sub.vals))
+        samples.append((rows, orc.spmm(sub, Xh[i]), orc.spmm(absub, np.abs(Xh[i]))))
+    other = plans[0]
+    xo = torch.ones(mats[0].n, dtype=torch.float64, device="cuda")
+    yo = torch.empty(mats[0].m, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        for y in Y:
+            y.fill_(np.nan)
+        spx.spmv(other, xo, yo)  # eager work between replays
+        torch.cuda.synchronize()
+        B.replay()
+        for i, (rows, ref, bound) in enumerate(samples):
+            y = host(Y[i]).reshape(mats[i].m, -1)[rows]
+            assert np.all(np.abs(y - ref) <= 1e-12 * bound), f"replay {rep} member {8 * i} k={ks[i]}"
