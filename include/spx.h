@@ -155,8 +155,11 @@ void spx_mat_destroy(spx_mat A);
  *   Theorem 2.
  * spx_split: nonzero-disjoint splitting into K parts (Section 4.1) by
  *   recursive bisection of the row-column-net hypergraph with the
- *   connectivity metric on row and column nets, minimizing the bound of
- *   Corollary 4.  Products then run as y <- y + A^k x.
+ *   connectivity metric on row and column nets.  Corollary 4 weighs a cut
+ *   row and a cut column alike; here a row net costs 32 and a column net 1,
+ *   because a row shared by one more part costs a binary64 atomic add on the
+ *   GPU while a shared column costs an x read that usually hits L2.
+ *   Products then run as y <- y + A^k x.
  *
  *   window_bytes > 0 continues the bisection inside each part until every
  *   leaf's x subvector (split: x and y subvectors) fits window_bytes; leaves
