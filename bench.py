@@ -88,6 +88,34 @@ def time_form(spx, torch, P, form, xs, y, warmup, steps):
     return total, kern
 
 
+FLUSH_BYTES = 512 << 20  # twice the 256 MB Infinity Cache, 128 times an XCD's L2
+
+
+def time_cold(spx, torch, P, form, xs, y, steps=20):
+    """Mean ms of one product (the split: zeroing of its shared rows plus the
+    product) right after a read of FLUSH_BYTES that evicts the L2s and the
+    Infinity Cache, so that the matrix, x and y come from HBM."""
+    stream = torch.cuda.current_stream()
+    flush = torch.zeros(FLUSH_BYTES // 8, dtype=torch.float64, device="cuda")
+    sink = torch.empty(spx.stream_sink_len(FLUSH_BYTES), dtype=torch.float64, device="cuda")
+    ev = []
+    for s in range(steps):
+        spx.stream_read(flush, FLUSH_BYTES, sink)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        if form == "split":
+            spx.split_prepare_y(P, y)
+            spx.spmv_split(P, xs[s % xs.shape[0]], y, accumulate=2)
+        else:
+            spx.spmv(P, xs[s % xs.shape[0]], y)
+        b.record(stream)
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    del flush, sink
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
 def stream_ceiling(spx, torch, nbytes=1 << 30, reps=20):
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
     sink = torch.empty(spx.stream_sink_len(nbytes), dtype=torch.float64, device="cuda")
@@ -418,6 +446,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
+    ap.add_argument("--cold", action="store_true",
+                    help="also time 20 products per form, each after a 512 MB read that empties the caches")
     ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched", "selector"],
                     help="spmv: repeated products on the n=10^6 matrix (default); precision: "
                          "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
@@ -520,6 +550,10 @@ def main():
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
                       inf["window_entries"]],
              "plan_sha256": plan_key}
+        if args.cold:
+            cold_ms = time_cold(spx, torch, P, form, xf, y)
+            r["cold_ms_per_step"] = round(cold_ms, 5)
+            r["cold_GBs"] = round(nb / (cold_ms * 1e-3) / 1e9, 1)
         results[form] = r
         log(form, json.dumps(r))
         if form != "plain":
@@ -560,6 +594,7 @@ def main():
                        "alg_bytes_per_launch": nb}
     if not args.no_stream:
         out["stream_read_GBs"] = round(stream_ceiling(spx, torch), 1)
+        out["pct_of_stream_ceiling"] = round(100 * hb["GBs"] / out["stream_read_GBs"], 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, xs_host)
     print(json.dumps(out), flush=True)
