@@ -135,6 +135,8 @@ spx_status spx_csr_upload(int32_t m, int32_t n, int64_t nnz, const int32_t *rowp
                           spx_mat *out);
 spx_status spx_csr_create_host(int32_t m, int32_t n, int64_t nnz, const int32_t *rowptr,
                                const int32_t *colidx, const double *vals, spx_mat *out);
+/* spx_mat_destroy frees the matrix (the upload has completed by the time
+ * spx_csr_upload returns); plans built from it stay valid. */
 void spx_mat_destroy(spx_mat A);
 
 /* ----------------------------------------------------------------------
@@ -205,6 +207,9 @@ spx_status spx_plan_from_parts(spx_mat A, int32_t form, int32_t K, const int32_t
 /* Rebuild the kernel schedule (row blocks, tiles, windows) of a plan without
  * repartitioning.  Not thread-safe against products running on the plan. */
 spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
+/* spx_plan_destroy frees the plan's host and device memory.  Work queued
+ * on a stream that reads the plan (products, permutations, batches built on
+ * it) must have completed first: synchronize that stream before destroying. */
 void spx_plan_destroy(spx_plan P);
 spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info);
 
@@ -321,6 +326,8 @@ typedef struct spx_batch_config_s {
 } spx_batch_config;
 
 spx_status spx_batch_create(int32_t count, const spx_plan *plans, const int32_t *nrhs, spx_batch *out);
+/* spx_batch_destroy frees the batch, its work queue and its captured graph;
+ * as for plans, runs and replays queued on a stream must have completed. */
 void spx_batch_destroy(spx_batch B);
 spx_status spx_batch_bind(spx_batch B, const double *const *X, const int64_t *ldx, double *const *Y,
                           const int64_t *ldy);
