@@ -293,6 +293,34 @@ def test_hidden_block_diagonal_found(orc, form):
         assert inf["sum_lambda_row"] == A.m
 
 
+def bridged_blocks(b, w):
+    """Two dense b x w blocks on disjoint columns and one row over all 2w
+    columns that joins them."""
+    rows = [np.arange(w)] * b + [np.arange(w, 2 * w)] * b + [np.arange(2 * w)]
+    rp = np.zeros(len(rows) + 1, np.int64)
+    np.cumsum([r.size for r in rows], out=rp[1:])
+    ci = np.concatenate(rows).astype(np.int32)
+    return CSR(len(rows), 2 * w, rp, ci, np.random.default_rng(w).uniform(-1, 1, ci.size))
+
+
+@pytest.mark.parametrize("w,row_cut", [(8, False), (16, False), (48, True), (64, True)])
+def test_split_weighs_a_shared_row_32_columns(orc, w, row_cut):
+    """Bisecting the bridged blocks either cuts the joining row (one row net
+    shared by both parts) or keeps it whole and cuts the w columns it reaches
+    in the other block.  Row nets weigh 32 column nets in the split's model,
+    so the row is kept whole while w < 32 and cut when w > 32; the oracle
+    counts the connectivities of the parts returned."""
+    A = bridged_blocks(100, w)
+    for seed in range(3):
+        M = spx.from_csr(A, device=False)
+        P, rp, cp, part = spx.split(M, 2, 0, seed)
+        lr, lc = orc.lambda_split(A, part, 2)
+        assert int(lr[-1]) == (2 if row_cut else 1)
+        assert lr.sum() == A.m + (1 if row_cut else 0)
+        assert lc.sum() == 2 * w + (0 if row_cut else w)
+        assert P.info()["sum_lambda_row"] == lr.sum()
+
+
 def test_empty_and_degenerate(orc):
     # matrix with empty rows and columns, one long row, rectangular
     rng = np.random.default_rng(0)
