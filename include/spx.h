@@ -358,7 +358,9 @@ spx_status spx_spmv_batched(int32_t count, const spx_plan *plans, const int32_t 
  *   row-major); theta[8344] holds W1 (64 x 40), b1, W2 (64 x 64), b2,
  *   W3 (24 x 64), b3, each row-major, in that order.
  * spx_mlp_loss_grad: mean softmax cross-entropy of labels[B] (device int32
- *   in 0..23) into *loss and its gradient into grad[8344] (device).
+ *   in 0..23) into *loss and its gradient into grad[8344] (device).  The
+ *   labels are device memory and are not checked on the host: a label
+ *   outside 0..23 reads no memory and turns the loss and the gradient NaN.
  * spx_mlp_adam: one Adam step (Kingma and Ba) on theta with moments m, v
  *   (device, 8344 each), step number t >= 1.
  * The network calls keep a per-thread device workspace sized for the

@@ -496,23 +496,40 @@ def cg_ir(P: Plan, precision, b, x, tol=1e-10, inner_tol=1e-3, max_outer=50, max
 
 # ---------------------------------------------------------------- batched products
 
-def _vec_table(tensors, ks):
-    """Pointer and leading-dimension tables of row-major (rows, k) tensors."""
+def _vec_table(tensors, ks, rows):
+    """Pointer and leading-dimension tables of row-major (rows, k) tensors.
+
+    ``rows[i]`` is the number of rows the i-th matrix reads (X: its n) or
+    writes (Y: its m); a tensor with fewer rows, or with rows closer than k
+    entries apart, is refused before any pointer reaches the library, which
+    cannot check raw device pointers."""
     import torch
     n = len(tensors)
+    if len(ks) != n or len(rows) != n:
+        raise ValueError("one tensor per matrix is needed")
     ptrs = (ctypes.c_void_p * max(n, 1))()
     lds = (ctypes.c_int64 * max(n, 1))()
-    for i, (t, k) in enumerate(zip(tensors, ks)):
-        if not t.is_cuda or t.dtype != torch.float64:
+    for i, (t, k, r) in enumerate(zip(tensors, ks, rows)):
+        if t.dtype != torch.float64:
             raise ValueError("batched vectors must be float64 device tensors")
         if t.dim() == 1:
             if k != 1 or t.stride(0) != 1:
                 raise ValueError("a 1-D tensor needs k = 1 and unit stride")
+            if t.shape[0] < r:
+                raise ValueError(f"tensor {i} has {t.shape[0]} entries, the matrix needs {r}")
             lds[i] = 1
-        else:
+        elif t.dim() == 2:
             if t.shape[1] != k or t.stride(1) != 1:
                 raise ValueError("expected a (rows, k) tensor with unit column stride")
-            lds[i] = t.stride(0)
+            if t.shape[0] < r:
+                raise ValueError(f"tensor {i} has {t.shape[0]} rows, the matrix needs {r}")
+            if t.shape[0] > 1 and t.stride(0) < k:
+                raise ValueError(f"tensor {i}: rows overlap (leading dimension {t.stride(0)} < k = {k})")
+            lds[i] = t.stride(0) if t.shape[0] > 1 else k
+        else:
+            raise ValueError("batched vectors must be 1-D or 2-D tensors")
+        if not t.is_cuda:
+            raise ValueError("batched vectors must be float64 device tensors")
         ptrs[i] = t.data_ptr()
     return ptrs, lds
 
@@ -538,8 +555,8 @@ class Batch:
             pass
 
     def bind(self, X, Y):
-        xp, xl = _vec_table(X, self.nrhs)
-        yp, yl = _vec_table(Y, self.nrhs)
+        xp, xl = _vec_table(X, self.nrhs, [p.mat_dims[1] for p in self.plans])
+        yp, yl = _vec_table(Y, self.nrhs, [p.mat_dims[0] for p in self.plans])
         _check(lib().spx_batch_bind(self._h, xp, xl, yp, yl))
         self._bound = (list(X), list(Y))
 
@@ -573,8 +590,8 @@ def spmv_batched(plans, nrhs, X, Y, stream=None):
     arr = (ctypes.c_void_p * max(len(plans), 1))(*[p.handle.value for p in plans])
     ks = [int(k) for k in nrhs]
     kk = np.ascontiguousarray(ks, dtype=np.int32)
-    xp, xl = _vec_table(X, ks)
-    yp, yl = _vec_table(Y, ks)
+    xp, xl = _vec_table(X, ks, [p.mat_dims[1] for p in plans])
+    yp, yl = _vec_table(Y, ks, [p.mat_dims[0] for p in plans])
     _check(lib().spx_spmv_batched(len(plans), arr, _hp(kk), xp, xl, yp, yl, _stream(stream)))
 
 
@@ -597,6 +614,12 @@ def mlp_forward(theta, X, logits, stream=None):
 def mlp_loss_grad(theta, X, labels, loss, grad, stream=None):
     import torch
     B = X.shape[0]
+    if labels.numel() < B:
+        raise ValueError(f"{labels.numel()} labels for {B} samples")
+    if B > 0:
+        lo, hi = int(labels[:B].min()), int(labels[:B].max())
+        if lo < 0 or hi >= NCHOICES:
+            raise ValueError(f"labels must lie in [0, {NCHOICES}), got [{lo}, {hi}]")
     _check(lib().spx_mlp_loss_grad(_dev(theta, torch.float32, MLP_PARAMS), _dev(X, torch.float32, B * NFEATURES),
                                    _dev(labels, torch.int32, B), int(B), _dev(loss, torch.float32, 1),
                                    _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))

@@ -43,8 +43,12 @@ __global__ __launch_bounds__(kWG) void softmax_ce_kernel(const float *__restrict
         float se = 0.0f;
         for (int c = 0; c < C; ++c) se += expf(zr[c] - mx);
         const int y = labels[bi];
-        acc += logf(se) - (zr[y] - mx);
-        for (int c = 0; c < C; ++c) d[(int64_t)bi * C + c] = (expf(zr[c] - mx) / se - (c == y ? 1.0f : 0.0f)) / (float)B;
+        // a label outside 0..C-1 reads nothing: its loss and gradient are NaN
+        const bool ok = y >= 0 && y < C;
+        acc += ok ? logf(se) - (zr[y] - mx) : __builtin_nanf("");
+        for (int c = 0; c < C; ++c)
+            d[(int64_t)bi * C + c] =
+                ok ? (expf(zr[c] - mx) / se - (c == y ? 1.0f : 0.0f)) / (float)B : __builtin_nanf("");
     }
     part[threadIdx.x] = acc;
     __syncthreads();

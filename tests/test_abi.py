@@ -440,3 +440,40 @@ def test_plans_from_random_partitions(orc, m, n, K, form, seed):
         cc = orc.canonical_rowcol(A, parts, leaf, K, nleaves=K)
         check_rowparts(orc, A, P, rq, cq, cc["part_ptr"][: K + (2 if form == "db" else 1)], K, form == "db")
     check_schedule(P)
+
+
+def test_batched_tensor_tables_refuse_short_or_overlapping_tensors():
+    """The batched entry points take raw device pointers, which the library
+    cannot bound: the binding refuses X with fewer than n rows, Y with fewer
+    than m rows and rows closer than k entries apart before any launch."""
+    import torch
+    ok1 = torch.zeros(10, dtype=torch.float64)
+    ok8 = torch.zeros(10, 8, dtype=torch.float64)
+    cases = [
+        ([torch.zeros(9, dtype=torch.float64)], [1], [10], "entries"),
+        ([torch.zeros(9, 8, dtype=torch.float64)], [8], [10], "rows"),
+        ([torch.zeros(10, 16, dtype=torch.float64)[:, :8].as_strided((10, 8), (4, 1))], [8], [10], "overlap"),
+        ([ok8], [4], [10], "unit column stride"),
+        ([ok1], [8], [10], "k = 1"),
+        ([ok1, ok1], [1], [10, 10], "one tensor per matrix"),
+        ([torch.zeros(10, dtype=torch.float32)], [1], [10], "float64"),
+    ]
+    for tensors, ks, rows, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            spx._vec_table(tensors, ks, rows)
+    # shapes that fit reach the device check (no GPU here)
+    with pytest.raises(ValueError, match="device"):
+        spx._vec_table([ok8, ok1], [8, 1], [10, 10])
+
+
+def test_selector_labels_checked_before_launch():
+    import torch
+    th = torch.zeros(spx.MLP_PARAMS, dtype=torch.float32)
+    X = torch.zeros(4, spx.NFEATURES, dtype=torch.float32)
+    loss = torch.zeros(1, dtype=torch.float32)
+    g = torch.zeros(spx.MLP_PARAMS, dtype=torch.float32)
+    for bad in ([0, 1, 24, 2], [0, -1, 3, 2]):
+        with pytest.raises(ValueError, match="labels"):
+            spx.mlp_loss_grad(th, X, torch.tensor(bad, dtype=torch.int32), loss, g)
+    with pytest.raises(ValueError, match="labels"):
+        spx.mlp_loss_grad(th, X, torch.tensor([0, 1], dtype=torch.int32), loss, g)

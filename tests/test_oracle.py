@@ -345,6 +345,58 @@ def test_canonical_split_and_gcsr(orc):
     assert np.all(inv[nleaf == 0] >= re_)
 
 
+def _split_example():
+    """8 x 8 matrix split into K = 2 parts with two leaves each (part 0:
+    leaves 0, 1; part 1: leaves 2, 3).  Entries (row, column, leaf):"""
+    entries = [(0, 0, 2), (0, 3, 2), (0, 6, 2), (0, 7, 2),      # row 0: leaf 2 only
+               (1, 2, 3), (1, 3, 2), (1, 6, 3), (1, 7, 3),      # row 1: leaves 2, 3 (part 1)
+               (3, 0, 0), (3, 4, 3),                            # row 3: parts 0 and 1
+               (4, 1, 0), (4, 5, 0),                            # row 4: leaf 0 only
+               (5, 2, 1), (5, 5, 0),                            # row 5: leaves 0, 1 (part 0)
+               (6, 4, 1),                                       # row 6: leaf 1 only
+               (7, 4, 3), (7, 7, 3)]                            # row 7: leaf 3 only; row 2 empty
+    D = np.zeros((8, 8))
+    leafD = np.full((8, 8), -1)
+    for r, c, l in entries:
+        D[r, c] = 10 * r + c + 1
+        leafD[r, c] = l
+    A = dense_to_csr(D)
+    rows = np.repeat(np.arange(8), np.diff(A.rowptr))
+    leaf = leafD[rows, A.colidx]
+    return A, leaf // 2, leaf
+
+
+def test_canonical_split_hand_worked(orc):
+    """Exact orders of the split (Section 4; the order inside the forms is
+    the reading that groups rows and columns by class, then by decreasing
+    column count, then by index), worked by hand on _split_example.
+
+    Rows: single-leaf rows by leaf (r4 | r6 | r0 | r7), not by index; then
+    rows shared by leaves of one part, by part (r5 of part 0 before r1 of
+    part 1), before the row shared by both parts (r3); the empty row r2 last.
+
+    Columns: c1, c5 only in leaf 0 (counts 1, 2); c3 only in leaf 2; c6, c7
+    in leaves 2 and 3 of part 1 (counts 2, 3); c0, c2, c4 in both parts
+    (counts 2, 2, 3).  Classes: leaf 0 | leaf 2 | part-1 shared | border,
+    each by decreasing count then index: c5 c1 | c3 | c7 c6 | c4 c0 c2."""
+    A, part, leaf = _split_example()
+    c = orc.canonical_split(A, part, leaf, 2)
+    assert list(c["row_perm"]) == [4, 6, 0, 7, 5, 1, 3, 2]
+    assert c["row_shared_begin"] == 4 and c["row_empty_begin"] == 7
+    assert list(c["col_perm"]) == [5, 1, 3, 7, 6, 4, 0, 2]
+    assert list(c["col_part_ptr"]) == [0, 2, 5, 8]
+    # per-leaf GCSR in the new coordinates (rows: r4->0, r6->1, r0->2,
+    # r7->3, r5->4, r1->5, r3->6, r2->7; columns: c5->0, c1->1, c3->2,
+    # c7->3, c6->4, c4->5, c0->6, c2->7), each leaf's non-empty rows
+    # ascending, entries by new column
+    g = orc.split_gcsr(A, leaf, 4, c["row_perm"], c["col_perm"])
+    assert list(g["leaf_slot_ptr"]) == [0, 3, 5, 7, 10]
+    assert list(g["slot_row"]) == [0, 4, 6, 1, 4, 2, 5, 3, 5, 6]
+    assert list(g["slot_ptr"]) == [0, 2, 3, 4, 5, 6, 10, 11, 13, 16, 17]
+    assert list(g["colidx"]) == [0, 1, 0, 6, 5, 7, 2, 3, 4, 6, 2, 3, 5, 3, 4, 7, 5]
+    assert list(g["vals"]) == [46, 42, 56, 31, 65, 53, 4, 8, 7, 1, 14, 78, 75, 18, 17, 13, 35]
+
+
 # ------------------------------------------------------------ precision
 
 def test_quantization_vs_libraries(orc):
@@ -371,6 +423,36 @@ def test_lowp_spmv_integer_exact(orc):
     y16 = orc.spmv_lowp(A, None, x.astype(np.float32), vals16=orc.f32_to_bf16(f))
     ref = (D.astype(np.int64) @ x).astype(np.float32)
     assert np.array_equal(y32, ref) and np.array_equal(y16, ref)
+
+
+def test_lowp_spmv_rounds_in_binary32_left_to_right(orc):
+    """The precision mode accumulates in binary32 (the reading for values
+    stored in binary32 or bfloat16), product by product in storage order.
+
+    Row 0: values (1, 2^24, -2^24) on x = 1.  In binary32, 1 + 2^24 is a tie
+    that rounds to the even 2^24, and the row then cancels to 0; a binary64
+    accumulator, or any order that adds 2^24 - 2^24 first, gives 1.
+    Row 1: (1 + 2^-23)^2 = 1 + 2^-22 + 2^-46 is rounded to 1 + 2^-22 as a
+    binary32 product, so subtracting 1 + 2^-22 leaves 0; a product kept in
+    binary64 leaves 2^-46."""
+    e = 2.0 ** -23
+    D = np.array([[1.0, 2.0 ** 24, -(2.0 ** 24), 0.0],
+                  [0.0, 0.0, 0.0, 0.0],
+                  [0.0, 0.0, 0.0, 0.0]])
+    A = dense_to_csr(D)
+    x = np.ones(4, dtype=np.float32)
+    y = orc.spmv_lowp(A, orc.to_f32(A.vals), x)
+    assert y[0] == 0.0
+    # bfloat16 holds 1 and 2^24 exactly: the same cancellation
+    y16 = orc.spmv_lowp(A, None, x, vals16=orc.f32_to_bf16(orc.to_f32(A.vals)))
+    assert y16[0] == 0.0
+    # row 1 of a second matrix: a * x with a = x = 1 + 2^-23, then -(1 + 2^-22) * 1
+    B = CSR(1, 2, np.array([0, 2]), np.array([0, 1], dtype=np.int32),
+            np.array([1.0 + e, -(1.0 + 2 * e)]))
+    xb = np.array([1.0 + e, 1.0], dtype=np.float32)
+    yb = orc.spmv_lowp(B, orc.to_f32(B.vals), xb)
+    assert yb[0] == 0.0
+    assert (1.0 + e) * (1.0 + e) - (1.0 + 2 * e) == 2.0 ** -46  # what binary64 would keep
 
 
 def spd(rng, n, density=0.2):
