@@ -31,8 +31,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-AUTOTUNE = [dict(wg_size=128), dict(wg_size=64), dict(wg_size=256), dict(wg_size=512),
-            dict(wg_size=128, nnz_per_block=1024), dict(wg_size=256, nnz_per_block=2048)]
 
 
 def log(*a):
@@ -50,7 +48,7 @@ def time_form(spx, torch, P, form, xs, y, warmup, steps):
     alone is timed in a second pass with an event pair around every launch,
     so the per-launch events do not weigh on the first figure."""
     stream = torch.cuda.current_stream()
-    split = form == "split"
+    split = form.startswith("split")
 
     def product(i):
         if split:
@@ -104,7 +102,7 @@ def time_cold(spx, torch, P, form, xs, y, steps=20):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        if form == "split":
+        if form.startswith("split"):
             spx.split_prepare_y(P, y)
             spx.spmv_split(P, xs[s % xs.shape[0]], y, accumulate=2)
         else:
@@ -134,20 +132,91 @@ def stream_ceiling(spx, torch, nbytes=1 << 30, reps=20):
     return nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(A, xs_host, budget_s=15.0, max_products=100):
-    """The oracle's CSR product on the host, on a bounded number of products."""
+CPU_SO = os.path.join(ROOT, "bench_cpu.so")
+
+
+def build_cpu_leg():
+    """Compile the multi-core host product (bench_cpu.c) with OpenMP."""
+    tmp = CPU_SO + ".tmp"
+    import subprocess
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
+                           os.path.join(ROOT, "bench_cpu.c")])
+    os.replace(tmp, CPU_SO)
+    return CPU_SO
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, xs_host, budget_s=12.0, max_products=100):
+    """Host CSR products on the full matrix, on a bounded number of products.
+
+    The oracle's C product runs single-threaded (its index arrays are
+    converted to the int64 it reads once, outside the timed loop); the
+    OpenMP product of bench_cpu.c runs on every host core with int32
+    indices.  Both sum each row left to right, so their results are
+    identical; the byte count is the same algorithmic one as the GPU's."""
+    import ctypes
     import oracle as orc
     nb = alg_bytes(A.m, A.n, A.nnz)
-    done = 0
-    t0 = time.perf_counter()
-    while done < max_products and time.perf_counter() - t0 < budget_s:
-        orc.spmv(A, xs_host[done % xs_host.shape[0]])
-        done += 1
-    dt = (time.perf_counter() - t0) / done
-    return {"value": round(nb / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} products of the full n=10^6 matrix (single-threaded C oracle, "
-                      f"{dt * 1e3:.1f} ms each)",
-            "gflops": round(2 * A.nnz / dt / 1e9, 3)}
+    P = ctypes.c_void_p
+    rp64 = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    ci64 = np.ascontiguousarray(A.colidx, dtype=np.int64)
+    vals = np.ascontiguousarray(A.vals, dtype=np.float64)
+    y1 = np.empty(A.m)
+    f = orc.lib().orc_spmv
+
+    def one(x, y):
+        rc = f(ctypes.c_int64(A.m), rp64.ctypes.data_as(P), ci64.ctypes.data_as(P), vals.ctypes.data_as(P),
+               x.ctypes.data_as(P), y.ctypes.data_as(P))
+        assert rc == 0
+
+    def timed(fn, budget):
+        fn(0)  # warm-up: pages and caches
+        done, t0 = 0, time.perf_counter()
+        while done < max_products and time.perf_counter() - t0 < budget:
+            fn(done)
+            done += 1
+        return (time.perf_counter() - t0) / done, done
+
+    xs = [np.ascontiguousarray(xs_host[i % xs_host.shape[0]]) for i in range(min(xs_host.shape[0], 103))]
+    dt1, n1 = timed(lambda i: one(xs[i % len(xs)], y1), budget_s)
+    out = {"value": round(nb / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n1} products of the full n={A.n} matrix after one warm-up (the oracle's C loop, "
+                     f"one thread, int64 indices converted once; {dt1 * 1e3:.1f} ms each)",
+           "gflops": round(2 * A.nnz / dt1 / 1e9, 3), "cpu_model": cpu_model(),
+           "host_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
+    try:
+        if not os.path.exists(CPU_SO):
+            build_cpu_leg()
+        C = ctypes.CDLL(CPU_SO)
+    except Exception as e:  # no compiler on the host: report the oracle leg only
+        out["all_cores"] = {"error": str(e)[:200]}
+        return out
+    rp32 = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+    ci32 = np.ascontiguousarray(A.colidx, dtype=np.int32)
+    yp = np.empty(A.m)
+
+    def par(i):
+        rc = C.cpu_csr_spmv(ctypes.c_int32(A.m), rp32.ctypes.data_as(P), ci32.ctypes.data_as(P),
+                            vals.ctypes.data_as(P), xs[i % len(xs)].ctypes.data_as(P), yp.ctypes.data_as(P))
+        assert rc == 0
+
+    dtp, npar = timed(par, budget_s)
+    one(xs[(npar - 1) % len(xs)], y1)
+    assert np.array_equal(y1, yp), "the OpenMP product differs from the oracle's"
+    out["all_cores"] = {"value": round(nb / dtp / 1e9, 3), "unit": "GB/s", "cores": int(C.cpu_threads()),
+                        "kind": "openmp static row blocks, int32 indices (bench_cpu.c)",
+                        "sample": f"{npar} products ({dtp * 1e3:.2f} ms each); result equal to the oracle's",
+                        "gflops": round(2 * A.nnz / dtp / 1e9, 3)}
+    return out
 
 
 def plan_sha256(rp, cp, parts, nleaves):
@@ -231,15 +300,9 @@ def main_precision(args, torch, spx):
     x32 = xd.float()
     y = torch.empty(A.m, dtype=torch.float64, device="cuda")
     y32 = torch.empty(A.m, dtype=torch.float32, device="cuda")
-    # one schedule serves the three precisions and the solves: the fastest
-    # binary32 product among the candidates
-    best_t, best_ms = None, None
-    for cand in AUTOTUNE:
-        spx.plan_retune(P, cand)
-        ms = time_calls(torch, lambda: spx.spmv_lowp(P, "f32", x32, y32), 2, 10)
-        if best_ms is None or ms < best_ms:
-            best_t, best_ms = cand, ms
-    spx.plan_retune(P, best_t)
+    # one schedule serves the three precisions and the solves: the library's
+    # autotuner picks the fastest binary32 product
+    best_t, _ = spx.plan_autotune(P, x32, y32, reps=10, precision="f32")
     ref = orc.spmv(A, x64)
     den = orc.abs_rowsum(A, x64)
     out = {"products": {}, "solves": {}}
@@ -395,9 +458,9 @@ def main_selector(args, torch, spx):
     norm = selector.Normalizer(F[tr])
     labels = T.argmin(axis=1)
     t0 = time.time()
-    theta, chosen_settings, tried = selector.fit(norm(F[tr]), T[tr])
+    theta, chosen_settings, tried = selector.fit(F[tr], T[tr], norm)
     ttrain = time.time() - t0
-    chosen = selector.predict(theta, norm(F[te]))
+    chosen = selector.predict(theta, F[te], norm)
     fixed = selector.best_fixed(T[tr])
     r_net = selector.regret(T[te], chosen)
     r_fix = selector.regret(T[te], np.full(te.size, fixed))
@@ -420,7 +483,7 @@ def main_selector(args, torch, spx):
         "best_fixed_choice": selector.choice_name(fixed), "regret_plain_default": stats(r_plain),
         "GBs_exhaustive": round(gbs(T[te].min(axis=1)), 1), "GBs_best_fixed": round(gbs(T[te, fixed]), 1),
         "GBs_plain": round(gbs(T[te, 0]), 1),
-        "train_accuracy": round(float(np.mean(selector.predict(theta, norm(F[tr])) == labels[tr])), 3),
+        "train_accuracy": round(float(np.mean(selector.predict(theta, F[tr], norm) == labels[tr])), 3),
         "test_accuracy": round(float(np.mean(chosen == labels[te])), 3),
         "label_counts": {selector.choice_name(c): int(k) for c, k in zip(*np.unique(labels, return_counts=True))},
         "settings_chosen_on_validation": chosen_settings,
@@ -436,13 +499,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--forms", default="plain,db,split")
+    ap.add_argument("--forms", default="plain,sbfs,srcm,shp_rn,sb,db,split,split_unit,banded",
+                    help="sbfs, srcm, shp_rn: breadth-first and reverse Cuthill-McKee orders of the "
+                         "bipartite graph and the row-net model (Section 5.1); split: row nets weigh 32 column nets; split_unit: all nets weigh 1 "
+                         "(Corollary 4); banded: plain CSR of the banded stand-in (same rows, columns next to "
+                         "the diagonal)")
     ap.add_argument("--K", type=int, default=64)
     ap.add_argument("--window-bytes", type=int, default=131072,
                     help="leaf window budget of the split (x plus y entries, bytes)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--tune", default="", help="wg,nnz_per_block[,blocks_per_tile,window_entries]")
+    ap.add_argument("--tune", default="",
+                    help="wg,nnz_per_block[,blocks_per_tile,window_entries,tiles_per_group]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
@@ -509,7 +577,7 @@ def main():
     tune = None
     if args.tune:
         f = [int(v) for v in args.tune.split(",")]
-        keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries"]
+        keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group"]
         tune = dict(zip(keys, f))
 
     results = {}
@@ -518,26 +586,34 @@ def main():
         if form == "plain":
             P = spx.plan_plain(M, tune=tune)
             xf = xs
+        elif form in ("sbfs", "srcm"):
+            rp, cp = (spx.order_bfs if form == "sbfs" else spx.order_rcm)(M)
+            parts = np.zeros(1, np.int32)
+            P = spx.plan_from_perm(M, rp, cp, tune=tune)
+            xf = torch.empty_like(xs)
+            for i in range(npool):
+                spx.permute_x(P, xs[i], xf[i])
+        elif form == "banded":
+            from synth import gen_banded_like
+            P = spx.plan_plain(spx.from_csr(gen_banded_like(A)), tune=tune)
+            xf = xs
         else:
-            fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
-            wb = args.window_bytes if form == "split" else 0
+            fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split, "shp_rn": spx.reorder_rn,
+                  "split_unit": lambda *a, **k: spx.split(*a, row_net_cost=1, **k)}[form]
+            wb = args.window_bytes if form.startswith("split") else 0
             P, rp, cp, parts = fn(M, args.K, wb, args.seed, tune=tune)
             xf = torch.empty_like(xs)
             for i in range(npool):
                 spx.permute_x(P, xs[i], xf[i])
         prep = time.time() - t
         if tune is None and not args.no_autotune:
-            # schedule autotuning (as OSKI tunes its kernel): a few products
-            # per workgroup shape, then the fastest is kept for the timed run
-            best_t, best_ms = None, None
-            for cand in AUTOTUNE:
-                spx.plan_retune(P, cand)
-                ms, _ = time_form(spx, torch, P, form, xf, y, 2, 10)
-                if best_ms is None or ms < best_ms:
-                    best_t, best_ms = cand, ms
-            spx.plan_retune(P, best_t)
+            # schedule autotuning by the library (as OSKI tunes its kernel):
+            # ten products per candidate schedule, the fastest is kept
+            t = time.time()
+            spx.plan_autotune(P, xf[0], y, reps=10)
+            log(f"{form}: autotune {time.time() - t:.1f} s")
         inf = P.info()
-        plan_key = "identity" if form == "plain" else plan_sha256(rp, cp, parts, inf["nleaves"])
+        plan_key = "identity" if form in ("plain", "banded") else plan_sha256(rp, cp, parts, inf["nleaves"])
         total_ms, kern_ms = time_form(spx, torch, P, form, xf, y, args.warmup, args.steps)
         r = {"ms_per_step": round(total_ms, 5), "kernel_ms": round(kern_ms, 5),
              "GBs": round(nb / (total_ms * 1e-3) / 1e9, 1),
@@ -548,7 +624,8 @@ def main():
              "sum_lambda_col": inf["sum_lambda_col"], "sum_lambda_row": inf["sum_lambda_row"],
              "border_row_nnz": inf["border_row_nnz"], "bytes_matrix": inf["bytes_matrix"],
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
-                      inf["window_entries"]],
+                      inf["window_entries"], inf["tiles_per_group"]],
+             "window_nnz": inf["window_nnz"],
              "plan_sha256": plan_key}
         if args.cold:
             cold_ms = time_cold(spx, torch, P, form, xf, y)
@@ -556,12 +633,29 @@ def main():
             r["cold_GBs"] = round(nb / (cold_ms * 1e-3) / 1e9, 1)
         results[form] = r
         log(form, json.dumps(r))
-        if form != "plain":
+        if form not in ("plain", "banded"):
             del xf
         del P
         torch.cuda.empty_cache()
 
-    reord = {k: v for k, v in results.items() if k != "plain"} or results
+    if "plain" in results:
+        # Table 3's method: the reordering overhead (partition, ordering and
+        # plan building on the host) in units of one plain CSR product on the
+        # same GPU, and the number of products after which the faster form
+        # has paid it back
+        tp = results["plain"]["ms_per_step"]
+        for k, r in results.items():
+            if k in ("plain", "banded"):
+                continue
+            # Table 2's normalized time: the form's time over plain CSR's
+            r["normalized_time"] = round(r["ms_per_step"] / tp, 3)
+            over_ms = 1e3 * r["prep_s"]
+            r["overhead_plain_products"] = round(over_ms / tp, 1)
+            gain = tp - r["ms_per_step"]
+            r["amortization_products"] = round(over_ms / gain) if gain > 0 else None
+    # the headline is the best of the paper's proposed forms (Sections 3 and
+    # 4); the comparison orderings and the banded stand-in are reported beside
+    reord = {k: v for k, v in results.items() if k in ("sb", "db", "split", "split_unit")} or results
     best = max(reord, key=lambda k: reord[k]["GBs"])
     hb = results[best]
     out = {

@@ -57,9 +57,11 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
 #define SPX_FORM_SB 1    /* singly-bordered block-diagonal form, Eq. 1      */
 #define SPX_FORM_DB 2    /* doubly-bordered block-diagonal form, Eq. 5      */
 #define SPX_FORM_SPLIT 3 /* nonzero-disjoint splitting, Section 4           */
+#define SPX_FORM_ORDER 4 /* CSR in a given row and column order (sBFS, sRCM) */
 
 /* Kernel schedule.  Any field set to 0 takes the library default.
- *   wg_size          threads per workgroup: 64, 128 (default), 256 or 512
+ *   wg_size          threads per workgroup: 64, 128 (default), 256, 512 (or
+ *                    1024, see tiles_per_group)
  *   nnz_per_block    nonzeros one workgroup stages per block: 4 * wg_size
  *                    (default; 8 * wg_size for wg_size 64) or 8 * wg_size
  *                    (every thread loads 4 or 8 consecutive nonzeros)
@@ -73,7 +75,19 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    -1 = hardware dispatch order
  *   reduce_iters     bound on the strided per-row reduction loop inside a
  *                    block, 1..64 (default 64); smaller bounds make blocks of
- *                    mixed row lengths hold fewer rows                       
+ *                    mixed row lengths hold fewer rows
+ *   tiles_per_group  0 (default): tiles as above.  T > 0: each of the 8 row
+ *                    groups (runs of the stored rows with nearly equal
+ *                    nonzeros, one per XCD) is cut into T tiles of nearly
+ *                    equal nonzeros across leaves, each run by one workgroup
+ *                    with its own LDS x window (the densest column range of
+ *                    at most window_entries among the tile's nonzeros, kept
+ *                    when it serves at least half as many gathers as it
+ *                    holds entries); blocks_per_tile is then ignored.  With
+ *                    T near the number of workgroups resident on an XCD the
+ *                    launch is persistent and each window is loaded once.
+ *                    wg_size 1024 is available only in this mode with a
+ *                    window (at most 15360 entries).
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
@@ -83,7 +97,8 @@ typedef struct spx_tune_s {
     int32_t window_entries;
     int32_t xcd_remap;
     int32_t reduce_iters;
-    int32_t reserved[2];
+    int32_t tiles_per_group;
+    int32_t reserved;
 } spx_tune;
 
 /* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
@@ -109,6 +124,7 @@ typedef struct spx_plan_info_s {
     double plan_seconds;      /* host time of ordering and table building */
     int32_t reduce_iters;     /* bound on the per-row reduction loop of a block */
     int32_t nlong_rows;       /* slots too long for one block, run as one-round segments */
+    int32_t tiles_per_group;  /* tiles of every row group (0: tiles follow leaves) */
 } spx_plan_info;
 
 const char *spx_last_error(void);
@@ -193,6 +209,26 @@ spx_status spx_reorder_db(spx_mat A, int32_t K, int64_t window_bytes, uint64_t s
 spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
                      int32_t *row_perm, int32_t *col_perm, int32_t *nz_part,
                      const spx_tune *tune, spx_plan *out);
+/* spx_reorder_rn (sHP_RN, Section 5.1, the row-net model of Yzelman and
+ * Bisseling): the columns of A are partitioned into K parts by recursive
+ * bisection of the row-net hypergraph (columns are vertices weighted
+ * nnz + 1, rows are nets; connectivity cutsize); a row whose columns lie in
+ * one part joins that part, a row reaching several parts goes to the row
+ * border R_B (the cut nets; the paper's method places them between the
+ * parts, here they follow all parts).  The result has the DB block
+ * structure of Eq. 5 and is stored as a DB plan: part_ptr[K+2] as for
+ * spx_reorder_db.  No leaves below the K parts. */
+spx_status spx_reorder_rn(spx_mat A, int32_t K, uint64_t seed, int32_t *row_perm, int32_t *col_perm,
+                          int32_t *part_ptr, const spx_tune *tune, spx_plan *out);
+/* spx_split_ex: spx_split with the cost of a row net of the row-column-net
+ * model given relative to a column net (1..2^20).  Corollary 4 bounds the
+ * misses of the split by the cut rows and cut columns alike: cost 1 is that
+ * objective as written.  spx_split uses 32: on the GPU a row shared by one
+ * more part costs a zeroed y entry and a binary64 atomic add, a shared
+ * column one more x read that usually hits L2. */
+spx_status spx_split_ex(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed, int32_t row_net_cost,
+                        int32_t *row_perm, int32_t *col_perm, int32_t *nz_part, const spx_tune *tune,
+                        spx_plan *out);
 
 /* spx_plan_from_parts: the SB form (Section 3.1, Eq. 1), DB form (Section
  * 3.2, Eq. 5) or split (Section 4) for a partition given by the caller
@@ -204,9 +240,48 @@ spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
 spx_status spx_plan_from_parts(spx_mat A, int32_t form, int32_t K, const int32_t *parts,
                                const spx_tune *tune, int32_t *row_perm, int32_t *col_perm,
                                spx_plan *out);
+/* Comparison orderings of the single-SpMxV framework (Section 5.1), on the
+ * bipartite graph of A (row i = vertex i, column j = vertex m + j, an edge
+ * per nonzero): the visit order of the row vertices is the row order, that
+ * of the column vertices the column order.  Outputs are host arrays
+ * row_perm[m] and col_perm[n] (new -> old).
+ * spx_order_bfs (sBFS): components in order of their smallest vertex,
+ *   breadth-first from it, neighbours by increasing vertex number.
+ * spx_order_rcm (sRCM): reverse Cuthill-McKee; each component (in order of
+ *   its smallest vertex) starts at the pseudo-peripheral vertex of George
+ *   and Liu's search begun at its least-degree vertex; neighbours by
+ *   increasing degree, then number; the whole visit sequence is reversed.
+ * spx_plan_from_perm: plan of form SPX_FORM_ORDER holding A_hat =
+ *   A[row_perm][:, col_perm] in CSR (columns ascending in every row), run
+ *   like a plain plan in the reordered space (spx_permute_x,
+ *   spx_unpermute_y).  SPX_EINVAL when a permutation is not a bijection. */
+spx_status spx_order_bfs(spx_mat A, int32_t *row_perm, int32_t *col_perm);
+spx_status spx_order_rcm(spx_mat A, int32_t *row_perm, int32_t *col_perm);
+spx_status spx_plan_from_perm(spx_mat A, const int32_t *row_perm, const int32_t *col_perm, const spx_tune *tune,
+                              spx_plan *out);
 /* Rebuild the kernel schedule (row blocks, tiles, windows) of a plan without
  * repartitioning.  Not thread-safe against products running on the plan. */
 spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
+/* spx_plan_autotune: pick the plan's schedule by measurement, as OSKI tunes
+ * its kernel to the matrix by timing it (Section 5.2).  Every candidate
+ * schedule of the library (spx_autotune_candidate) is installed in turn and
+ * timed over `reps` products (after two warm-up products) of x into y on
+ * `stream` with HIP events.  precision SPX_PREC_F64: binary64 products, x
+ * and y binary64 device vectors of n and m entries (a split product
+ * includes zeroing its shared rows, accumulate = 0).  SPX_PREC_F32 /
+ * SPX_PREC_BF16: the low-precision product of spx_spmv_lowp on binary32
+ * vectors, over the candidates without tiles (spx_plan_add_lowp first).
+ * The plan keeps the fastest schedule; *chosen (may be NULL) receives it
+ * and *ms (may be NULL) its mean milliseconds per product.  y is
+ * overwritten.  Synchronizes the device between candidates; not
+ * thread-safe against other products on the plan.  SPX_ENODEVICE for a
+ * host-only plan, SPX_EINVAL for reps < 1 or a NULL vector. */
+/* spx_autotune_candidate: the number of candidate schedules of
+ * spx_plan_autotune; when 0 <= i < that number and out is not NULL, *out
+ * receives candidate i (in the order they are tried). */
+int32_t spx_autotune_candidate(int32_t i, spx_tune *out);
+spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void *y, int32_t reps,
+                             spx_tune *chosen, float *ms, void *stream);
 /* spx_plan_destroy frees the plan's host and device memory.  Work queued
  * on a stream that reads the plan (products, permutations, batches built on
  * it) must have completed first: synchronize that stream before destroying. */
@@ -269,6 +344,8 @@ spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *str
  *   ||r|| / ||b|| > tol and fewer than max_outer refinements: run CG in the
  *   given precision on A_low d = r / ||r|| to relative residual inner_tol
  *   (at most max_inner iterations), x <- x + ||r|| d, r <- b - A x.
+ *   The host reads the inner residual every 8 iterations, so an inner
+ *   solve may take up to 7 iterations past the first that meets inner_tol.
  *   SPX_PREC_F64 runs the inner CG in binary64 with the binary64 product.
  *   Returns SPX_ENOTCONV (with stats filled and x the last iterate) if the
  *   tolerance was not reached.  Allocates its workspace on every call.
@@ -376,6 +453,48 @@ spx_status spx_mlp_loss_grad(const float *theta, const float *X, const int32_t *
                              float *loss, float *grad, void *stream);
 spx_status spx_mlp_adam(float *theta, const float *grad, float *m, float *v, int32_t t, float lr,
                         float beta1, float beta2, float eps, void *stream);
+
+/* Selection among the 24 choices (the paper picks the ordering by measuring
+ * it, Section 5.2; here a trained network picks and measurement is the
+ * fallback).  Choice c < 6: plain CSR with schedule c (workgroup 128, 64,
+ * 256, 128 with 8 nonzeros per thread, 128 with reduce_iters 16, 512);
+ * 6 <= c < 24: form SB, DB, split for (c - 6) / 6 = 0, 1, 2 at
+ * K = 8, 16, 32, 64, 128, 256 for (c - 6) % 6, default schedule.  The K-way
+ * partitions of one form all come from one K = 256 recursive bisection of
+ * that form's model (seed `seed`): part p of it lies in part
+ * p >> (8 - log2 K), the DB row border stays the border.
+ *
+ * spx_choice_info: form (SPX_FORM_*), K and schedule of choice c (any
+ *   output may be NULL); SPX_EINVAL outside 0..23.
+ * spx_select: the choice the network picks for A: the 40 features of
+ *   spx_features, each mapped to (log1p(max(f, 0)) - mu[t]) / sd[t] (mu, sd:
+ *   host, 40 binary64 each, the training set's statistics), the network
+ *   forward with theta (device, 8344 binary32) on `stream`, and the largest
+ *   logit (first on ties) into *choice; logits (host, 24, may be NULL)
+ *   receives the logits.  Synchronizes `stream`.
+ * spx_select_features: the same from features f (host, 40) already
+ *   computed by spx_features.
+ * spx_plan_for_choice: the plan of choice c for A (partitioning at K = 256
+ *   and coarsening for the reordered forms); row_perm[m] / col_perm[n]
+ *   (host, may be NULL) receive its permutations (identity for plain).
+ * spx_select_exhaustive: the fallback and the judge of the network's
+ *   regret: every choice is built and timed over `reps` products (two
+ *   warm-up products first) of x (device, n binary64) into y (device, m,
+ *   overwritten; split products include zeroing their shared rows) on
+ *   `stream`; the reordered forms multiply x permuted by their column
+ *   order.  ms (host, 24, may be NULL) receives the milliseconds per
+ *   product of every choice, *choice the fastest, *partition_seconds (may
+ *   be NULL) the host time of the three K = 256 partitions.  SPX_ENODEVICE
+ *   for a host-only matrix. */
+spx_status spx_choice_info(int32_t choice, int32_t *form, int32_t *K, spx_tune *tune);
+spx_status spx_select(spx_mat A, const float *theta, const double *mu, const double *sd, int32_t *choice,
+                      float *logits, void *stream);
+spx_status spx_select_features(const float *f, const float *theta, const double *mu, const double *sd,
+                               int32_t *choice, float *logits, void *stream);
+spx_status spx_plan_for_choice(spx_mat A, int32_t choice, uint64_t seed, int32_t *row_perm, int32_t *col_perm,
+                               spx_plan *out);
+spx_status spx_select_exhaustive(spx_mat A, const double *x, double *y, int32_t reps, uint64_t seed, float *ms,
+                                 int32_t *choice, double *partition_seconds, void *stream);
 
 /* ----------------------------------------------------------------------
  * Inspection (host arrays, caller-allocated; any pointer may be NULL).

@@ -209,6 +209,28 @@ def _sets_per_index(idx, lab, size):
     return cnt, first
 
 
+XCD_GROUPS = 8  # row groups of the order inside classes: one per XCD of the MI355X
+
+
+def _group_of_start(start, nnz):
+    """Row group of a stored row (slot) whose nonzeros start at storage
+    offset ``start``: the stored matrix is cut into XCD_GROUPS runs of nearly
+    equal nonzeros, floor(XCD_GROUPS * start / nnz)."""
+    start = np.asarray(start, dtype=np.int64)
+    if nnz <= 0:
+        return np.zeros_like(start)
+    return (XCD_GROUPS * start) // int(nnz)
+
+
+def _reader_mask(cols, grp, n):
+    """For every column, the set of row groups with a nonzero in it, as a
+    number whose bit g is set when group g reads the column."""
+    mask = np.zeros(n, dtype=np.int64)
+    if cols.size:
+        np.bitwise_or.at(mask, cols, np.left_shift(np.int64(1), grp.astype(np.int64)))
+    return mask
+
+
 def canonical_rowcol(A, r2p, r2leaf, K, nleaves=None):
     """Row and column orders of the SB form (Eq. 1) or DB form (Eq. 5).
 
@@ -219,9 +241,11 @@ def canonical_rowcol(A, r2p, r2leaf, K, nleaves=None):
     Columns, judged over the non-border rows that touch them: a column touched
     by one leaf goes with that leaf, a column touched by several leaves of one
     part goes after that part's leaf columns, and every other column (touched
-    by several parts, or by none) goes to the column border C_B at the end;
-    inside each of these classes columns go by decreasing number of nonzeros
-    (in A), then by original index.
+    by several parts, or by none) goes to the column border C_B at the end.
+    Inside each of these classes columns go by the set of row groups that
+    read them (as a number, ascending; the rows in their new order are cut
+    into XCD_GROUPS runs of nearly equal nonzeros, border rows included),
+    then by decreasing number of nonzeros (in A), then by original index.
 
     Returns dict(row_perm, col_perm, part_ptr[K+2], col_part_ptr[K+2],
     leaf_row_ptr, leaf_col_lo, leaf_col_hi, row_leaf, col_class).
@@ -245,7 +269,12 @@ def canonical_rowcol(A, r2p, r2leaf, K, nleaves=None):
     ck_sub = np.where(ck_part == K, 0, ck_sub)
     ck_leaf = np.where(ck_part == K, 0, ck_leaf)
     cdeg = np.bincount(cols, minlength=n)
-    col_perm = np.lexsort((np.arange(n), -cdeg, ck_leaf, ck_sub, ck_part))
+    rdeg = np.diff(_i64(A.rowptr))
+    start_new = np.cumsum(rdeg[row_perm]) - rdeg[row_perm]
+    rgrp = np.empty(m, dtype=np.int64)
+    rgrp[row_perm] = _group_of_start(start_new, A.nnz)
+    mask = _reader_mask(cols, rgrp[rows], n)
+    col_perm = np.lexsort((np.arange(n), -cdeg, mask, ck_leaf, ck_sub, ck_part))
     part_ptr = np.searchsorted(grp[row_perm], np.arange(K + 2), side="left")
     part_ptr[K + 1] = m
     col_part_ptr = np.searchsorted(ck_part[col_perm], np.arange(K + 2), side="left")
@@ -273,8 +302,11 @@ def canonical_split(A, nz_part, nz_leaf, K):
     Rows whose nonzeros all lie in one leaf come first, grouped by leaf; rows
     spread over several leaves follow, grouped by part (rows spread over
     several parts last); empty rows close the order.  Columns follow the same
-    rule as :func:`canonical_rowcol` (classes, then decreasing number of
-    nonzeros); remaining ties by original index.
+    rule as :func:`canonical_rowcol` (classes, then the set of row groups that
+    read them, then decreasing number of nonzeros, then original index); a
+    nonzero's row group is that of its stored row (leaf, row) in the per-leaf
+    storage of :func:`split_gcsr`, whose stored rows are cut into
+    XCD_GROUPS runs of nearly equal nonzeros.
 
     Returns dict(row_perm, col_perm, row_shared_begin, row_empty_begin,
     col_part_ptr[K+2]).
@@ -299,7 +331,18 @@ def canonical_split(A, nz_part, nz_leaf, K):
     ck_sub = np.where((ck_part < K) & (nl_c > 1), 1, 0)
     ck_leaf = np.where((ck_part < K) & (nl_c == 1), l_c, 0)
     cdeg = np.bincount(cols, minlength=n)
-    col_perm = np.lexsort((np.arange(n), -cdeg, ck_leaf, ck_sub, ck_part))
+    # stored rows: (leaf, new row) pairs, leaf-major then by new row
+    inv_r = np.empty(m, dtype=np.int64)
+    inv_r[row_perm] = np.arange(m)
+    nr = inv_r[rows]
+    order = np.lexsort((nr, nz_leaf))
+    key = nz_leaf[order] * max(m, 1) + nr[order]
+    first = np.r_[True, key[1:] != key[:-1]] if key.size else np.zeros(0, bool)
+    start_sorted = np.maximum.accumulate(np.where(first, np.arange(key.size), 0)) if key.size else key
+    start = np.empty(key.size, dtype=np.int64)
+    start[order] = start_sorted
+    mask = _reader_mask(cols, _group_of_start(start, A.nnz), n)
+    col_perm = np.lexsort((np.arange(n), -cdeg, mask, ck_leaf, ck_sub, ck_part))
     col_part_ptr = np.searchsorted(ck_part[col_perm], np.arange(K + 2), side="left")
     col_part_ptr[K + 1] = n
     return dict(row_perm=row_perm.astype(np.int64), col_perm=col_perm.astype(np.int64),
@@ -611,3 +654,99 @@ def features(A):
     if m and rdeg.mean() > 0:
         f[39] = rdeg.std() / rdeg.mean()
     return f
+
+
+# --------------------------------------------------------------------------
+# Comparison orderings of Section 5.1 on the bipartite graph of A: vertices
+# are rows 0..m-1 and columns m..m+n-1, an edge per nonzero.  Readings (the
+# paper names the methods, not their start vertices or tie-breaks): sBFS
+# visits components in order of their smallest vertex, breadth-first from
+# it, neighbours by increasing number; sRCM starts each component (in order
+# of its smallest vertex) at George and Liu's pseudo-peripheral vertex,
+# searched from the component's least-degree vertex (smallest number on
+# ties), visits unvisited neighbours by increasing (degree, number), and
+# reverses the whole visit sequence.
+
+
+def _bipartite(A):
+    """CSR adjacency of the bipartite graph, neighbours ascending."""
+    m, n = A.m, A.n
+    rows = _row_of(A)
+    cols = _i64(A.colidx) + m
+    src = np.concatenate([rows, cols])
+    dst = np.concatenate([cols, rows])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    off = np.zeros(m + n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=m + n), out=off[1:])
+    return off, dst
+
+
+def _levels(off, adj, start, visited):
+    """Breadth-first search from start over vertices with visited False,
+    level by level; each level lists the new vertices in the order their
+    first visiting neighbour (earlier in the previous level, and earlier in
+    its adjacency list) reaches them.  Marks them visited; returns the
+    levels."""
+    visited[start] = True
+    levels = [np.array([start], dtype=np.int64)]
+    while True:
+        fr = levels[-1]
+        lens = off[fr + 1] - off[fr]
+        if lens.sum() == 0:
+            break
+        idx = np.repeat(off[fr] - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens) + np.arange(lens.sum())
+        cand = adj[idx]
+        cand = cand[~visited[cand]]
+        if cand.size == 0:
+            break
+        _, first = np.unique(cand, return_index=True)
+        new = cand[np.sort(first)]
+        visited[new] = True
+        levels.append(new)
+    return levels
+
+
+def order_bfs(A):
+    """sBFS row and column orders (new -> old)."""
+    m, n = A.m, A.n
+    off, adj = _bipartite(A)
+    visited = np.zeros(m + n, dtype=bool)
+    seq = []
+    for v in range(m + n):
+        if not visited[v]:
+            seq.extend(_levels(off, adj, v, visited))
+    seq = np.concatenate(seq) if seq else np.zeros(0, np.int64)
+    return seq[seq < m], seq[seq >= m] - m
+
+
+def order_rcm(A):
+    """sRCM row and column orders (new -> old)."""
+    m, n = A.m, A.n
+    off, adj = _bipartite(A)
+    deg = np.diff(off)
+    # every adjacency list sorted by (degree, number) for Cuthill-McKee
+    owner = np.repeat(np.arange(m + n), deg)
+    o2 = np.lexsort((adj, deg[adj], owner))
+    adj_cm = adj[o2]
+    done = np.zeros(m + n, dtype=bool)
+    seq = []
+    for v0 in range(m + n):
+        if done[v0]:
+            continue
+        comp = np.concatenate(_levels(off, adj, v0, np.zeros(m + n, dtype=bool)))
+        start = int(comp[np.lexsort((comp, deg[comp]))[0]])
+
+        def last_level(s):
+            lv = _levels(off, adj, s, np.zeros(m + n, dtype=bool))
+            return len(lv), lv[-1]
+        ecc, last = last_level(start)
+        while True:
+            cand = int(last[np.lexsort((last, deg[last]))[0]])
+            e2, l2 = last_level(cand)
+            if e2 <= ecc:
+                break
+            start, ecc, last = cand, e2, l2
+        seq.extend(_levels(off, adj_cm, start, done))
+    seq = np.concatenate(seq)[::-1] if seq else np.zeros(0, np.int64)
+    return seq[seq < m], seq[seq >= m] - m

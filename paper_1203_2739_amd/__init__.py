@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspx.so")
 
 FORM_PLAIN, FORM_SB, FORM_DB, FORM_SPLIT = 0, 1, 2, 3
-FORM_NAMES = {0: "plain", 1: "sb", 2: "db", 3: "split"}
+FORM_NAMES = {0: "plain", 1: "sb", 2: "db", 3: "split", 4: "order"}
 
 _lib = None
 
@@ -34,7 +34,7 @@ class Tune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("nnz_per_block", ctypes.c_int32),
                 ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("tiles_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +49,8 @@ class PlanInfo(ctypes.Structure):
                 ("cut_connectivity", ctypes.c_int64), ("bytes_matrix", ctypes.c_int64),
                 ("bytes_window", ctypes.c_int64), ("window_nnz", ctypes.c_int64),
                 ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
-                ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32)]
+                ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32),
+                ("tiles_per_group", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -67,7 +68,20 @@ _SIGS = {
     "spx_reorder_sb": ([_VP, _I32, _I64, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_reorder_db": ([_VP, _I32, _I64, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_split": ([_VP, _I32, _I64, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_split_ex": ([_VP, _I32, _I64, ctypes.c_uint64, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_reorder_rn": ([_VP, _I32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_plan_retune": ([_VP, _VP], _I32),
+    "spx_plan_autotune": ([_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
+    "spx_autotune_candidate": ([_I32, _VP], _I32),
+    "spx_choice_info": ([_I32, _VP, _VP, _VP], _I32),
+    "spx_order_bfs": ([_VP, _VP, _VP], _I32),
+    "spx_order_rcm": ([_VP, _VP, _VP], _I32),
+    "spx_plan_from_perm": ([_VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_mlp_loss_grad_noalloc": ([_VP, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
+    "spx_select": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_select_features": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_plan_for_choice": ([_VP, _I32, ctypes.c_uint64, _VP, _VP, _VP], _I32),
+    "spx_select_exhaustive": ([_VP, _VP, _VP, _I32, ctypes.c_uint64, _VP, _VP, _VP, _VP], _I32),
     "spx_plan_destroy": ([_VP], None),
     "spx_plan_info_get": ([_VP, _VP], _I32),
     "spx_spmv": ([_VP, _VP, _VP, _VP], _I32),
@@ -404,13 +418,55 @@ def reorder_db(A: Mat, K, window_bytes=0, seed=0, tune=None):
     return _reorder(lib().spx_reorder_db, A, K, window_bytes, seed, tune, K + 2)
 
 
-def split(A: Mat, K, window_bytes=0, seed=0, tune=None):
-    """Splitting (Section 4): returns (plan, row_perm, col_perm, nz_part[nnz])."""
-    return _reorder(lib().spx_split, A, K, window_bytes, seed, tune, A.nnz)
+def reorder_rn(A: Mat, K, window_bytes=0, seed=0, tune=None):
+    """sHP_RN (row-net model, Section 5.1) as a DB-shaped plan: returns
+    (plan, row_perm, col_perm, part_ptr[K+2]).  window_bytes is ignored."""
+    fn = lambda a, k, wb, sd, *rest: lib().spx_reorder_rn(a, k, sd, *rest)  # noqa: E731
+    return _reorder(fn, A, K, window_bytes, seed, tune, K + 2)
+
+
+def split(A: Mat, K, window_bytes=0, seed=0, tune=None, row_net_cost=None):
+    """Splitting (Section 4): returns (plan, row_perm, col_perm, nz_part[nnz]).
+    row_net_cost: cost of a row net relative to a column net (None: the
+    library's default, 32; 1 is Corollary 4's objective as written)."""
+    if row_net_cost is None:
+        return _reorder(lib().spx_split, A, K, window_bytes, seed, tune, A.nnz)
+    fn = lambda *a: lib().spx_split_ex(a[0], a[1], a[2], a[3], int(row_net_cost), *a[4:])  # noqa: E731
+    return _reorder(fn, A, K, window_bytes, seed, tune, A.nnz)
 
 
 def plan_retune(P: Plan, tune=None):
     _check(lib().spx_plan_retune(P.handle, _tune_ptr(tune)))
+
+
+_TUNE_FIELDS = ("wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "xcd_remap", "reduce_iters",
+                "tiles_per_group")
+
+
+def autotune_candidates():
+    """The library's candidate schedules, as dicts, in the order tried."""
+    n = int(lib().spx_autotune_candidate(-1, None))
+    out = []
+    for i in range(n):
+        t = make_tune()
+        lib().spx_autotune_candidate(i, ctypes.byref(t))
+        out.append({f: getattr(t, f) for f in _TUNE_FIELDS if getattr(t, f)})
+    return out
+
+
+def plan_autotune(P: Plan, x, y, reps=10, precision="f64", stream=None):
+    """Time the library's candidate schedules on x -> y and keep the fastest
+    (binary64 products, or the "f32"/"bf16" products on binary32 vectors).
+    Returns (schedule dict, milliseconds per product)."""
+    import torch
+    m, n, _ = P.mat_dims
+    prec = {"f64": 0}.get(precision, _PREC.get(precision, precision))
+    dt = torch.float64 if prec == 0 else torch.float32
+    t = make_tune()
+    ms = ctypes.c_float()
+    _check(lib().spx_plan_autotune(P.handle, int(prec), _dev(x, dt, n), _dev(y, dt, m), int(reps),
+                                   ctypes.byref(t), ctypes.byref(ms), _stream(stream)))
+    return {f: getattr(t, f) for f in _TUNE_FIELDS}, ms.value
 
 
 def spmv(P: Plan, x, y, stream=None):
@@ -625,6 +681,23 @@ def mlp_loss_grad(theta, X, labels, loss, grad, stream=None):
                                    _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
 
 
+def mlp_loss_grad_noalloc(theta, X, labels, loss, grad, stream=None):
+    """mlp_loss_grad through the entry point that allocates nothing (batches of
+    at most 512 samples share one fixed device workspace per GPU)."""
+    import torch
+    B = X.shape[0]
+    if labels.numel() < B:
+        raise ValueError(f"{labels.numel()} labels for {B} samples")
+    if 0 < B <= 512:
+        lo, hi = int(labels[:B].min()), int(labels[:B].max())
+        if lo < 0 or hi >= NCHOICES:
+            raise ValueError(f"labels must lie in [0, {NCHOICES}), got [{lo}, {hi}]")
+    _check(lib().spx_mlp_loss_grad_noalloc(_dev(theta, torch.float32, MLP_PARAMS),
+                                           _dev(X, torch.float32, B * NFEATURES), _dev(labels, torch.int32, B),
+                                           int(B), _dev(loss, torch.float32, 1),
+                                           _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
+
+
 def mlp_adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     import torch
     _check(lib().spx_mlp_adam(_dev(theta, torch.float32, MLP_PARAMS), _dev(grad, torch.float32, MLP_PARAMS),
@@ -644,3 +717,99 @@ def plan_from_parts(A: Mat, form, K, parts, tune=None):
     _check(lib().spx_plan_from_parts(A.handle, f, int(K), _hp(pa), _tune_ptr(tune), _hp(rp), _hp(cp),
                                      ctypes.byref(h)))
     return Plan(h.value, A), rp[:A.m], cp[:A.n]
+
+
+# ---------------------------------------------------------------- selection
+
+def choice_info(choice):
+    """(form name, K, schedule dict) of one of the 24 choices."""
+    f, k = ctypes.c_int32(), ctypes.c_int32()
+    t = make_tune()
+    _check(lib().spx_choice_info(int(choice), ctypes.byref(f), ctypes.byref(k), ctypes.byref(t)))
+    return FORM_NAMES[f.value], k.value, {n: getattr(t, n) for n in _TUNE_FIELDS if getattr(t, n)}
+
+
+def _norm_arrays(mu, sd):
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    sd = np.ascontiguousarray(sd, dtype=np.float64)
+    if mu.size != NFEATURES or sd.size != NFEATURES:
+        raise ValueError(f"mu and sd need {NFEATURES} entries")
+    return mu, sd
+
+
+def select(A: Mat, theta, mu, sd, stream=None):
+    """The network's choice for matrix A: (choice, logits[24])."""
+    import torch
+    mu, sd = _norm_arrays(mu, sd)
+    c = ctypes.c_int32()
+    lg = np.empty(NCHOICES, np.float32)
+    _check(lib().spx_select(A.handle, _dev(theta, torch.float32, MLP_PARAMS), _hp(mu), _hp(sd), ctypes.byref(c),
+                            _hp(lg), _stream(stream)))
+    return c.value, lg
+
+
+def select_features(f, theta, mu, sd, stream=None):
+    """The network's choice for raw features f[40] (from features()): (choice, logits)."""
+    import torch
+    mu, sd = _norm_arrays(mu, sd)
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    if f.size != NFEATURES:
+        raise ValueError(f"features need {NFEATURES} entries")
+    c = ctypes.c_int32()
+    lg = np.empty(NCHOICES, np.float32)
+    _check(lib().spx_select_features(_hp(f), _dev(theta, torch.float32, MLP_PARAMS), _hp(mu), _hp(sd),
+                                     ctypes.byref(c), _hp(lg), _stream(stream)))
+    return c.value, lg
+
+
+def plan_for_choice(A: Mat, choice, seed=0):
+    """(plan, row_perm, col_perm) of a choice for A."""
+    rp = np.empty(max(A.m, 1), np.int32)
+    cp = np.empty(max(A.n, 1), np.int32)
+    h = _VP()
+    _check(lib().spx_plan_for_choice(A.handle, int(choice), ctypes.c_uint64(int(seed)), _hp(rp), _hp(cp),
+                                     ctypes.byref(h)))
+    return Plan(h.value, A), rp[:A.m], cp[:A.n]
+
+
+def select_exhaustive(A: Mat, x, y, reps=10, seed=0, stream=None):
+    """Every choice timed on x -> y: (fastest choice, ms[24], partition seconds)."""
+    import torch
+    ms = np.empty(NCHOICES, np.float32)
+    c = ctypes.c_int32()
+    tp = ctypes.c_double()
+    _check(lib().spx_select_exhaustive(A.handle, _dev(x, torch.float64, A.n), _dev(y, torch.float64, A.m),
+                                       int(reps), ctypes.c_uint64(int(seed)), _hp(ms), ctypes.byref(c),
+                                       ctypes.byref(tp), _stream(stream)))
+    return c.value, ms.astype(np.float64), tp.value
+
+
+# ---------------------------------------------------------------- comparison orderings
+
+def order_bfs(A: Mat):
+    """sBFS (Section 5.1): (row_perm, col_perm) from breadth-first search on
+    the bipartite graph of A."""
+    rp = np.empty(max(A.m, 1), np.int32)
+    cp = np.empty(max(A.n, 1), np.int32)
+    _check(lib().spx_order_bfs(A.handle, _hp(rp), _hp(cp)))
+    return rp[:A.m], cp[:A.n]
+
+
+def order_rcm(A: Mat):
+    """sRCM (Section 5.1): (row_perm, col_perm) from reverse Cuthill-McKee on
+    the bipartite graph of A."""
+    rp = np.empty(max(A.m, 1), np.int32)
+    cp = np.empty(max(A.n, 1), np.int32)
+    _check(lib().spx_order_rcm(A.handle, _hp(rp), _hp(cp)))
+    return rp[:A.m], cp[:A.n]
+
+
+def plan_from_perm(A: Mat, row_perm, col_perm, tune=None):
+    """Plan holding A[row_perm][:, col_perm] in CSR (form "order")."""
+    rp = np.ascontiguousarray(row_perm, dtype=np.int32)
+    cp = np.ascontiguousarray(col_perm, dtype=np.int32)
+    if rp.size != A.m or cp.size != A.n:
+        raise ValueError("row_perm needs m entries and col_perm n entries")
+    h = _VP()
+    _check(lib().spx_plan_from_perm(A.handle, _hp(rp), _hp(cp), _tune_ptr(tune), ctypes.byref(h)))
+    return Plan(h.value, A)

@@ -22,7 +22,7 @@ CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 ARCH = "gfx950"
 
 DEVICE_SOURCES = ["kernels.hip", "mlp.hip"]
-HOST_HIP_SOURCES = ["api.cpp", "lowp.cpp", "batch.cpp", "selector.cpp"]
+HOST_HIP_SOURCES = ["api.cpp", "lowp.cpp", "batch.cpp", "selector.cpp", "tune.cpp", "orderings.cpp"]
 HOST_SOURCES = ["partition.cpp", "plan.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

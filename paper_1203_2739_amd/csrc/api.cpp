@@ -60,9 +60,13 @@ Tune resolve_tune(const spx_tune *t, int form) {
         if (t->window_entries) r.window_entries = t->window_entries;
         if (t->xcd_remap) r.xcd_remap = t->xcd_remap > 0 ? 1 : 0;
         if (t->reduce_iters) r.reduce_iters = t->reduce_iters;
+        if (t->tiles_per_group) r.tiles_per_group = t->tiles_per_group;
     }
-    if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512)
-        fail(SPX_EINVAL, "wg_size must be 64, 128, 256 or 512");
+    if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512 && r.wg != 1024)
+        fail(SPX_EINVAL, "wg_size must be 64, 128, 256, 512 or 1024");
+    if (r.tiles_per_group < 0 || r.tiles_per_group > 4096) fail(SPX_EINVAL, "tiles_per_group must be in 0..4096");
+    if (r.wg == 1024 && (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
+        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only tiles per row group with an LDS window");
     if (!t || !t->nnz_per_block) r.nnz_per_block = (r.wg == 64 ? 8 : kDefaultNpt) * r.wg;
     if (r.nnz_per_block != 4 * r.wg && r.nnz_per_block != 8 * r.wg)
         fail(SPX_EINVAL, "nnz_per_block must be 4 or 8 times wg_size (nonzeros per thread)");
@@ -164,6 +168,23 @@ void upload_schedule(spx_plan_s &P, void *stream) {
 }
 }  // namespace spx
 
+// A plan of form SB, DB or split from a given partition (leaves as given
+// by r), with the schedule `tune` (NULL: library default), uploaded when A
+// has a device copy.
+spx_plan_s *spx::plan_from_partition(const spx_mat_s &A, int form, int32_t K, const PartitionResult &r,
+                                     const spx_tune *tune) {
+    std::unique_ptr<spx_plan_s> P(new spx_plan_s());
+    P->K = K;
+    if (form == SPX_FORM_SPLIT) plan_from_split(*P, A.h, r);
+    else plan_from_rowparts(*P, A.h, r, form == SPX_FORM_DB);
+    spx_tune t{};
+    if (tune) t = *tune;
+    P->tune = resolve_tune(&t, P->form);
+    build_schedule(*P);
+    upload_plan(*P, A, nullptr);
+    return P.release();
+}
+
 static void apply_tune(spx_plan_s &P, const spx_tune *tune, int64_t window_bytes) {
     spx_tune t{};
     if (tune) t = *tune;
@@ -179,7 +200,8 @@ static void write_outputs(const spx_plan_s &P, int32_t *row_perm, int32_t *col_p
 
 static spx_status build_reordered(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
                                   Model model, int32_t *row_perm, int32_t *col_perm,
-                                  int32_t *part_out, const spx_tune *tune, spx_plan *out) {
+                                  int32_t *part_out, const spx_tune *tune, spx_plan *out,
+                                  int64_t row_net_cost = kSplitRowNetCostDefault) {
     return guarded([&] {
         if (!A || !out) fail(SPX_EINVAL, "NULL handle");
         if (K < 1) fail(SPX_EINVAL, "K must be >= 1");
@@ -188,9 +210,9 @@ static spx_status build_reordered(spx_mat A, int32_t K, int64_t window_bytes, ui
         std::unique_ptr<spx_plan_s> P(new spx_plan_s());
         P->K = K;
         const CsrHost &h = A->h;
-        PartitionResult r = partition(h, model, K, window_bytes / 8, seed);
+        PartitionResult r = partition(h, model, K, window_bytes / 8, seed, row_net_cost);
         if (model == Model::ColumnNet) plan_from_rowparts(*P, h, r, false);
-        else if (model == Model::ERowColumnNet) plan_from_rowparts(*P, h, r, true);
+        else if (model == Model::ERowColumnNet || model == Model::RowNet) plan_from_rowparts(*P, h, r, true);
         else plan_from_split(*P, h, r);
         apply_tune(*P, tune, window_bytes);
         upload_plan(*P, *A, nullptr);
@@ -216,6 +238,8 @@ hipError_t spx::run_product(spx_plan_s &P, const double *x, double *y, int32_t a
     const bool tl = tiled(P.tune);
     a.ntiles = (int32_t)(tl ? P.tiles.size() / 4 : P.blk_desc.size() / 4);
     a.xcd_remap = P.tune.xcd_remap;
+    std::copy(tl ? P.xcd_tile_ptr.begin() : P.xcd_blk_ptr.begin(),
+              tl ? P.xcd_tile_ptr.end() : P.xcd_blk_ptr.end(), a.xcd_ptr);
     a.n = P.n;
     a.long_seg_ptr = (const int32_t *)P.d_long_seg_ptr->ptr;
     a.partials = (double *)P.d_partials->ptr;
@@ -330,6 +354,22 @@ spx_status spx_split(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed,
                            nz_part, tune, out);
 }
 
+spx_status spx_reorder_rn(spx_mat A, int32_t K, uint64_t seed, int32_t *row_perm, int32_t *col_perm,
+                          int32_t *part_ptr, const spx_tune *tune, spx_plan *out) {
+    return build_reordered(A, K, 0, seed, Model::RowNet, row_perm, col_perm, part_ptr, tune, out);
+}
+
+spx_status spx_split_ex(spx_mat A, int32_t K, int64_t window_bytes, uint64_t seed, int32_t row_net_cost,
+                        int32_t *row_perm, int32_t *col_perm, int32_t *nz_part, const spx_tune *tune,
+                        spx_plan *out) {
+    if (row_net_cost < 1 || row_net_cost > 1 << 20) {
+        spx::set_last_error("row_net_cost must be in 1..2^20");
+        return SPX_EINVAL;
+    }
+    return build_reordered(A, K, window_bytes, seed, Model::RowColumnNet, row_perm, col_perm,
+                           nz_part, tune, out, row_net_cost);
+}
+
 spx_status spx_plan_retune(spx_plan P, const spx_tune *tune) {
     return guarded([&] {
         if (!P) fail(SPX_EINVAL, "NULL handle");
@@ -383,6 +423,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->plan_seconds = P->plan_seconds;
         info->reduce_iters = P->tune.reduce_iters;
         info->nlong_rows = P->long_seg_ptr.empty() ? 0 : (int32_t)P->long_seg_ptr.size() - 1;
+        info->tiles_per_group = P->tune.tiles_per_group;
     });
 }
 
@@ -466,7 +507,8 @@ spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *sl
 spx_status spx_plan_export_parts(spx_plan P, int32_t *a, int32_t *b) {
     return guarded([&] {
         if (!P) fail(SPX_EINVAL, "NULL handle");
-        if (P->form == SPX_FORM_PLAIN) fail(SPX_EUNSUPPORTED, "plain plans have no partition");
+        if (P->form == SPX_FORM_PLAIN || P->form == SPX_FORM_ORDER)
+            fail(SPX_EUNSUPPORTED, "plain and ordered plans have no partition");
         if (a) std::copy(P->part_a.begin(), P->part_a.end(), a);
         if (b) std::copy(P->part_b.begin(), P->part_b.end(), b);
     });

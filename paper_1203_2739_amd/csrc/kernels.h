@@ -26,8 +26,9 @@ struct SpmvArgsT {
     int32_t ntiles;           // workgroups: tiles, or blocks when not tiled
     int32_t shared_begin;     // split: rows >= this are accumulated atomically
     int32_t accumulate;       // split: add to y for rows owned by one leaf
-    int32_t xcd_remap;
+    int32_t xcd_remap;        // 1: workgroup w runs unit xcd_ptr[w % 8] + w / 8 of row group w % 8
     int32_t n;                // columns
+    int32_t xcd_ptr[kXcdGroups + 1];  // first unit (tile or block) of every row group
     const int32_t *long_seg_ptr;  // [nlong+1] partial-sum entries of each long slot
     double *partials;             // one per long-slot segment
     uint32_t *counters;           // one per long slot, zero between products

@@ -62,11 +62,16 @@ __device__ __forceinline__ float xor_lanes(float v, int off) {
     return __int_as_float(xor_lanes_i(__float_as_int(v), off));
 }
 
-__device__ __forceinline__ int remap_tile(int bid, int ntiles, int on) {
-    if (!on) return bid;
-    int x = bid & 7, i = bid >> 3;
-    int per = ntiles >> 3, rem = ntiles & 7;
-    return x * per + (x < rem ? x : rem) + i;
+// Unit (tile or block) of workgroup bid: with the XCD mapping on, the
+// hardware's round-robin dispatch puts workgroup bid on XCD bid % 8, which
+// runs the units of row group bid % 8 in order; -1 when that group has no
+// unit left for this workgroup.
+template <class V, class A>
+__device__ __forceinline__ int unit_of(const SpmvArgsT<V, A> &a, int bid) {
+    if (!a.xcd_remap) return bid;
+    const int x = bid & (kXcdGroups - 1), i = bid / kXcdGroups;
+    const int u = a.xcd_ptr[x] + i;
+    return u < a.xcd_ptr[x + 1] ? u : -1;
 }
 
 // Writes the sum of one slot: an atomic add for a row shared by several
@@ -225,11 +230,16 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgsT<V, A> &a, const
             const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / (NPT * WG);
             // The partial goes to the device-coherent level (an agent-scope
             // atomic store writes through the XCD's L2) and must have landed
-            // before the counter moves: wait for the store to complete.  An
-            // acquire/release fence would also write back and invalidate the
-            // whole L2 of the XCD, discarding the cached x entries.
+            // before the counter moves: the wave waits until the store is
+            // acknowledged (vmcnt counts stores on gfx9 parts), and the
+            // signal fence keeps the compiler from moving the counter update
+            // above that wait.  The segment that sees the final count reads
+            // the partials with agent-scope loads issued after its update
+            // returned.  A release on the update would instead write back
+            // the whole L2 of the XCD (buffer_wbl2) for every segment.
             __hip_atomic_store(&a.partials[base + seg], (double)part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): expcnt and lgkmcnt left unconstrained
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             const uint32_t done =
                 __hip_atomic_fetch_add(&a.counters[lr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (done == (uint32_t)nseg - 1) {
@@ -252,7 +262,8 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
     __shared__ A swave[WG / 64];
     __shared__ A swin[WMAX > 0 ? WMAX : 1];
     const int tid = threadIdx.x;
-    const int id = remap_tile(blockIdx.x, a.ntiles, a.xcd_remap);
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
     if (!TILED) {
         const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
         if (d.y >= 0) multi_row_block<WG, NPT, SPLIT, 0>(a, d, sprod, sptr, swin, 0, 0);
@@ -284,6 +295,30 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
 // groups of k (one lane per right-hand side) and each group sums whole rows,
 // reading one contiguous row of X per nonzero.
 
+// sum over z = z0, z0 + step, ... < z1 of a_z * X[col_z, j]: eight nonzeros
+// per round, so that the eight index/value loads and then the eight gathers
+// of X rows are in flight together instead of one dependent chain per
+// nonzero
+__device__ __forceinline__ double spmm_dot(const BatchMat &M, int32_t z0, int32_t z1, int32_t step, int j) {
+    double sum = 0.0;
+    int32_t z = z0;
+    for (; z + 7 * step < z1; z += 8 * step) {
+        int32_t c[8];
+        double v[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c[u] = M.colidx[z + u * step];
+            v[u] = M.vals[z + u * step];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = M.X[(int64_t)c[u] * M.ldx + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sum += v[u] * xv[u];
+    }
+    for (; z < z1; z += step) sum += M.vals[z] * M.X[(int64_t)M.colidx[z] * M.ldx + j];
+    return sum;
+}
+
 template <int WG>
 __device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it, double *red) {
     const int tid = threadIdx.x;
@@ -295,12 +330,8 @@ __device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it,
         // a group of k lanes per row: lane j sums a_z * X[col_z, j] over the
         // row; the k lanes read one contiguous row of X per nonzero
         if (g < ngroups)
-            for (int32_t r = s_lo + g; r < s_hi; r += ngroups) {
-                const int32_t a0 = M.slot_ptr[r], a1 = M.slot_ptr[r + 1];
-                double sum = 0.0;
-                for (int32_t z = a0; z < a1; ++z) sum += M.vals[z] * M.X[(int64_t)M.colidx[z] * M.ldx + j];
-                M.Y[(int64_t)r * M.ldy + j] = sum;
-            }
+            for (int32_t r = s_lo + g; r < s_hi; r += ngroups)
+                M.Y[(int64_t)r * M.ldy + j] = spmm_dot(M, M.slot_ptr[r], M.slot_ptr[r + 1], 1, j);
         return;
     }
     // a segment of a long row: the groups share its nonzeros, their sums meet
@@ -308,9 +339,7 @@ __device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it,
     // (see long_row_segment)
     __shared__ uint32_t last;
     double sum = 0.0;
-    if (g < ngroups)
-        for (int32_t z = z_lo + g; z < z_hi; z += ngroups)
-            sum += M.vals[z] * M.X[(int64_t)M.colidx[z] * M.ldx + j];
+    if (g < ngroups) sum = spmm_dot(M, z_lo + g, z_hi, ngroups, j);
     if (g < ngroups) red[g * k + j] = sum;
     __syncthreads();
     if (tid < k) {
@@ -328,6 +357,7 @@ __device__ __forceinline__ void spmm_block(const BatchMat &M, const int32_t *it,
         __hip_atomic_store(&M.partials[(int64_t)(base + seg) * k + tid], sum, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the partial has landed
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
     __syncthreads();
     if (tid == 0)
@@ -443,7 +473,7 @@ __global__ void cg_update_kernel(const T *__restrict__ rr, const T *__restrict__
                                  T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ q, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const T alpha = *rr / *pq;
+        const T alpha = *pq != T(0) ? *rr / *pq : T(0);
         d[i] += alpha * p[i];
         r[i] -= alpha * q[i];
     }
@@ -454,7 +484,7 @@ template <class T>
 __global__ void cg_direction_kernel(const T *__restrict__ rr, const T *__restrict__ rr_new, T *__restrict__ p,
                                     const T *__restrict__ r, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = r[i] + (*rr_new / *rr) * p[i];
+    if (i < n) p[i] = r[i] + (*rr != T(0) ? *rr_new / *rr : T(0)) * p[i];
 }
 
 // x += scale * d (binary64 update)
@@ -538,19 +568,39 @@ __global__ __launch_bounds__(kStreamWG) void stream_copy_kernel(const v2d *__res
 // ----------------------------------------------------------------- launchers
 
 namespace {
+// Workgroups of a launch: one per unit, or with the XCD mapping 8 times the
+// largest number of units of a row group.  Groups hold nearly equal
+// nonzeros, but a row long enough to fill most of a group puts many
+// one-round segments into it; when the largest group has over 1.5 times the
+// mean number of units, the launch keeps the hardware order instead, so
+// that one XCD does not run most of the work.
+template <class V, class A>
+unsigned grid_of_units(SpmvArgsT<V, A> &a) {
+    if (!a.xcd_remap) return (unsigned)a.ntiles;
+    int mx = 0;
+    for (int g = 0; g < kXcdGroups; ++g) mx = std::max(mx, a.xcd_ptr[g + 1] - a.xcd_ptr[g]);
+    if (2 * kXcdGroups * (int64_t)mx > 3 * (int64_t)a.ntiles) {
+        a.xcd_remap = 0;
+        return (unsigned)a.ntiles;
+    }
+    return (unsigned)(kXcdGroups * mx);
+}
+
 template <int WG, int NPT, int WMAX, class V, class A>
-hipError_t launch_variant(const SpmvArgsT<V, A> &a, bool split, bool tiled, hipStream_t s) {
-    if (a.ntiles <= 0) return hipSuccess;
+hipError_t launch_variant(const SpmvArgsT<V, A> &a0, bool split, bool tiled, hipStream_t s) {
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
     if (WMAX == 0 && !tiled) {
         if (split)
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, 0, false, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, 0, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
         else
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, 0, false, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, 0, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
     } else {
         if (split)
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, WMAX, true, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, true, WMAX, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
         else
-            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, WMAX, true, V, A>), dim3(a.ntiles), dim3(WG), 0, s, a);
+            hipLaunchKernelGGL((spmv_blocks<WG, NPT, false, WMAX, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -581,6 +631,7 @@ struct Table<double, double> {
         {256, 4, 8192, launch_variant<256, 4, 8192, double, double>},
         {256, 4, 16384, launch_variant<256, 4, 16384, double, double>},
         {512, 4, 16384, launch_variant<512, 4, 16384, double, double>},
+        {1024, 4, 15360, launch_variant<1024, 4, 15360, double, double>},
     };
 };
 

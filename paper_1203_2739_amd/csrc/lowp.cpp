@@ -4,6 +4,8 @@
 // binary64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -14,21 +16,7 @@
 
 using namespace spx;
 
-namespace {
-
-// bfloat16 keeps the upper 16 bits of a binary32.  Round to nearest, ties to
-// even: the dropped half decides, and an exact half rounds to the even kept
-// pattern.  NaNs stay NaN (quiet bit set); a carry out of the mantissa
-// correctly steps the exponent (up to infinity).
-uint16_t bf16_of(float f) {
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    const uint32_t kept = u >> 16, dropped = u & 0xFFFFu;
-    if (std::isnan(f)) return (uint16_t)(kept | 0x0040u);
-    const bool up = dropped > 0x8000u || (dropped == 0x8000u && (kept & 1u));
-    return (uint16_t)(kept + (up ? 1u : 0u));
-}
-
+namespace spx {
 void check_lowp_plan(const spx_plan_s &P, int32_t prec, bool need_device) {
     if (prec != SPX_PREC_F32 && prec != SPX_PREC_BF16) fail(SPX_EINVAL, "precision must be SPX_PREC_F32 or SPX_PREC_BF16");
     if (P.form == SPX_FORM_SPLIT) fail(SPX_EUNSUPPORTED, "the precision mode takes plain, SB or DB plans");
@@ -51,6 +39,7 @@ SpmvArgsT<V, float> lowp_args(const spx_plan_s &P, const V *vals, const float *x
     a.tiles = (const int32_t *)P.d_tiles->ptr;
     a.ntiles = (int32_t)(P.blk_desc.size() / 4);
     a.xcd_remap = P.tune.xcd_remap;
+    std::copy(P.xcd_blk_ptr.begin(), P.xcd_blk_ptr.end(), a.xcd_ptr);
     a.n = P.n;
     a.long_seg_ptr = (const int32_t *)P.d_long_seg_ptr->ptr;
     a.partials = (double *)P.d_partials->ptr;
@@ -64,6 +53,23 @@ hipError_t run_lowp(const spx_plan_s &P, int32_t prec, const float *x, float *y,
         return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s);
     return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s);
 }
+}  // namespace spx
+
+namespace {
+
+// bfloat16 keeps the upper 16 bits of a binary32.  Round to nearest, ties to
+// even: the dropped half decides, and an exact half rounds to the even kept
+// pattern.  NaNs stay NaN (quiet bit set); a carry out of the mantissa
+// correctly steps the exponent (up to infinity).
+uint16_t bf16_of(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t kept = u >> 16, dropped = u & 0xFFFFu;
+    if (std::isnan(f)) return (uint16_t)(kept | 0x0040u);
+    const bool up = dropped > 0x8000u || (dropped == 0x8000u && (kept & 1u));
+    return (uint16_t)(kept + (up ? 1u : 0u));
+}
+
 
 // Device workspace of one solve.
 struct Work {
@@ -85,6 +91,14 @@ T read_scalar(const T *dev, hipStream_t s) {
     hip_check(hipStreamSynchronize(s), "scalar copy");
     return h;
 }
+
+// Iterations between two reads of the residual norm by the host: each read
+// waits for the stream, so reading every iteration would leave the GPU idle
+// for a launch round trip per iteration.  The solve may therefore run up to
+// kCheckEvery - 1 iterations past the first one that meets its tolerance
+// (each only lowers the residual further; the update and direction kernels
+// take a zero step once the residual or the curvature is exactly zero).
+constexpr int32_t kCheckEvery = 8;
 
 // Inner CG on A_low d = rhs with rhs = r / scale, in precision T, to relative
 // residual inner_tol; d ends in w.v[3].  Returns the iterations taken.
@@ -109,10 +123,12 @@ int32_t inner_cg(spx_plan_s &P, int32_t prec, Work &w, double scale, double inne
         hip_check(launch_cg_update<T>(&sc[cur], &sc[2], d, rl, p, q, n, s), "cg update");
         hip_check(launch_dot<T>(rl, rl, n, part, &sc[1 - cur], s), "cg dot");
         hip_check(launch_cg_direction<T>(&sc[cur], &sc[1 - cur], p, rl, n, s), "cg direction");
-        rr = read_scalar(&sc[1 - cur], s);
         cur = 1 - cur;
         ++it;
-        if (!std::isfinite((double)rr)) break;
+        if (it % kCheckEvery == 0 || it == max_inner) {
+            rr = read_scalar(&sc[cur], s);
+            if (!std::isfinite((double)rr)) break;
+        }
     }
     return it;
 }

@@ -9,8 +9,10 @@
 //    (cut-net metric), which sends row i to the row border R_B.  Bound:
 //    Theorem 2.
 //  * Row-column-net model (Section 4.1): nonzeros are vertices, rows and
-//    columns are unit-cost nets under the connectivity metric.  Bound:
-//    Corollary 4.
+//    columns are nets under the connectivity metric.  Bound: Corollary 4,
+//    which weighs rows and columns alike (cost 1 each); the split weighs a
+//    row net kSplitRowNetCostDefault times a column net unless the caller
+//    gives another cost (see row_column_net).
 //
 // Each bisection is multilevel: matching-based coarsening that favours
 // vertices sharing many small nets (heavy connectivity), greedy growing
@@ -854,23 +856,21 @@ Sub column_net_of_rows(const CsrHost &A, const std::vector<int32_t> &rows) {
     return s;
 }
 
-// Cost of a row net in the row-column-net model of the split.  Corollary 4
-// counts a cut row and a cut column alike, as each bounds a cache miss.  On
-// the GPU they are not alike: a row shared by one more part costs a zeroed
-// y entry and an atomic add into it, while a column shared by one more part
-// costs one more read of an x entry that usually hits L2.  Weighting a row
-// net 32 times a column net, the split of the n = 10^6 irregular matrix at
-// K = 64 with 128 KB leaves has 1.55 M row slots instead of 4.71 M and its
-// product runs 1.48 times faster (1.12 times without leaves); weights from
-// 16 up give about the same.
-#ifndef SPX_SPLIT_ROW_NET_COST
-#define SPX_SPLIT_ROW_NET_COST 32
-#endif
-constexpr int64_t kSplitRowNetCost = SPX_SPLIT_ROW_NET_COST;
+// Cost of a row net in the row-column-net model of the split (the caller's
+// choice through spx_split_ex; spx_split uses kSplitRowNetCostDefault).
+// Corollary 4 counts a cut row and a cut column alike, as each bounds a
+// cache miss, which is cost 1.  On the GPU they are not alike: a row shared
+// by one more part costs a zeroed y entry and an atomic add into it, while a
+// column shared by one more part costs one more read of an x entry that
+// usually hits L2.  Weighting a row net 32 times a column net, the split of
+// the n = 10^6 irregular matrix at K = 64 with 128 KB leaves has 1.55 M row
+// slots instead of 4.71 M and its product runs 1.48 times faster (1.12 times
+// without leaves); weights from 16 up give about the same.
 
 // Row-column-net hypergraph of A: vertices are nonzeros (CSR order), nets
-// are the non-empty rows then the non-empty columns.
-Sub row_column_net(const CsrHost &A, bool enhanced) {
+// are the non-empty rows then the non-empty columns.  Row nets cost nnz(r)
+// in the enhanced model, row_cost otherwise.
+Sub row_column_net(const CsrHost &A, bool enhanced, int64_t row_cost) {
     Sub s;
     int64_t nnz = A.nnz;
     s.gid.resize(nnz);
@@ -883,7 +883,7 @@ Sub row_column_net(const CsrHost &A, bool enhanced) {
         if (d == 0) continue;
         for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s.H.pins.push_back(p);
         s.H.xpins.push_back((int64_t)s.H.pins.size());
-        s.H.nc.push_back(enhanced ? d : kSplitRowNetCost);
+        s.H.nc.push_back(enhanced ? d : row_cost);
         s.H.nrow.push_back(enhanced ? 1 : 0);
     }
     std::vector<int64_t> cptr((size_t)A.n + 1, 0);
@@ -1075,8 +1075,49 @@ void recurse(Ctx &C, Sub S, int32_t K, int32_t part, uint64_t path, int32_t dept
 
 }  // namespace
 
+// The row-net model of A is the column-net model of its transpose: the
+// columns of A are partitioned; then each row lands in the one part its
+// columns lie in, or in the row border (part K) when they lie in several
+// (empty rows join part 0).  Leaves are the parts.
+static PartitionResult partition_row_net(const CsrHost &A, int32_t K, uint64_t seed) {
+    auto t0 = std::chrono::steady_clock::now();
+    CsrHost At;
+    At.m = A.n;
+    At.n = A.m;
+    At.nnz = A.nnz;
+    At.rowptr.assign((size_t)A.n + 1, 0);
+    for (int64_t q = 0; q < A.nnz; ++q) At.rowptr[A.colidx[q] + 1]++;
+    for (int32_t j = 0; j < A.n; ++j) At.rowptr[j + 1] += At.rowptr[j];
+    At.colidx.resize(A.nnz);
+    {
+        std::vector<int32_t> fill(At.rowptr.begin(), At.rowptr.end() - 1);
+        for (int32_t i = 0; i < A.m; ++i)
+            for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) At.colidx[fill[A.colidx[q]]++] = i;
+    }
+    PartitionResult c = partition(At, Model::ColumnNet, K, 0, seed);
+    PartitionResult R;
+    R.part.assign(A.m, 0);
+    R.leaf.assign(A.m, 0);
+    for (int32_t i = 0; i < A.m; ++i) {
+        int32_t p = -1;
+        bool cut = false;
+        for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+            const int32_t pc = c.part[A.colidx[q]];
+            if (p < 0) p = pc;
+            else if (pc != p) cut = true;
+        }
+        R.part[i] = p < 0 ? 0 : (cut ? K : p);
+        R.leaf[i] = R.part[i] < K ? R.part[i] : -1;
+    }
+    R.nleaves = K;
+    R.cut = c.cut;
+    R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return R;
+}
+
 PartitionResult partition(const CsrHost &A, Model model, int32_t K, int64_t window_entries,
-                          uint64_t seed) {
+                          uint64_t seed, int64_t row_net_cost) {
+    if (model == Model::RowNet) return partition_row_net(A, K, seed);
     auto t0 = std::chrono::steady_clock::now();
     Ctx C;
     C.model = model;
@@ -1091,7 +1132,7 @@ PartitionResult partition(const CsrHost &A, Model model, int32_t K, int64_t wind
         std::iota(rows.begin(), rows.end(), 0);
         root = column_net_of_rows(A, rows);
     } else {
-        root = row_column_net(A, model == Model::ERowColumnNet);
+        root = row_column_net(A, model == Model::ERowColumnNet, row_net_cost);
     }
     recurse(C, std::move(root), K, 0, 0, 0, false);
 

@@ -7,6 +7,9 @@
 // single leaf goes with that leaf; one touched from several leaves of a
 // single part follows that part's leaf columns; every other column -- touched
 // from several parts, or from none -- forms the column border C_B at the end.
+// Inside a class, columns go by the set of row groups (kXcdGroups runs of
+// the stored rows with nearly equal nonzeros, one per XCD) that read them,
+// then by decreasing count, then by index.
 // The split orders rows the same way over the leaves of their nonzeros, with
 // rows spread over several leaves after all single-leaf rows and empty rows
 // last, so that the rows needing atomic accumulation form one range.
@@ -19,6 +22,12 @@
 #include "spx_internal.h"
 
 namespace spx {
+
+// Row group of a stored row whose nonzeros start at storage offset `start`:
+// the stored matrix is cut into kXcdGroups runs of nearly equal nonzeros.
+static inline int32_t group_of_start(int64_t start, int64_t nnz) {
+    return nnz > 0 ? (int32_t)((kXcdGroups * start) / nnz) : 0;
+}
 
 namespace {
 
@@ -56,12 +65,16 @@ struct ColClass {
     std::vector<uint8_t> multi_leaf, multi_part;
 };
 
-// Columns by class (leaf, part-shared, border), inside a class by decreasing
-// number of nonzeros, then by original index: the x entries gathered most
-// often share cache lines, so the hot part of x stays in L2.
+// Columns by class (leaf, part-shared, border); inside a class by the set of
+// row groups that read them (mask[j], bit g for group g, ascending as a
+// number), then by decreasing number of nonzeros, then by original index.
+// The kernel runs the blocks of row group g on XCD g, so a cache line of x
+// then holds entries read by the same XCDs, and among those the entries
+// gathered most often share lines.
 std::vector<int32_t> column_order(const CsrHost &A, int32_t K, int32_t nleaves,
                                   const std::vector<int32_t> &leaf_lo_of_part,
-                                  const ColClass &cc, int32_t &border_begin) {
+                                  const ColClass &cc, const std::vector<uint8_t> &mask,
+                                  int32_t &border_begin) {
     const int32_t n = A.n;
     std::vector<int32_t> bucket(n);
     for (int32_t j = 0; j < n; ++j) {
@@ -74,7 +87,11 @@ std::vector<int32_t> column_order(const CsrHost &A, int32_t K, int32_t nleaves,
     for (int64_t q = 0; q < A.nnz; ++q) deg[A.colidx[q]]++;
     std::vector<int32_t> by_deg(n);
     std::iota(by_deg.begin(), by_deg.end(), 0);
-    std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg[a] > deg[b]; });
+    std::sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) {
+        if (mask[a] != mask[b]) return mask[a] < mask[b];
+        if (deg[a] != deg[b]) return deg[a] > deg[b];
+        return a < b;
+    });
     // stable counting sort of the degree order by class
     std::vector<int64_t> off((size_t)nleaves + K + 2, 0);
     for (int32_t j = 0; j < n; ++j) off[bucket[j] + 1]++;
@@ -148,6 +165,31 @@ void plan_plain(spx_plan_s &P, const CsrHost &A) {
     P.col_border_begin = A.n;
 }
 
+// A_hat = P_r A P_c for orders given by the caller (new -> old), stored in
+// CSR with columns ascending inside rows; one leaf, no parts.
+void plan_from_perm(spx_plan_s &P, const CsrHost &A, const int32_t *row_perm, const int32_t *col_perm) {
+    auto t0 = std::chrono::steady_clock::now();
+    P.form = SPX_FORM_ORDER;
+    P.K = 1;
+    P.m = A.m;
+    P.n = A.n;
+    P.nnz = A.nnz;
+    P.row_perm.assign(row_perm, row_perm + A.m);
+    P.col_perm.assign(col_perm, col_perm + A.n);
+    std::vector<int32_t> inv_col(A.n);
+    for (int32_t t = 0; t < A.n; ++t) inv_col[P.col_perm[t]] = t;
+    permuted_rows(P, A, inv_col);
+    P.nleaves = 1;
+    P.leaf_slot_ptr = {0, A.m};
+    P.leaf_col_lo = {0};
+    P.leaf_col_hi = {0};
+    P.part_ptr = {0, A.m};
+    P.row_border_begin = A.m;
+    P.row_empty_begin = A.m;
+    P.col_border_begin = A.n;
+    P.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &r, bool db) {
     auto t0 = std::chrono::steady_clock::now();
     int32_t m = A.m, n = A.n, K = P.K;
@@ -191,8 +233,19 @@ void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &
             }
         }
     }
+    // row groups of the rows in their new order (border rows included)
+    std::vector<uint8_t> mask(n, 0);
+    {
+        int64_t run = 0;
+        for (int32_t t = 0; t < m; ++t) {
+            const int32_t i = P.row_perm[t];
+            const uint8_t bit = (uint8_t)(1u << group_of_start(run, A.nnz));
+            for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) mask[A.colidx[q]] |= bit;
+            run += A.rowptr[i + 1] - A.rowptr[i];
+        }
+    }
     int32_t cb = n;
-    P.col_perm = column_order(A, K, L, leaf_lo_of_part, cc, cb);
+    P.col_perm = column_order(A, K, L, leaf_lo_of_part, cc, mask, cb);
     P.col_border_begin = cb;
     std::vector<int32_t> inv_col(n);
     for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;
@@ -288,13 +341,8 @@ void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) 
             if (cc.first_leaf[j] != r.leaf[q]) cc.multi_leaf[j] = 1;
         }
     }
-    int32_t cb = n;
-    P.col_perm = column_order(A, K, L, leaf_lo_of_part, cc, cb);
-    P.col_border_begin = cb;
     std::vector<int32_t> inv_col(n), inv_row(m);
-    for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;
     for (int32_t t = 0; t < m; ++t) inv_row[P.row_perm[t]] = t;
-    // per-leaf GCSR: nonzeros grouped by leaf, then by (new row, new col)
     std::vector<int32_t> row_of(nnz);
     for (int32_t i = 0; i < m; ++i)
         for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) row_of[q] = i;
@@ -303,6 +351,33 @@ void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) 
     for (int32_t l = 0; l < L; ++l) loff[l + 1] += loff[l];
     std::vector<int64_t> key(nnz);
     std::vector<int32_t> src(nnz);
+    // stored rows (leaf, new row), leaf-major then by new row: the storage
+    // offset of each stored row gives the row group of its nonzeros
+    {
+        std::vector<int64_t> fill(loff.begin(), loff.end() - 1);
+        for (int64_t q = 0; q < nnz; ++q) {
+            int64_t o = fill[r.leaf[q]]++;
+            key[o] = ((int64_t)inv_row[row_of[q]] << 32) | (uint32_t)q;
+            src[o] = (int32_t)q;
+        }
+    }
+    parallel_for(L, [&](int64_t lo, int64_t hi) {
+        for (int64_t l = lo; l < hi; ++l) std::sort(key.begin() + loff[l], key.begin() + loff[l + 1]);
+    });
+    std::vector<uint8_t> mask(n, 0);
+    for (int32_t l = 0; l < L; ++l) {
+        int64_t start = loff[l];
+        for (int64_t o = loff[l]; o < loff[l + 1]; ++o) {
+            if (o > loff[l] && (key[o] >> 32) != (key[o - 1] >> 32)) start = o;
+            const int32_t q = (int32_t)(key[o] & 0xffffffff);
+            mask[A.colidx[q]] |= (uint8_t)(1u << group_of_start(start, nnz));
+        }
+    }
+    int32_t cb = n;
+    P.col_perm = column_order(A, K, L, leaf_lo_of_part, cc, mask, cb);
+    P.col_border_begin = cb;
+    for (int32_t t = 0; t < n; ++t) inv_col[P.col_perm[t]] = t;
+    // per-leaf GCSR: nonzeros grouped by leaf, then by (new row, new col)
     {
         std::vector<int64_t> fill(loff.begin(), loff.end() - 1);
         for (int64_t q = 0; q < nnz; ++q) {
@@ -370,6 +445,82 @@ void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r) 
 
 // ----------------------------------------------------------------- schedule
 
+// Densest range of at most W consecutive column indices among the stored
+// nonzeros [z0, z1): its first column, its length and the nonzeros it
+// serves (0, 0, 0 when empty).
+static void densest_window(const std::vector<int32_t> &colidx, int64_t z0, int64_t z1, int32_t W,
+                           std::vector<int32_t> &buf, int32_t &lo, int32_t &len, int64_t &served) {
+    lo = len = 0;
+    served = 0;
+    buf.assign(colidx.begin() + z0, colidx.begin() + z1);
+    std::sort(buf.begin(), buf.end());
+    size_t bi = 0, bj = 0, j = 0;
+    for (size_t i = 0; i < buf.size(); ++i) {
+        while (j < buf.size() && buf[j] < (int64_t)buf[i] + W) ++j;
+        if ((int64_t)(j - i) > served) {
+            served = (int64_t)(j - i);
+            bi = i;
+            bj = j;
+        }
+    }
+    if (served > 0) {
+        lo = buf[bi];
+        len = buf[bj - 1] + 1 - lo;
+    }
+}
+
+// Tiles per row group: the blocks [xb[g], xb[g+1]) of group g are cut into
+// T runs of nearly equal nonzeros (fewer when the group has fewer blocks),
+// each with the densest window of at most W columns among its nonzeros,
+// kept when it serves at least half as many gathers as it holds entries.
+static void group_tiles(spx_plan_s &P, const std::vector<int32_t> &xb, int32_t T, int32_t W) {
+    P.tiles.clear();
+    P.window_nnz = 0;
+    P.window_bytes_fill = 0;
+    auto bnz = [&](int32_t b) { return (int64_t)P.blk_desc[4 * (size_t)b + 3] - P.blk_desc[4 * (size_t)b + 2]; };
+    for (int g = 0; g < kXcdGroups; ++g) {
+        const int32_t b0 = xb[g], b1 = xb[g + 1];
+        if (b0 >= b1) continue;
+        int64_t total = 0;
+        for (int32_t b = b0; b < b1; ++b) total += bnz(b);
+        int64_t acc = 0;
+        int32_t start = b0, t = 1;
+        for (int32_t b = b0; b < b1; ++b) {
+            acc += bnz(b);
+            // close the tile once it reaches t/T of the group's nonzeros
+            if (b + 1 < b1 && acc * T >= total * t) {
+                P.tiles.insert(P.tiles.end(), {start, b + 1, 0, 0});
+                start = b + 1;
+                while (acc * T >= total * t) ++t;
+            }
+        }
+        P.tiles.insert(P.tiles.end(), {start, b1, 0, 0});
+    }
+    if (W <= 0) return;
+    const int32_t nt = (int32_t)(P.tiles.size() / 4);
+    std::vector<int64_t> served(nt, 0);
+    parallel_for(nt, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t t = lo; t < hi; ++t) {
+            int32_t *tl = &P.tiles[4 * (size_t)t];
+            const int64_t z0 = P.blk_desc[4 * (size_t)tl[0] + 2], z1 = P.blk_desc[4 * (size_t)(tl[1] - 1) + 3];
+            int32_t wlo, wlen;
+            int64_t sv;
+            densest_window(P.colidx, z0, z1, W, buf, wlo, wlen, sv);
+            if (sv > 0 && 2 * sv >= (int64_t)wlen) {
+                tl[2] = wlo;
+                tl[3] = wlen;
+                served[t] = sv;
+            }
+        }
+    });
+    for (int32_t t = 0; t < nt; ++t) {
+        P.window_nnz += served[t];
+        P.window_bytes_fill += 8 * (int64_t)P.tiles[4 * (size_t)t + 3];
+    }
+}
+
+
 // Lanes the kernel gives to each row of a block of nr rows: the largest
 // power of two <= wg / nr, at most a wave.
 static int32_t lanes_per_row(int32_t wg, int32_t nr) {
@@ -400,16 +551,35 @@ void build_schedule(spx_plan_s &P) {
     P.window_bytes_fill = 0;
     std::vector<std::pair<int32_t, int32_t>> units;
     std::vector<int32_t> unit_leaf;
-    for (int32_t l = 0; l < P.nleaves; ++l) {
-        units.emplace_back(P.leaf_slot_ptr[l], P.leaf_slot_ptr[l + 1]);
-        unit_leaf.push_back(l);
+    const int32_t nslots = (int32_t)P.slot_ptr.size() - 1;
+    const int64_t nnz_all = nslots > 0 ? P.slot_ptr[nslots] : 0;
+    // first slot of every row group; blocks and tiles never cross a group
+    std::vector<int32_t> gfirst(kXcdGroups + 1, nslots);
+    gfirst[0] = 0;
+    for (int g = 1; g < kXcdGroups; ++g) {
+        int32_t lo = 0, hi = nslots;  // first slot whose group is >= g
+        while (lo < hi) {
+            int32_t mid = lo + (hi - lo) / 2;
+            if (group_of_start(P.slot_ptr[mid], nnz_all) >= g) hi = mid;
+            else lo = mid + 1;
+        }
+        gfirst[g] = lo;
     }
-    int32_t nslots = (int32_t)P.slot_ptr.size() - 1;
+    auto add_unit = [&](int32_t s0, int32_t s1, int32_t leaf) {
+        for (int g = 0; g < kXcdGroups && s0 < s1; ++g) {
+            const int32_t cut = gfirst[g + 1];
+            if (cut > s0 && cut < s1) {
+                units.emplace_back(s0, cut);
+                unit_leaf.push_back(leaf);
+                s0 = cut;
+            }
+        }
+        units.emplace_back(s0, s1);
+        unit_leaf.push_back(leaf);
+    };
+    for (int32_t l = 0; l < P.nleaves; ++l) add_unit(P.leaf_slot_ptr[l], P.leaf_slot_ptr[l + 1], l);
     int32_t covered = P.nleaves ? P.leaf_slot_ptr[P.nleaves] : 0;
-    if (covered < nslots) {
-        units.emplace_back(covered, nslots);
-        unit_leaf.push_back(-1);
-    }
+    if (covered < nslots) add_unit(covered, nslots, -1);
     // a slot too long for a block of its own
     auto is_long = [&](int64_t len) {
         return len > span - 3 || (len + 63) / 64 > iters;
@@ -454,7 +624,7 @@ void build_schedule(spx_plan_s &P) {
         int32_t wlo = 0, wlen = 0;
         int32_t B = std::max(1, T.blocks_per_tile);
         int32_t l = unit_leaf[u];
-        if (T.window_entries > 0 && l >= 0 && last_blk > first_blk) {
+        if (T.window_entries > 0 && T.tiles_per_group == 0 && l >= 0 && last_blk > first_blk) {
             int64_t z0 = P.slot_ptr[s0], z1 = P.slot_ptr[s1];
             cols.assign(P.colidx.begin() + z0, P.colidx.begin() + z1);
             std::sort(cols.begin(), cols.end());
@@ -489,6 +659,21 @@ void build_schedule(spx_plan_s &P) {
     P.blk_slot.resize((size_t)nb + 1);
     for (int32_t b = 0; b < nb; ++b) P.blk_slot[b] = P.blk_desc[4 * (size_t)b];
     P.blk_slot[nb] = nslots;
+    // first block and first tile of every row group
+    auto group_ptr = [&](bool by_tile, std::vector<int32_t> &ptr) {
+        const int32_t nu = by_tile ? (int32_t)(P.tiles.size() / 4) : nb;
+        ptr.assign(kXcdGroups + 1, nu);
+        ptr[0] = 0;
+        int32_t g = 0;
+        for (int32_t u = 0; u < nu; ++u) {
+            const int32_t b = by_tile ? P.tiles[4 * (size_t)u] : u;
+            const int32_t ug = group_of_start(P.slot_ptr[P.blk_desc[4 * (size_t)b]], nnz_all);
+            while (g < ug) ptr[++g] = u;
+        }
+    };
+    group_ptr(false, P.xcd_blk_ptr);
+    if (T.tiles_per_group > 0) group_tiles(P, P.xcd_blk_ptr, T.tiles_per_group, T.window_entries);
+    group_ptr(true, P.xcd_tile_ptr);
 }
 
 }  // namespace spx

@@ -11,4 +11,9 @@ constexpr int kDefaultNpt = 4;
 // Default bound on the strided reduction loop of a row inside a block:
 // ceil(row length / lanes given to the row).
 constexpr int kReduceIters = 64;
+// Row groups: the stored rows (slots) are cut into this many runs of nearly
+// equal nonzeros (a slot starting at storage offset s is in group
+// floor(kXcdGroups * s / nnz)); the kernels run the blocks of group g on XCD
+// g of the MI355X, and the plans order columns by the groups that read them.
+constexpr int kXcdGroups = 8;
 }  // namespace spx

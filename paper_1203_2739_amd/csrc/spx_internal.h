@@ -47,7 +47,10 @@ struct CsrHost {
     std::vector<double> vals;
 };
 
-enum class Model { ColumnNet, ERowColumnNet, RowColumnNet };
+// RowNet: the row-net model of sHP_RN (columns are vertices, rows are nets;
+// Section 5.1), given as rows: a row whose columns lie in one part joins it,
+// a row reaching several parts goes to the row border (part K).
+enum class Model { ColumnNet, ERowColumnNet, RowColumnNet, RowNet };
 
 // Recursive bisection into K parts, optionally refined into leaves whose
 // window (distinct columns, plus distinct rows for the split) fits
@@ -61,8 +64,11 @@ struct PartitionResult {
     int64_t cut = 0;
     double seconds = 0.0;
 };
+// Cost of a row net of the split's row-column-net model relative to a
+// column net (1 each in Corollary 4).
+constexpr int64_t kSplitRowNetCostDefault = 32;
 PartitionResult partition(const CsrHost &A, Model model, int32_t K, int64_t window_entries,
-                          uint64_t seed);
+                          uint64_t seed, int64_t row_net_cost = kSplitRowNetCostDefault);
 
 int32_t num_threads();
 void set_num_threads(int32_t t);
@@ -79,10 +85,10 @@ DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream
 
 struct Tune {
     int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
-    int32_t xcd_remap = 1, reduce_iters = kReduceIters;
+    int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0;
 };
 Tune resolve_tune(const spx_tune *t, int form);
-inline bool tiled(const Tune &t) { return t.window_entries > 0 || t.blocks_per_tile > 1; }
+inline bool tiled(const Tune &t) { return t.window_entries > 0 || t.blocks_per_tile > 1 || t.tiles_per_group > 0; }
 
 }  // namespace spx
 
@@ -114,6 +120,7 @@ struct spx_plan_s {
     std::vector<int32_t> blk_desc;              // 4 per block: slot range, nonzero range
     std::vector<int32_t> tiles;                 // 4 per tile
     std::vector<int32_t> long_seg_ptr;          // [nlong+1] first partial-sum entry of each long slot
+    std::vector<int32_t> xcd_blk_ptr, xcd_tile_ptr;  // [kXcdGroups+1] first block / tile of each row group
     std::vector<float> vals32;                  // precision mode: values rounded to binary32
     std::vector<uint16_t> vals16;               // precision mode: binary32 values rounded to bfloat16
     int64_t window_nnz = 0, window_bytes_fill = 0;
@@ -134,4 +141,9 @@ void upload_schedule(spx_plan_s &P, void *stream);
 void plan_from_rowparts(spx_plan_s &P, const CsrHost &A, const PartitionResult &r, bool db);
 void plan_from_split(spx_plan_s &P, const CsrHost &A, const PartitionResult &r);
 void plan_plain(spx_plan_s &P, const CsrHost &A);
+void plan_from_perm(spx_plan_s &P, const CsrHost &A, const int32_t *row_perm, const int32_t *col_perm);
+// orderings.cpp: row and column orders (new -> old) of the comparison
+// orderings on the bipartite graph of A
+void order_bfs(const CsrHost &A, int32_t *row_perm, int32_t *col_perm);
+void order_rcm(const CsrHost &A, int32_t *row_perm, int32_t *col_perm);
 }  // namespace spx

@@ -1,88 +1,37 @@
-"""Learned choice of the SpMV form, K and schedule.
+"""Learned choice of the SpMV form, K and schedule: training and evaluation.
 
-The 24 choices are 6 schedules of plain CSR and the SB, DB and split forms
-(Sections 3 and 4) at K = 8, 16, 32, 64, 128, 256.  For each training matrix
-every choice is timed on the GPU (the label is the fastest), the 40 features
-come from :func:`paper_1203_2739_amd.features`, and the 40 -> 64 -> 64 -> 24
-network is trained by the library's own forward/backward and Adam kernels.
-Exhaustive timing is the fallback and the reference for the regret
-t(chosen) / t(best) - 1.
-
-The reordered forms at every K come from one K = 256 recursive bisection per
-model: bisection numbers parts so that part p of the K = 256 tree lies in
-part p >> (8 - log2 K) of the tree cut at K (the row border of DB stays the
-border), which gives the K-way partition that the same tree yields at that
-depth without partitioning again.
+The 24 choices (6 schedules of plain CSR, and the SB, DB and split forms of
+Sections 3 and 4 at K = 8 .. 256) live in the library (spx_choice_info), as
+do the exhaustive timing of every choice (spx_select_exhaustive: the label,
+the fallback and the judge of the regret t(chosen) / t(best) - 1) and the
+selection itself (spx_select / spx_select_features: features, normalisation,
+network forward, argmax).  This module holds what is training: the
+normalisation statistics of the training set, the label tolerance, and the
+loop that trains the 40 -> 64 -> 64 -> 24 network with the library's
+forward/backward and Adam kernels.
 """
 from __future__ import annotations
 
-import time
-
 import numpy as np
 
-from . import (Plan, features, from_csr, mlp_adam, mlp_forward, mlp_loss_grad, plan_from_parts, plan_plain,
-               reorder_db, reorder_sb, split, split_prepare_y, spmv, spmv_split, permute_x, MLP_PARAMS,
-               NCHOICES, NFEATURES)
-
-PLAIN_TILES = [dict(wg_size=128), dict(wg_size=64), dict(wg_size=256), dict(wg_size=128, nnz_per_block=1024),
-               dict(reduce_iters=16), dict(wg_size=512)]
-KS = [8, 16, 32, 64, 128, 256]
-CHOICES = [("plain", t) for t in PLAIN_TILES] + [(f, k) for f in ("sb", "db", "split") for k in KS]
-assert len(CHOICES) == NCHOICES
+from . import (choice_info, features, from_csr, mlp_adam, mlp_loss_grad, select_exhaustive, select_features,
+               MLP_PARAMS, NCHOICES, NFEATURES)
 
 
 def choice_name(c):
-    f, p = CHOICES[c]
-    return f"plain{PLAIN_TILES.index(p)}" if f == "plain" else f"{f}{p}"
+    form, K, tune = choice_info(c)
+    return f"plain{c}" if form == "plain" else f"{form}{K}"
 
 
-def _time_products(torch, run, warmup, steps):
-    for _ in range(warmup):
-        run()
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(steps):
-        run()
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / steps
-
-
-def measure(A, seed=0, warmup=2, steps=10):
+def measure(A, seed=0, reps=10):
     """Milliseconds per product of every choice on matrix A (a synth CSR),
-    and the host seconds of the three partitions."""
+    timed by the library, and the host seconds of the three partitions."""
     import torch
     M = from_csr(A)
     rng = np.random.default_rng(seed)
     x = torch.from_numpy(rng.uniform(-1, 1, A.n)).cuda()
     y = torch.empty(max(A.m, 1), dtype=torch.float64, device="cuda")
-    times = np.zeros(NCHOICES)
-    t0 = time.time()
-    trees = {"sb": reorder_sb(M, 256, 0, seed)[0].export_parts()[0],
-             "db": reorder_db(M, 256, 0, seed)[0].export_parts()[0],
-             "split": split(M, 256, 0, seed)[0].export_parts()[0]}
-    tpart = time.time() - t0
-    for c, (form, p) in enumerate(CHOICES):
-        if form == "plain":
-            P = plan_plain(M, tune=p)
-            times[c] = _time_products(torch, lambda: spmv(P, x, y), warmup, steps)
-            continue
-        a = trees[form]
-        shift = 8 - int(np.log2(p))
-        parts = np.where(a >= 256, p, a >> shift) if form == "db" else a >> shift
-        P, rp, cp = plan_from_parts(M, form, p, parts.astype(np.int32))
-        xh = torch.empty_like(x)
-        permute_x(P, x, xh)
-        if form == "split":
-            def run(P=P, xh=xh):
-                split_prepare_y(P, y)
-                spmv_split(P, xh, y, accumulate=2)
-        else:
-            def run(P=P, xh=xh):
-                spmv(P, xh, y)
-        times[c] = _time_products(torch, run, warmup, steps)
+    _, times, tpart = select_exhaustive(M, x, y, reps=reps, seed=seed)
     return times, tpart
 
 
@@ -144,12 +93,9 @@ def train(Xn, labels, epochs=400, batch=64, lr=3e-3, seed=0):
     return theta, curve
 
 
-def predict(theta, Xn):
-    import torch
-    Xd = torch.from_numpy(np.ascontiguousarray(Xn, dtype=np.float32)).cuda()
-    logits = torch.empty((Xd.shape[0], NCHOICES), dtype=torch.float32, device="cuda")
-    mlp_forward(theta, Xd, logits)
-    return logits.argmax(dim=1).cpu().numpy()
+def predict(theta, F, norm):
+    """The library's choice for every row of raw features F (spx_select_features)."""
+    return np.array([select_features(f, theta, norm.mu, norm.sd)[0] for f in F], dtype=np.int64)
 
 
 def regret(times, chosen):
@@ -176,12 +122,15 @@ def augment(F, T, tol=0.02):
     return np.concatenate(Xs), np.concatenate(ls).astype(np.int32)
 
 
-def fit(Fn, T, epochs=300, check_every=20, val_frac=0.2, tols=(0.0, 0.02), lrs=(1e-3, 3e-3), batch=32, seed=0):
+def fit(F, T, norm, epochs=300, check_every=20, val_frac=0.2, tols=(0.0, 0.02), lrs=(1e-3, 3e-3), batch=32,
+        seed=0):
     """Train on near-optimal labels with early stopping.  A held-back fifth of
-    the training matrices picks the label tolerance, the learning rate and
-    the epoch count (lowest mean regret); the network is then trained again
-    on every training matrix with that choice.  Returns (theta, settings,
+    the training matrices (raw features F, normalised by norm) picks the
+    label tolerance, the learning rate and the epoch count (lowest mean
+    regret of the library's choice); the network is then trained again on
+    every training matrix with that choice.  Returns (theta, settings,
     validation regret of every setting tried)."""
+    Fn = norm(F)
     rng = np.random.default_rng(seed)
     N = T.shape[0]
     perm = rng.permutation(N)
@@ -193,7 +142,7 @@ def fit(Fn, T, epochs=300, check_every=20, val_frac=0.2, tols=(0.0, 0.02), lrs=(
         for lr in lrs:
             for ep in range(check_every, epochs + 1, check_every):
                 theta, _ = train(X, lab, epochs=ep, batch=batch, lr=lr, seed=seed)
-                r = float(regret(T[va], predict(theta, Fn[va])).mean())
+                r = float(regret(T[va], predict(theta, F[va], norm)).mean())
                 tried.append({"tol": tol, "lr": lr, "epochs": ep, "val_regret": round(r, 5)})
                 if best is None or r < best[0]:
                     best = (r, tol, lr, ep)

@@ -18,5 +18,6 @@ from .generators import (  # noqa: F401
     gen_family,
     gen_vectors,
     gen_block_hidden,
+    gen_banded_like,
     csr_sha256,
 )

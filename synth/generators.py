@@ -421,3 +421,18 @@ def csr_sha256(A: CSR) -> str:
     h.update(np.ascontiguousarray(A.colidx, dtype=np.int32).tobytes())
     h.update(np.ascontiguousarray(A.vals, dtype=np.float64).tobytes())
     return h.hexdigest()
+
+
+def gen_banded_like(A: CSR) -> CSR:
+    """The banded stand-in of a matrix: the same row lengths and values, row
+    i of length d holding the d consecutive columns that start at
+    min(max(i - d // 2, 0), n - d).  Every row's entries sit next to its
+    diagonal, so a product's reads of x stay inside a band as wide as the
+    longest row: the rate it reaches is the kernel's rate without scattered
+    gathers."""
+    deg = np.diff(A.rowptr).astype(np.int64)
+    assert deg.size == 0 or int(deg.max()) <= A.n, "a row longer than the matrix is wide"
+    start = np.clip(np.arange(A.m, dtype=np.int64) - deg // 2, 0, np.maximum(A.n - deg, 0))
+    off = np.arange(A.nnz, dtype=np.int64) - np.repeat(A.rowptr[:-1].astype(np.int64), deg)
+    cols = (np.repeat(start, deg) + off).astype(np.int32)
+    return CSR(A.m, A.n, A.rowptr, cols, A.vals, {"banded_like": True})

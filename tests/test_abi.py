@@ -180,7 +180,13 @@ def check_schedule(P):
     assert inf["nlong_rows"] == nlong
     assert tiles[0, 0] == 0 and tiles[-1, 1] == inf["nblocks"]
     assert np.all(tiles[1:, 0] == tiles[:-1, 1]) and np.all(tiles[:, 1] > tiles[:, 0])
-    assert np.all(tiles[:, 1] - tiles[:, 0] <= max(1, inf["blocks_per_tile"]))
+    if inf["tiles_per_group"] == 0:
+        assert np.all(tiles[:, 1] - tiles[:, 0] <= max(1, inf["blocks_per_tile"]))
+    else:
+        # at most tiles_per_group tiles start in each row group
+        g_of_tile = (8 * sp[bd[tiles[:, 0], 0]]) // max(int(sp[-1]), 1)
+        assert np.all(np.bincount(g_of_tile, minlength=8) <= inf["tiles_per_group"])
+        assert np.all(np.diff(g_of_tile) >= 0)
     assert np.all(tiles[:, 3] >= 0) and np.all(tiles[:, 2] + tiles[:, 3] <= inf["n"])
     assert np.all(tiles[:, 3] <= max(inf["window_entries"], 0))
     if inf["form"] == 3 and inf["nleaves"] > 0:
@@ -192,16 +198,16 @@ def check_schedule(P):
 
 
 @pytest.mark.parametrize("K", [1, 2, 8])
-@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("form", ["sb", "db", "split", "rn"])
 def test_c1_plans_match_oracle(orc, form, K):
     A = gen_c1()
     M = spx.from_csr(A, device=False)
-    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split, "rn": spx.reorder_rn}[form]
     P, rp, cp, pp = fn(M, K, 0, 7)
     if form == "split":
         check_split(orc, A, P, rp, cp, pp, K)
     else:
-        check_rowparts(orc, A, P, rp, cp, pp, K, form == "db")
+        check_rowparts(orc, A, P, rp, cp, pp, K, form in ("db", "rn"))
     check_schedule(P)
 
 
@@ -275,19 +281,19 @@ def hidden_block_diag(seed, K, bs, deg=4):
     return CSR(n, n, rp, c2[o].astype(np.int32), rng.uniform(-1, 1, rows.size)), p
 
 
-@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("form", ["sb", "db", "split", "rn"])
 def test_hidden_block_diagonal_found(orc, form):
     """A block-diagonal matrix hidden by a symmetric permutation: the
     partitioner recovers the blocks, so the border is empty and
     sum_j lambda(c_j) = n (Theorems 1-3 at their minimum)."""
     A, _ = hidden_block_diag(4, 8, 400)
     M = spx.from_csr(A, device=False)
-    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split, "rn": spx.reorder_rn}[form]
     P, rp, cp, pp = fn(M, 8, 0, 1)
     inf = P.info()
     assert inf["col_border_begin"] == A.n
     assert inf["sum_lambda_col"] == A.n
-    if form == "db":
+    if form in ("db", "rn"):
         assert inf["border_row_nnz"] == 0
     if form == "split":
         assert inf["sum_lambda_row"] == A.m
@@ -361,7 +367,10 @@ def long_row_csr(lens, n, seed=0):
 @pytest.mark.parametrize("tune", [None, dict(wg_size=64), dict(wg_size=128, nnz_per_block=1024),
                                   dict(wg_size=256), dict(wg_size=512), dict(reduce_iters=1),
                                   dict(reduce_iters=64), dict(blocks_per_tile=5),
-                                  dict(window_entries=4096, blocks_per_tile=8)])
+                                  dict(window_entries=4096, blocks_per_tile=8),
+                                  dict(wg_size=512, tiles_per_group=3, window_entries=16384),
+                                  dict(wg_size=1024, tiles_per_group=2, window_entries=15360),
+                                  dict(wg_size=256, tiles_per_group=40)])
 def test_schedule_rules(tune):
     """Schedules of matrices mixing empty, short, long and multi-segment rows
     obey the block rules for every tune."""
@@ -477,3 +486,87 @@ def test_selector_labels_checked_before_launch():
             spx.mlp_loss_grad(th, X, torch.tensor(bad, dtype=torch.int32), loss, g)
     with pytest.raises(ValueError, match="labels"):
         spx.mlp_loss_grad(th, X, torch.tensor([0, 1], dtype=torch.int32), loss, g)
+
+
+def test_hand_worked_orders_from_the_library():
+    """The library's SB and DB plans of the hand-worked 8 x 6 example (see
+    the oracle's pins) carry exactly the orders worked out by hand: columns
+    by class, then by the set of row groups reading them, then by count."""
+    D = np.zeros((8, 6))
+    for i, cs in enumerate([[0, 1], [1], [0, 1, 2], [2], [3, 4], [3, 5], [4, 5], [2, 4, 5]]):
+        D[i, cs] = 1.0
+    r, c = np.nonzero(D)
+    rp = np.zeros(9, np.int64)
+    np.cumsum(np.bincount(r, minlength=8), out=rp[1:])
+    M = spx.from_csr(CSR(8, 6, rp, c.astype(np.int32), D[r, c]), device=False)
+    _, row_perm, col_perm = spx.plan_from_parts(M, "sb", 2, [0, 0, 0, 0, 1, 1, 1, 1])
+    assert list(row_perm) == list(range(8)) and list(col_perm) == [1, 0, 3, 4, 5, 2]
+    _, row_perm, col_perm = spx.plan_from_parts(M, "db", 2, [0, 0, 0, 0, 1, 1, 1, 2])
+    assert list(row_perm) == list(range(8)) and list(col_perm) == [1, 0, 2, 3, 4, 5]
+
+
+@pytest.mark.parametrize("cost,w,row_cut", [(1, 4, True), (4, 2, False), (4, 8, True), (100, 64, False)])
+def test_split_row_net_cost_is_a_parameter(orc, cost, w, row_cut):
+    """spx_split_ex weighs a row net `cost` column nets: on the bridged blocks
+    the joining row is kept whole while it would cut fewer than `cost`
+    columns, and cut otherwise; cost 1 is Corollary 4's objective as written
+    (rows and columns alike)."""
+    A = bridged_blocks(100, w)
+    M = spx.from_csr(A, device=False)
+    for seed in range(2):
+        P, rp, cp, part = spx.split(M, 2, 0, seed, row_net_cost=cost)
+        lr, lc = orc.lambda_split(A, part, 2)
+        assert int(lr[-1]) == (2 if row_cut else 1)
+        assert lc.sum() == 2 * w + (0 if row_cut else w)
+    with pytest.raises(spx.SpxError):
+        spx.split(M, 2, 0, 0, row_net_cost=0)
+
+
+def test_comparison_orderings_match_oracle(orc):
+    """sBFS and sRCM (Section 5.1) from the library equal the oracle's
+    independent orders bit for bit, on matrices with several components,
+    empty rows and empty columns; the order plan stores A[row_perm][:, col_perm]."""
+    from synth import gen_family
+    rng = np.random.default_rng(21)
+    E, _ = (None, None)
+    D = (rng.random((60, 70)) < 0.04).astype(float)
+    D[5] = 0.0
+    D[:, 9] = 0.0
+    r, c = np.nonzero(D)
+    rp = np.zeros(61, np.int64)
+    np.cumsum(np.bincount(r, minlength=60), out=rp[1:])
+    sparse = CSR(60, 70, rp, c.astype(np.int32), rng.uniform(-1, 1, r.size))
+    for A in (gen_c1(), gen_family("F2", 3, 2000), gen_family("F3", 4, 3000), sparse):
+        M = spx.from_csr(A, device=False)
+        for name in ("bfs", "rcm"):
+            lr, lc = getattr(spx, "order_" + name)(M)
+            orr, oc = getattr(orc, "order_" + name)(A)
+            assert np.array_equal(lr, orr) and np.array_equal(lc, oc), (name, A.m)
+        P = spx.plan_from_perm(M, lr, lc)
+        assert P.info()["form_name"] == "order"
+        orp, oci, ov = orc.permute_csr(A, lr, lc)
+        rp_, ci_, v_ = P.export_csr()
+        assert np.array_equal(rp_, orp) and np.array_equal(ci_, oci) and np.array_equal(v_, ov)
+        check_schedule(P)
+    M = spx.from_csr(sparse, device=False)
+    with pytest.raises(spx.SpxError):
+        spx.plan_from_perm(M, np.zeros(60, np.int32), np.arange(70))
+
+
+def test_row_net_border_rows_are_the_cut_rows(orc):
+    """sHP_RN: a row lies in the row border exactly when its columns lie in
+    more than one column part; the parts the plan gives the other rows put
+    all of a row's columns in that part's column block (Eq. 5 with an empty
+    column border among part rows)."""
+    from synth import gen_family
+    A = gen_family("F3", 11, 3000)
+    M = spx.from_csr(A, device=False)
+    P, rp, cp, pp = spx.reorder_rn(M, 8, 0, 2)
+    r2p, _ = P.export_parts()
+    rows = np.repeat(np.arange(A.m), np.diff(A.rowptr))
+    inner = r2p[rows] < 8
+    # every column read by part rows is read by part rows of one part only
+    cols, parts = A.colidx[inner], r2p[rows[inner]]
+    pairs = np.unique(cols.astype(np.int64) * 16 + parts)
+    assert np.unique(pairs // 16).size == pairs.size
+    check_rowparts(orc, A, P, rp, cp, pp, 8, True)

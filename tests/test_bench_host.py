@@ -80,3 +80,18 @@ def test_rocprof_summary_tool(tmp_path, capsys):
                      "Dispatch_Id": 2}])
     rs.pmc(str(pmc), "kern")
     assert "FETCH_SIZE=20.0 (n=2)" in capsys.readouterr().out
+
+
+def test_cpu_baseline_legs_agree_and_report_cores():
+    """Both host legs run on a small matrix: the oracle on one thread and
+    the OpenMP product on every core give identical results (checked inside)
+    and report their thread counts and the CPU model."""
+    import bench
+    from synth import gen_c1, gen_vectors
+    bench.build_cpu_leg()
+    A = gen_c1()
+    xs = gen_vectors(9, A.n, 4)
+    out = bench.cpu_baseline(A, xs, budget_s=0.5, max_products=5)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0
+    assert out["cpu_model"] and out["host_cpus"] >= 1
+    assert out["all_cores"]["cores"] >= 1 and out["all_cores"]["value"] > 0

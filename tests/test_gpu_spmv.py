@@ -32,7 +32,7 @@ def run_plain(A, x, tune=None):
 
 def run_reordered(A, x, form, K, window_bytes=0, tune=None, seed=0):
     M = spx.from_csr(A)
-    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split, "rn": spx.reorder_rn}[form]
     P, rp, cp, part = fn(M, K, window_bytes, seed, tune=tune)
     xh = dev(x[cp])
     yh = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
@@ -49,7 +49,9 @@ TUNES = [None,
          dict(reduce_iters=1, wg_size=256),
          dict(blocks_per_tile=2, xcd_remap=-1),
          dict(wg_size=128, nnz_per_block=1024, reduce_iters=7, blocks_per_tile=200),
-         dict(wg_size=128, nnz_per_block=1024, xcd_remap=-1)]
+         dict(wg_size=128, nnz_per_block=1024, xcd_remap=-1),
+         dict(wg_size=256, tiles_per_group=5),
+         dict(wg_size=1024, tiles_per_group=4, window_entries=15360)]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -65,7 +67,7 @@ def test_plain_c1_integer_exact(orc):
     assert np.array_equal(run_plain(A, x), orc.spmv(A, x))
 
 
-@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("form", ["sb", "db", "split", "rn"])
 @pytest.mark.parametrize("K", [1, 8])
 def test_reordered_c1(orc, form, K):
     A = gen_c1()
@@ -77,7 +79,7 @@ def test_reordered_c1(orc, form, K):
         assert_close_rowwise(y, ys[rp], orc.abs_rowsum(A, x)[rp], "split vs part order")
 
 
-@pytest.mark.parametrize("form", ["sb", "db", "split"])
+@pytest.mark.parametrize("form", ["sb", "db", "split", "rn"])
 def test_reordered_c1_integer_exact(orc, form):
     A, x = integer_problem(gen_c1(), 9)
     y, rp, cp, part, P = run_reordered(A, x, form, 8)
@@ -88,7 +90,10 @@ WINDOW_TUNES = [dict(window_entries=4096, blocks_per_tile=64, wg_size=128),
                 dict(window_entries=4096, blocks_per_tile=64, wg_size=256),
                 dict(window_entries=8192, blocks_per_tile=32),
                 dict(window_entries=16384, blocks_per_tile=16),
-                dict(window_entries=16384, wg_size=512, blocks_per_tile=32)]
+                dict(window_entries=16384, wg_size=512, blocks_per_tile=32),
+                dict(window_entries=16384, wg_size=512, tiles_per_group=1),
+                dict(window_entries=15360, wg_size=1024, tiles_per_group=1),
+                dict(window_entries=4096, wg_size=256, tiles_per_group=1)]
 
 
 @pytest.mark.parametrize("form", ["sb", "db", "split"])
@@ -306,3 +311,30 @@ def test_products_from_random_partitions(orc, form, K):
     yh = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
     spx.spmv(P, xh, yh)
     assert_close_rowwise(host(yh), orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], f"{form} K={K}")
+
+
+@pytest.mark.parametrize("name", ["bfs", "rcm"])
+def test_comparison_orderings_c1(orc, name):
+    """Products on the sBFS and sRCM orders (Section 5.1) in their reordered
+    space, against the oracle: within the per-entry bound, and bit for bit
+    on small integers."""
+    A = gen_c1()
+    M = spx.from_csr(A)
+    rp, cp = getattr(spx, "order_" + name)(M)
+    P = spx.plan_from_perm(M, rp, cp)
+    x = gen_vectors(107, A.n)[0]
+    xd = dev(x)
+    xh = torch.empty_like(xd)
+    spx.permute_x(P, xd, xh)
+    yh = torch.full((A.m,), np.nan, dtype=torch.float64, device="cuda")
+    spx.spmv(P, xh, yh)
+    assert_close_rowwise(host(yh), orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], name)
+    y = torch.empty_like(yh)
+    spx.unpermute_y(P, yh, y)
+    assert_close_rowwise(host(y), orc.spmv(A, x), orc.abs_rowsum(A, x), name + " unpermuted")
+    Ai, xi = integer_problem(A, 12)
+    Mi = spx.from_csr(Ai)
+    Pi = spx.plan_from_perm(Mi, rp, cp)
+    yi = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    spx.spmv(Pi, dev(xi[cp]), yi)
+    assert np.array_equal(host(yi), orc.spmv(Ai, xi)[rp])

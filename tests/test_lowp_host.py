@@ -93,7 +93,11 @@ def test_selector_host_logic():
     assert selector.best_fixed(T) == 2          # regrets 0.01 and 0: the best mean
     X, lab = selector.augment(np.eye(2, 40, dtype=np.float32), T, tol=0.02)
     assert sorted(lab[:2]) == [0, 2] and list(lab[2:]) == [2]
-    assert len(selector.CHOICES) == 24 and selector.choice_name(23) == "split256"
+    assert selector.choice_name(23) == "split256" and selector.choice_name(6) == "sb8"
+    assert [spx.choice_info(c)[0] for c in range(24)] == ["plain"] * 6 + ["sb"] * 6 + ["db"] * 6 + ["split"] * 6
+    assert [spx.choice_info(c)[1] for c in range(6, 24)] == [8, 16, 32, 64, 128, 256] * 3
+    with pytest.raises(spx.SpxError):
+        spx.choice_info(24)
     # part p of a K = 256 tree lies in part p >> (8 - log2 K) of the tree cut at K
     parts = np.arange(256)
     assert np.array_equal(np.unique(parts >> 5), np.arange(8))

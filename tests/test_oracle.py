@@ -255,31 +255,49 @@ def test_bounds_hand_worked():
 # -------------------------------------------------------- canonical orders
 
 def test_canonical_rowcol_hand_worked(orc):
-    """Same 4x5 matrix, SB with parts {row0,row1}, {row2,row3}, one leaf
-    per part.  Rows keep their order.  Columns: c1 only in part 0 -> C_1;
-    c3, c4 only in part 1 -> C_2; c0, c2 in both -> C_B.  Inside a class by
-    decreasing column count (c0, c1, c2, c4 have 2 nonzeros, c3 has 1), then
-    by index.  So the new column order is c1 | c4 c3 | c0 c2."""
-    D = np.zeros((4, 5))
-    for i, cs in enumerate([[0, 1], [1, 2], [2, 3, 4], [0, 4]]):
+    """Canonical orders of the SB and DB forms worked by hand (Eq. 1 and
+    Eq. 5 fix the blocks; inside them: class, then the set of row groups
+    reading a column, then decreasing count, then index).
+
+    8 x 6 matrix, 16 nonzeros, parts {r0..r3}, {r4..r7}, one leaf each:
+      r0: c0 c1 | r1: c1 | r2: c0 c1 c2 | r3: c2 | r4: c3 c4 | r5: c3 c5 |
+      r6: c4 c5 | r7: c2 c4 c5
+    Row starts 0 2 3 6 7 9 11 13 give row groups floor(8 s / 16) =
+    0 1 1 3 3 4 5 6.  Reader sets (bit g for group g): c0 {0,1} = 3,
+    c1 {0,1} = 3, c2 {1,3,6} = 74, c3 {3,4} = 24, c4 {3,5,6} = 104,
+    c5 {4,5,6} = 112.  SB classes: C_1 = {c0, c1}, C_2 = {c3, c4, c5},
+    C_B = {c2}.  In C_1 the sets tie, so the count decides (c1: 3 before
+    c0: 2, against index order); in C_2 the sets decide (c3 before c4, c5,
+    against count order)."""
+    D = np.zeros((8, 6))
+    for i, cs in enumerate([[0, 1], [1], [0, 1, 2], [2], [3, 4], [3, 5], [4, 5], [2, 4, 5]]):
         D[i, cs] = 1.0
     A = dense_to_csr(D)
-    c = orc.canonical_rowcol(A, [0, 0, 1, 1], [0, 0, 1, 1], 2)
-    assert list(c["row_perm"]) == [0, 1, 2, 3]
-    assert list(c["col_perm"]) == [1, 4, 3, 0, 2]
-    assert list(c["part_ptr"]) == [0, 2, 4, 4]
-    assert list(c["col_part_ptr"]) == [0, 1, 3, 5]
+    c = orc.canonical_rowcol(A, [0, 0, 0, 0, 1, 1, 1, 1], [0, 0, 0, 0, 1, 1, 1, 1], 2)
+    assert list(c["row_perm"]) == list(range(8))
+    assert list(c["col_perm"]) == [1, 0, 3, 4, 5, 2]
+    assert list(c["part_ptr"]) == [0, 4, 8, 8]
+    assert list(c["col_part_ptr"]) == [0, 2, 5, 6]
     orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
     assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2) == []
-    # DB with row 3 in the border: c4 is then touched by part 1 only
-    # among part rows, c0 only by part 0 -> c0 c1 | c4 c3 | c2 (counts over
-    # all of A, border rows included)
-    c = orc.canonical_rowcol(A, [0, 0, 1, 2], [0, 0, 1, 0], 2)
-    assert list(c["row_perm"]) == [0, 1, 2, 3]
-    assert list(c["col_perm"]) == [0, 1, 4, 3, 2]
+    # DB with r7 in the row border R_B: c2 is then read by part 0 only among
+    # part rows (C_1), while its reader set still counts r7's group (74):
+    # C_1 = c1 c0 (set 3) then c2 (set 74); C_2 = c3 c4 c5; C_B empty
+    c = orc.canonical_rowcol(A, [0, 0, 0, 0, 1, 1, 1, 2], [0, 0, 0, 0, 1, 1, 1, 0], 2)
+    assert list(c["row_perm"]) == list(range(8))
+    assert list(c["col_perm"]) == [1, 0, 2, 3, 4, 5]
+    assert list(c["col_part_ptr"]) == [0, 3, 6, 6]
     orp, oci, _ = orc.permute_csr(A, c["row_perm"], c["col_perm"])
     assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2, db=True) == []
     assert orc.check_sb(orp, oci, c["part_ptr"], c["col_part_ptr"], 2, db=False) != []
+    # 4 x 5 matrix, 9 nonzeros: r0: c0 c1 | r1: c1 c2 | r2: c2 c3 c4 | r3: c0 c4,
+    # parts {r0, r1}, {r2, r3}; groups 0 1 3 6; sets c0 65, c1 3, c2 10, c3 8,
+    # c4 72: C_1 = c1 | C_2 = c3 c4 | C_B = c2 c0 (sets 10 < 65, against index)
+    D = np.zeros((4, 5))
+    for i, cs in enumerate([[0, 1], [1, 2], [2, 3, 4], [0, 4]]):
+        D[i, cs] = 1.0
+    c = orc.canonical_rowcol(dense_to_csr(D), [0, 0, 1, 1], [0, 0, 1, 1], 2)
+    assert list(c["col_perm"]) == [1, 3, 4, 2, 0]
 
 
 def test_check_sb_flags_violation(orc):
@@ -367,34 +385,37 @@ def _split_example():
 
 
 def test_canonical_split_hand_worked(orc):
-    """Exact orders of the split (Section 4; the order inside the forms is
-    the reading that groups rows and columns by class, then by decreasing
-    column count, then by index), worked by hand on _split_example.
+    """Exact orders of the split (Section 4; inside the forms rows and
+    columns go by class, columns then by the set of row groups that read
+    them, then by decreasing count, then by index), worked by hand on
+    _split_example.
 
     Rows: single-leaf rows by leaf (r4 | r6 | r0 | r7), not by index; then
     rows shared by leaves of one part, by part (r5 of part 0 before r1 of
     part 1), before the row shared by both parts (r3); the empty row r2 last.
 
-    Columns: c1, c5 only in leaf 0 (counts 1, 2); c3 only in leaf 2; c6, c7
-    in leaves 2 and 3 of part 1 (counts 2, 3); c0, c2, c4 in both parts
-    (counts 2, 2, 3).  Classes: leaf 0 | leaf 2 | part-1 shared | border,
-    each by decreasing count then index: c5 c1 | c3 | c7 c6 | c4 c0 c2."""
+    Stored rows, leaf-major (new row numbers: r4 0, r6 1, r0 2, r7 3, r5 4,
+    r1 5, r3 6, r2 7) start at offsets 0 2 3 | 4 5 | 6 10 | 11 13 16 of the
+    17 nonzeros: row groups floor(8 s / 17) = 0 0 1 | 1 2 | 2 4 | 5 6 7.
+    Columns (class; reader set; count): c1 (leaf 0; 1; 1), c5 (leaf 0; 1; 2),
+    c3 (leaf 2; 20; 2), c6 (part 1 shared; 68; 2), c7 (part 1 shared; 100; 3),
+    c0 (border; 6; 2), c2 (border; 68; 2), c4 (border; 162; 3).  Order:
+    c5 c1 (sets tie: count) | c3 | c6 c7 (sets, against count) | c0 c2 c4."""
     A, part, leaf = _split_example()
     c = orc.canonical_split(A, part, leaf, 2)
     assert list(c["row_perm"]) == [4, 6, 0, 7, 5, 1, 3, 2]
     assert c["row_shared_begin"] == 4 and c["row_empty_begin"] == 7
-    assert list(c["col_perm"]) == [5, 1, 3, 7, 6, 4, 0, 2]
+    assert list(c["col_perm"]) == [5, 1, 3, 6, 7, 0, 2, 4]
     assert list(c["col_part_ptr"]) == [0, 2, 5, 8]
-    # per-leaf GCSR in the new coordinates (rows: r4->0, r6->1, r0->2,
-    # r7->3, r5->4, r1->5, r3->6, r2->7; columns: c5->0, c1->1, c3->2,
-    # c7->3, c6->4, c4->5, c0->6, c2->7), each leaf's non-empty rows
+    # per-leaf GCSR in the new coordinates (columns: c5->0, c1->1, c3->2,
+    # c6->3, c7->4, c0->5, c2->6, c4->7), each leaf's non-empty rows
     # ascending, entries by new column
     g = orc.split_gcsr(A, leaf, 4, c["row_perm"], c["col_perm"])
     assert list(g["leaf_slot_ptr"]) == [0, 3, 5, 7, 10]
     assert list(g["slot_row"]) == [0, 4, 6, 1, 4, 2, 5, 3, 5, 6]
     assert list(g["slot_ptr"]) == [0, 2, 3, 4, 5, 6, 10, 11, 13, 16, 17]
-    assert list(g["colidx"]) == [0, 1, 0, 6, 5, 7, 2, 3, 4, 6, 2, 3, 5, 3, 4, 7, 5]
-    assert list(g["vals"]) == [46, 42, 56, 31, 65, 53, 4, 8, 7, 1, 14, 78, 75, 18, 17, 13, 35]
+    assert list(g["colidx"]) == [0, 1, 0, 5, 7, 6, 2, 3, 4, 5, 2, 4, 7, 3, 4, 6, 7]
+    assert list(g["vals"]) == [46, 42, 56, 31, 65, 53, 4, 7, 8, 1, 14, 78, 75, 17, 18, 13, 35]
 
 
 # ------------------------------------------------------------ precision
@@ -571,3 +592,79 @@ def test_features_closed_forms(orc):
 def test_degree_bins_edges(orc):
     d = np.array([0, 1, 2, 3, 4, 7, 8, 2**13, 2**14 - 1, 2**14, 10**6])
     assert list(orc.degree_bin(d)) == [0, 1, 2, 2, 3, 3, 4, 14, 14, 15, 15]
+
+
+# ------------------------------------------------- comparison orderings (Sec. 5.1)
+
+def test_bfs_order_vs_scipy_breadth_first():
+    """sBFS on a connected matrix is scipy's breadth-first order of the
+    bipartite graph (rows 0..m-1, columns m..m+n-1) from vertex 0, whose
+    neighbours it takes in ascending order; on several components each
+    starts at its smallest vertex."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order, connected_components
+    import oracle as orc
+    for A in (gen_c1(), gen_uniform_zipf(7, 3000, 9000, 50)):
+        m, n = A.m, A.n
+        S = sp.csr_matrix((np.ones(A.nnz), A.colidx, A.rowptr), shape=(m, n))
+        G = sp.bmat([[None, S], [S.T, None]]).tocsr()
+        G.sort_indices()
+        ncomp, lab = connected_components(G, directed=False)
+        seq = []
+        for comp in range(ncomp):
+            v = int(np.flatnonzero(lab == comp)[0])
+            seq.append(breadth_first_order(G, v, directed=False, return_predecessors=False))
+        seq = np.concatenate([seq[i] for i in np.argsort([s.min() for s in seq])])
+        r, c = orc.order_bfs(A)
+        assert np.array_equal(r, seq[seq < m]) and np.array_equal(c, seq[seq >= m] - m)
+
+
+def test_bfs_and_rcm_hand_worked(orc):
+    """Two 3 x 3 matrices worked by hand (vertices r0 r1 r2 = 0 1 2, c0 c1
+    c2 = 3 4 5).
+
+    First: r0: c1 | r1: c0 c2 | r2: c2.  Components {0, 4}, {1, 3, 5, 2}.
+    BFS: 0 4 | 1 3 5 2.  RCM: component {0, 4} starts at 0; component
+    {1, 2, 3, 5} at its least-degree vertex 2 (degrees 2: 1, 3: 1; 2 < 3),
+    whose last level {3} does not reach further; Cuthill-McKee 0 4 | 2 5 1 3,
+    reversed 3 1 5 2 4 0.
+
+    Second: r0: c1 | r1: c0 c1 | r2: c1 c2, a path c0-r1-c1-r2-c2 with r0
+    hanging from c1.  The least-degree vertex 0 has eccentricity 3 (4
+    levels); from the least-degree vertex 3 of its last level {3, 5} the
+    search has 5 levels, so George and Liu's search moves to 3, and from 5
+    (last level of 3) it stays at 5 levels: start 3.  Cuthill-McKee 3 1 4
+    0 2 5 (0 before 2: degree 1 < 2), reversed 5 2 0 4 1 3.  Starting at 0
+    instead would give 5 3 2 1 4 0."""
+    A = CSR(3, 3, np.array([0, 1, 3, 4]), np.array([1, 0, 2, 2], np.int32), np.ones(4))
+    r, c = orc.order_bfs(A)
+    assert list(r) == [0, 1, 2] and list(c) == [1, 0, 2]
+    r, c = orc.order_rcm(A)
+    assert list(r) == [1, 2, 0] and list(c) == [0, 2, 1]
+    B = CSR(3, 3, np.array([0, 1, 3, 5]), np.array([1, 0, 1, 1, 2], np.int32), np.ones(5))
+    r, c = orc.order_bfs(B)
+    assert list(r) == [0, 1, 2] and list(c) == [1, 0, 2]
+    r, c = orc.order_rcm(B)
+    assert list(r) == [2, 0, 1] and list(c) == [2, 1, 0]
+
+
+def test_rcm_recovers_a_hidden_band(orc):
+    """A banded matrix (bandwidth 3) hidden by random row and column
+    permutations: the sRCM orders bring every nonzero back within a few
+    positions of the diagonal of the reordered matrix (the envelope
+    reduction RCM exists for), while the hidden order spreads them."""
+    rng = np.random.default_rng(3)
+    n = 400
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in range(max(0, i - 3), min(n, i + 4)):
+            D[i, j] = 1.0
+    pr, pc = rng.permutation(n), rng.permutation(n)
+    A = dense_to_csr(D[pr][:, pc])
+    r, c = orc.order_rcm(A)
+    assert sorted(r) == list(range(n)) and sorted(c) == list(range(n))
+    orp, oci, _ = orc.permute_csr(A, r, c)
+    rows = np.repeat(np.arange(n), np.diff(orp))
+    assert np.max(np.abs(rows - oci)) <= 8
+    rows0 = np.repeat(np.arange(n), np.diff(A.rowptr))
+    assert np.max(np.abs(rows0 - A.colidx)) > 100
