@@ -230,6 +230,26 @@ def plan_sha256(rp, cp, parts, nleaves):
     return h.hexdigest()
 
 
+def tune_list(t):
+    """A schedule dict as the bench line's tune list."""
+    return [t.get("wg_size", 0), t.get("nnz_per_block", 0), t.get("blocks_per_tile", 1),
+            t.get("window_entries", -1) or -1, t.get("tiles_per_group", 0), t.get("wave_blocks", 0)]
+
+
+def schedule_name(tune):
+    """Short name of a schedule [wg, nnz_per_block, blocks_per_tile, window,
+    tiles_per_group, wave_blocks]: threads x nonzeros per thread (per lane
+    for wave blocks, marked w), then tiles per row group (t) and the LDS
+    window (W) when used."""
+    wg, nb, _, win, tpg, wave = (list(tune) + [0, 0])[:6]
+    name = f"{wg}x{nb // (64 if wave else wg)}" + ("w" if wave else "")
+    if tpg:
+        name += f"t{tpg}"
+    if win and win > 0:
+        name += f"W{win}"
+    return name
+
+
 def measured_traffic(form, nnz, sched, plan):
     """HBM bytes per launch of the SpMV kernel of this form from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
@@ -237,7 +257,7 @@ def measured_traffic(form, nnz, sched, plan):
     schedule or plan layout, or the kernel source changed after the counters
     were taken."""
     from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256
-    path = os.path.join(ROOT, "profiles", f"spmv_blocks_c2_{form}_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"spmv_c2_{form}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -510,7 +530,7 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tune", default="",
-                    help="wg,nnz_per_block[,blocks_per_tile,window_entries,tiles_per_group]")
+                    help="wg,nnz_per_block[,blocks_per_tile,window_entries,tiles_per_group,wave_blocks]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
@@ -577,7 +597,7 @@ def main():
     tune = None
     if args.tune:
         f = [int(v) for v in args.tune.split(",")]
-        keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group"]
+        keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group", "wave_blocks"]
         tune = dict(zip(keys, f))
 
     results = {}
@@ -610,8 +630,9 @@ def main():
             # schedule autotuning by the library (as OSKI tunes its kernel):
             # ten products per candidate schedule, the fastest is kept
             t = time.time()
-            spx.plan_autotune(P, xf[0], y, reps=10)
-            log(f"{form}: autotune {time.time() - t:.1f} s")
+            _, _, cand = spx.plan_autotune(P, xf[0], y, reps=10, report=True)
+            log(f"{form}: autotune {time.time() - t:.1f} s, ms per candidate "
+                + " ".join(f"{schedule_name(tune_list(c))}={v:.4f}" for c, v in zip(spx.autotune_candidates(), cand)))
         inf = P.info()
         plan_key = "identity" if form in ("plain", "banded") else plan_sha256(rp, cp, parts, inf["nleaves"])
         total_ms, kern_ms = time_form(spx, torch, P, form, xf, y, args.warmup, args.steps)
@@ -624,7 +645,7 @@ def main():
              "sum_lambda_col": inf["sum_lambda_col"], "sum_lambda_row": inf["sum_lambda_row"],
              "border_row_nnz": inf["border_row_nnz"], "bytes_matrix": inf["bytes_matrix"],
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
-                      inf["window_entries"], inf["tiles_per_group"]],
+                      inf["window_entries"], inf["tiles_per_group"], inf["wave_blocks"]],
              "window_nnz": inf["window_nnz"],
              "plan_sha256": plan_key}
         if args.cold:
@@ -682,9 +703,9 @@ def main():
         out["speedup_vs_plain"] = round(results["plain"]["ms_per_step"] / hb["ms_per_step"], 3)
     out["roofline"] = {"bound": "hbm", "achieved": hb["kernel_GBs"], "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": round(hb["kernel_GBs"] / PEAK_HBM_GBS, 4),
-                       "traffic": measured_traffic(best, A.nnz, f"{hb['tune'][0]}x{hb['tune'][1] // hb['tune'][0]}",
-                                                  hb["plan_sha256"]),
-                       "kernel": f"spmv_blocks ({best})",
+                       "traffic": measured_traffic(best, A.nnz, schedule_name(hb["tune"]), hb["plan_sha256"]),
+                       "kernel": f"{'spmv_waves' if hb['tune'][5] else 'spmv_blocks'} ({best}, "
+                                 f"{schedule_name(hb['tune'])})",
                        "alg_bytes_per_launch": nb}
     if not args.no_stream:
         out["stream_read_GBs"] = round(stream_ceiling(spx, torch), 1)

@@ -87,7 +87,16 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    T near the number of workgroups resident on an XCD the
  *                    launch is persistent and each window is loaded once.
  *                    wg_size 1024 is available only in this mode with a
- *                    window (at most 15360 entries).
+ *                    window (at most 15360 entries), or with wave_blocks.
+ *   wave_blocks      0 (default): a row block is run by a whole workgroup.
+ *                    1: blocks are sized for one 64-lane wave (at most 64
+ *                    slots, nnz_per_block = 256 or 512, i.e. 4 or 8
+ *                    nonzeros per lane, default 256) and each wave of a
+ *                    workgroup runs the blocks of the workgroup's tile in
+ *                    turn with no workgroup barrier after the window load;
+ *                    wg_size 256, 512 or 1024; tiles hold blocks_per_tile
+ *                    blocks (default wg_size / 64) or come from
+ *                    tiles_per_group.
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
@@ -98,7 +107,7 @@ typedef struct spx_tune_s {
     int32_t xcd_remap;
     int32_t reduce_iters;
     int32_t tiles_per_group;
-    int32_t reserved;
+    int32_t wave_blocks;
 } spx_tune;
 
 /* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
@@ -125,6 +134,7 @@ typedef struct spx_plan_info_s {
     int32_t reduce_iters;     /* bound on the per-row reduction loop of a block */
     int32_t nlong_rows;       /* slots too long for one block, run as one-round segments */
     int32_t tiles_per_group;  /* tiles of every row group (0: tiles follow leaves) */
+    int32_t wave_blocks;      /* 1: blocks sized for and run by single waves */
 } spx_plan_info;
 
 const char *spx_last_error(void);
@@ -272,7 +282,9 @@ spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
  * SPX_PREC_BF16: the low-precision product of spx_spmv_lowp on binary32
  * vectors, over the candidates without tiles (spx_plan_add_lowp first).
  * The plan keeps the fastest schedule; *chosen (may be NULL) receives it
- * and *ms (may be NULL) its mean milliseconds per product.  y is
+ * and *ms (may be NULL) its mean milliseconds per product; cand_ms (host,
+ * one entry per candidate, may be NULL) receives every candidate's mean
+ * milliseconds (-1 for candidates the precision does not run).  y is
  * overwritten.  Synchronizes the device between candidates; not
  * thread-safe against other products on the plan.  SPX_ENODEVICE for a
  * host-only plan, SPX_EINVAL for reps < 1 or a NULL vector. */
@@ -281,7 +293,7 @@ spx_status spx_plan_retune(spx_plan P, const spx_tune *tune);
  * receives candidate i (in the order they are tried). */
 int32_t spx_autotune_candidate(int32_t i, spx_tune *out);
 spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void *y, int32_t reps,
-                             spx_tune *chosen, float *ms, void *stream);
+                             spx_tune *chosen, float *ms, float *cand_ms, void *stream);
 /* spx_plan_destroy frees the plan's host and device memory.  Work queued
  * on a stream that reads the plan (products, permutations, batches built on
  * it) must have completed first: synchronize that stream before destroying. */

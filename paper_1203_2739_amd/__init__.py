@@ -34,7 +34,7 @@ class Tune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("nnz_per_block", ctypes.c_int32),
                 ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
-                ("tiles_per_group", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -50,7 +50,7 @@ class PlanInfo(ctypes.Structure):
                 ("bytes_window", ctypes.c_int64), ("window_nnz", ctypes.c_int64),
                 ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32),
-                ("tiles_per_group", ctypes.c_int32)]
+                ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -71,13 +71,12 @@ _SIGS = {
     "spx_split_ex": ([_VP, _I32, _I64, ctypes.c_uint64, _I32, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_reorder_rn": ([_VP, _I32, ctypes.c_uint64, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_plan_retune": ([_VP, _VP], _I32),
-    "spx_plan_autotune": ([_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
+    "spx_plan_autotune": ([_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP, _VP], _I32),
     "spx_autotune_candidate": ([_I32, _VP], _I32),
     "spx_choice_info": ([_I32, _VP, _VP, _VP], _I32),
     "spx_order_bfs": ([_VP, _VP, _VP], _I32),
     "spx_order_rcm": ([_VP, _VP, _VP], _I32),
     "spx_plan_from_perm": ([_VP, _VP, _VP, _VP, _VP], _I32),
-    "spx_mlp_loss_grad_noalloc": ([_VP, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
     "spx_select": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_select_features": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_plan_for_choice": ([_VP, _I32, ctypes.c_uint64, _VP, _VP, _VP], _I32),
@@ -440,7 +439,7 @@ def plan_retune(P: Plan, tune=None):
 
 
 _TUNE_FIELDS = ("wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "xcd_remap", "reduce_iters",
-                "tiles_per_group")
+                "tiles_per_group", "wave_blocks")
 
 
 def autotune_candidates():
@@ -454,19 +453,23 @@ def autotune_candidates():
     return out
 
 
-def plan_autotune(P: Plan, x, y, reps=10, precision="f64", stream=None):
+def plan_autotune(P: Plan, x, y, reps=10, precision="f64", stream=None, report=False):
     """Time the library's candidate schedules on x -> y and keep the fastest
     (binary64 products, or the "f32"/"bf16" products on binary32 vectors).
-    Returns (schedule dict, milliseconds per product)."""
+    Returns (schedule dict, milliseconds per product), plus with report=True
+    the milliseconds of every candidate (-1: not run)."""
     import torch
     m, n, _ = P.mat_dims
     prec = {"f64": 0}.get(precision, _PREC.get(precision, precision))
     dt = torch.float64 if prec == 0 else torch.float32
     t = make_tune()
     ms = ctypes.c_float()
+    nc = int(lib().spx_autotune_candidate(-1, None))
+    cm = np.empty(max(nc, 1), np.float32)
     _check(lib().spx_plan_autotune(P.handle, int(prec), _dev(x, dt, n), _dev(y, dt, m), int(reps),
-                                   ctypes.byref(t), ctypes.byref(ms), _stream(stream)))
-    return {f: getattr(t, f) for f in _TUNE_FIELDS}, ms.value
+                                   ctypes.byref(t), ctypes.byref(ms), _hp(cm), _stream(stream)))
+    chosen = {f: getattr(t, f) for f in _TUNE_FIELDS}
+    return (chosen, ms.value, cm[:nc].tolist()) if report else (chosen, ms.value)
 
 
 def spmv(P: Plan, x, y, stream=None):
@@ -679,23 +682,6 @@ def mlp_loss_grad(theta, X, labels, loss, grad, stream=None):
     _check(lib().spx_mlp_loss_grad(_dev(theta, torch.float32, MLP_PARAMS), _dev(X, torch.float32, B * NFEATURES),
                                    _dev(labels, torch.int32, B), int(B), _dev(loss, torch.float32, 1),
                                    _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
-
-
-def mlp_loss_grad_noalloc(theta, X, labels, loss, grad, stream=None):
-    """mlp_loss_grad through the entry point that allocates nothing (batches of
-    at most 512 samples share one fixed device workspace per GPU)."""
-    import torch
-    B = X.shape[0]
-    if labels.numel() < B:
-        raise ValueError(f"{labels.numel()} labels for {B} samples")
-    if 0 < B <= 512:
-        lo, hi = int(labels[:B].min()), int(labels[:B].max())
-        if lo < 0 or hi >= NCHOICES:
-            raise ValueError(f"labels must lie in [0, {NCHOICES}), got [{lo}, {hi}]")
-    _check(lib().spx_mlp_loss_grad_noalloc(_dev(theta, torch.float32, MLP_PARAMS),
-                                           _dev(X, torch.float32, B * NFEATURES), _dev(labels, torch.int32, B),
-                                           int(B), _dev(loss, torch.float32, 1),
-                                           _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
 
 
 def mlp_adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -20,6 +20,7 @@ hipError_t run_product(spx_plan_s &P, const double *x, double *y, int32_t accumu
 // values of that precision (check_lowp_plan).
 hipError_t run_lowp(const spx_plan_s &P, int32_t prec, const float *x, float *y, hipStream_t s);
 void check_lowp_plan(const spx_plan_s &P, int32_t prec, bool need_device);
+bool lowp_schedule_ok(const Tune &t);
 // A plan of form SB, DB or split from a given partition, scheduled with
 // `tune` (NULL: default) and uploaded when A is on the device.
 spx_plan_s *plan_from_partition(const spx_mat_s &A, int form, int32_t K, const PartitionResult &r,

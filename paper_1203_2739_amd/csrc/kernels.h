@@ -63,14 +63,19 @@ int batch_grid();  // workgroups that are resident at once on the device
 
 // One workgroup of wg threads per tile (tiled) or per block (not tiled);
 // ntiles counts workgroups.  npt = nonzeros staged per thread.
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out);
+// wave = true: the wave-block kernel (tiles of wave-sized blocks, each wave
+// of a workgroup running its own blocks); npt is then the nonzeros per lane.
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave = false);
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s);
+                       hipStream_t s, bool wave = false);
 // Low-precision products (binary32 or bfloat16 values, binary32 x, y and
-// accumulation), untiled schedules only.
+// accumulation): untiled workgroup blocks, or wave blocks without a window.
 bool spmv_lowp_variant_exists(int wg, int npt, int window_entries);
-hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s);
-hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s);
+bool spmv_lowp_wave_variant_exists(int wg, int npt);
+hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s,
+                           bool wave = false);
+hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s,
+                            bool wave = false);
 // Precision-mode vector kernels (see spx_cg_ir).  Dot products write their
 // result to *out (device) using part[dot_groups(n)] as scratch.
 int dot_groups(int64_t n);

@@ -139,11 +139,28 @@ __device__ __forceinline__ A group_sum_unrolled(A v, int g) {
     return v;
 }
 
-// One multi-row block: whole slots [d.x, d.y) with nonzeros [d.z, d.w).
-template <int WG, int NPT, bool SPLIT, int WMAX, class V, class A>
+// Orders the LDS writes of the lanes before the reads that follow.  A
+// workgroup block needs a barrier; a wave block (WAVE) only needs the
+// compiler to keep its LDS accesses in order, since one wave's LDS
+// instructions execute in issue order.
+template <bool WAVE>
+__device__ __forceinline__ void block_sync() {
+    if (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// One multi-row block: whole slots [d.x, d.y) with nonzeros [d.z, d.w), run
+// by the WG threads of a workgroup (tid = threadIdx.x) or, with WAVE, by the
+// 64 lanes of one wave (WG = 64, tid = lane) on the wave's own LDS slices.
+template <int WG, int NPT, bool SPLIT, int WMAX, bool WAVE = false, class V, class A>
 __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const v4i d, A *sprod, int32_t *sptr,
-                                                const A *swin, int32_t wlo, int32_t wlen) {
-    const int tid = threadIdx.x;
+                                                const A *swin, int32_t wlo, int32_t wlen,
+                                                const int tid = threadIdx.x) {
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
     const int32_t zb = d.z & ~3;
     const int32_t nr = d.y - d.x;  // at most WG (schedule)
@@ -168,7 +185,7 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
     }
     if (tid <= nr) sptr[tid] = rp0 - zb;
     if (nr == WG && tid == 0) sptr[WG] = rp1 - zb;
-    __syncthreads();
+    block_sync<WAVE>();
     // lanes per row: the largest power of two <= WG / nr, at most 64
     const int q = WG / nr;
     const int lg = q >= 64 ? 6 : 31 - __builtin_clz(q);
@@ -189,10 +206,9 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
 // partial sum, and the workgroup that arrives last (counted by an atomic
 // counter) adds the partials in segment order, writes the slot and resets
 // the counter for the next product.
-template <int WG, int NPT, bool SPLIT, int WMAX, class V, class A>
+template <int WG, int NPT, bool SPLIT, int WMAX, bool WAVE = false, class V, class A>
 __device__ __forceinline__ void long_row_segment(const SpmvArgsT<V, A> &a, const v4i d, A *swave, const A *swin,
-                                                 int32_t wlo, int32_t wlen) {
-    const int tid = threadIdx.x;
+                                                 int32_t wlo, int32_t wlen, const int tid = threadIdx.x) {
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
     const int32_t zb = d.z & ~3;
     const int32_t G = (d.w - zb + 3) >> 2;
@@ -215,12 +231,18 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgsT<V, A> &a, const
         }
     }
     acc = group_sum_unrolled(acc, 64);
-    if ((tid & 63) == 0) swave[tid >> 6] = acc;
-    __syncthreads();
+    if (!WAVE) {
+        if ((tid & 63) == 0) swave[tid >> 6] = acc;
+        __syncthreads();
+    }
     if (tid == 0) {
         A part = 0;
+        if (WAVE) {
+            part = acc;
+        } else {
 #pragma unroll
-        for (int w = 0; w < WG / 64; ++w) part += swave[w];
+            for (int w = 0; w < WG / 64; ++w) part += swave[w];
+        }
         const int32_t lr = -1 - d.y;
         const int32_t base = a.long_seg_ptr[lr];
         const int32_t nseg = a.long_seg_ptr[lr + 1] - base;
@@ -282,6 +304,37 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
         if (d.y >= 0) multi_row_block<WG, NPT, SPLIT, WMAX>(a, d, sprod, sptr, swin, wlo, wlen);
         else long_row_segment<WG, NPT, SPLIT, WMAX>(a, d, swave, swin, wlo, wlen);
         __syncthreads();
+    }
+}
+
+// Wave blocks: every workgroup runs one tile (with its LDS window, loaded
+// once), and each of its waves takes the tile's blocks in turn -- wave w the
+// blocks first + w, first + w + WG/64, ... -- reducing rows on its own LDS
+// slices, so no workgroup barrier follows the window load.  A block is a
+// run of whole slots sized for one wave (at most 64 slots and 64 NPT
+// nonzeros from the aligned start), or one segment of a long slot.
+template <int WG, int NPT, bool SPLIT, int WMAX, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_waves(SpmvArgsT<V, A> a) {
+    constexpr int NW = WG / 64;
+    __shared__ A sprod[NW][NPT * 64];
+    __shared__ int32_t sptr[NW][65];
+    __shared__ A swin[WMAX > 0 ? WMAX : 1];
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
+    const v4i tl = reinterpret_cast<const v4i *>(a.tiles)[id];
+    const int32_t wlo = tl.z;
+    const int32_t wlen = WMAX > 0 ? tl.w : 0;
+    if (WMAX > 0 && wlen > 0) {
+        for (int i = threadIdx.x; i < wlen; i += WG) swin[i] = a.x[wlo + i];
+        __syncthreads();
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (int b = tl.x + w; b < tl.y; b += NW) {
+        const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[b];
+        if (d.y >= 0) multi_row_block<64, NPT, SPLIT, WMAX, true>(a, d, sprod[w], sptr[w], swin, wlo, wlen, lane);
+        else long_row_segment<64, NPT, SPLIT, WMAX, true>(a, d, sprod[w], swin, wlo, wlen, lane);
+        block_sync<true>();  // the next block rewrites this wave's slices
     }
 }
 
@@ -605,11 +658,59 @@ hipError_t launch_variant(const SpmvArgsT<V, A> &a0, bool split, bool tiled, hip
     return hipGetLastError();
 }
 
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_waves(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
+    if (split)
+        hipLaunchKernelGGL((spmv_waves<WG, NPT, true, WMAX, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((spmv_waves<WG, NPT, false, WMAX, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
     hipError_t (*fn)(const SpmvArgsT<V, A> &, bool, bool, hipStream_t);
 };
+
+// wave-block kernels: workgroup size, nonzeros per lane, window capacity
+// (LDS: WG/64 slices of 64 NPT products and 65 row offsets, plus the window);
+// the low precisions take the shapes without a window
+template <class V, class A>
+struct WaveTable;
+
+template <>
+struct WaveTable<double, double> {
+    static constexpr Variant<double, double> v[] = {
+        {256, 4, 0, launch_waves<256, 4, 0, double, double>},
+        {512, 4, 0, launch_waves<512, 4, 0, double, double>},
+        {1024, 4, 0, launch_waves<1024, 4, 0, double, double>},
+        {256, 8, 0, launch_waves<256, 8, 0, double, double>},
+        {512, 8, 0, launch_waves<512, 8, 0, double, double>},
+        {256, 4, 8192, launch_waves<256, 4, 8192, double, double>},
+        {512, 4, 16384, launch_waves<512, 4, 16384, double, double>},
+        {512, 8, 8192, launch_waves<512, 8, 8192, double, double>},
+        {1024, 4, 15360, launch_waves<1024, 4, 15360, double, double>},
+    };
+};
+
+template <class V>
+struct LowWaveTable {
+    static constexpr Variant<V, float> v[] = {
+        {256, 4, 0, launch_waves<256, 4, 0, V, float>},
+        {512, 4, 0, launch_waves<512, 4, 0, V, float>},
+        {1024, 4, 0, launch_waves<1024, 4, 0, V, float>},
+        {256, 8, 0, launch_waves<256, 8, 0, V, float>},
+        {512, 8, 0, launch_waves<512, 8, 0, V, float>},
+    };
+};
+template <>
+struct WaveTable<float, float> : LowWaveTable<float> {};
+template <>
+struct WaveTable<uint16_t, float> : LowWaveTable<uint16_t> {};
 
 // binary64: every schedule shape; low precision: the untiled shapes
 template <class V, class A>
@@ -652,6 +753,20 @@ template <>
 struct Table<uint16_t, float> : LowTable<uint16_t> {};
 
 template <class V, class A>
+bool find_wave_variant(int wg, int npt, int window_entries, int *wmax_out) {
+    int best = -1;
+    for (const auto &v : WaveTable<V, A>::v) {
+        if (v.wg != wg || v.npt != npt) continue;
+        if (window_entries <= 0 ? v.wmax == 0 : v.wmax >= window_entries) {
+            if (best < 0 || v.wmax < best) best = v.wmax;
+        }
+    }
+    if (best < 0) return false;
+    if (wmax_out) *wmax_out = best;
+    return true;
+}
+
+template <class V, class A>
 bool find_variant(int wg, int npt, int window_entries, int *wmax_out) {
     int best = -1;
     for (const auto &v : Table<V, A>::v) {
@@ -666,6 +781,16 @@ bool find_variant(int wg, int npt, int window_entries, int *wmax_out) {
 }
 
 template <class V, class A>
+hipError_t launch_wave_any(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entries, bool split,
+                           hipStream_t s) {
+    int wmax = 0;
+    if (!find_wave_variant<V, A>(wg, npt, window_entries, &wmax)) return hipErrorInvalidValue;
+    for (const auto &v : WaveTable<V, A>::v)
+        if (v.wg == wg && v.npt == npt && v.wmax == wmax) return v.fn(a, split, true, s);
+    return hipErrorInvalidValue;
+}
+
+template <class V, class A>
 hipError_t launch_any(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entries, bool tiled, bool split,
                       hipStream_t s) {
     int wmax = 0;
@@ -676,8 +801,13 @@ hipError_t launch_any(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entr
 }
 }  // namespace
 
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out) {
-    return find_variant<double, double>(wg, npt, window_entries, wmax_out);
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave) {
+    return wave ? find_wave_variant<double, double>(wg, npt, window_entries, wmax_out)
+                : find_variant<double, double>(wg, npt, window_entries, wmax_out);
+}
+
+bool spmv_lowp_wave_variant_exists(int wg, int npt) {
+    return find_wave_variant<float, float>(wg, npt, -1, nullptr);
 }
 
 bool spmv_lowp_variant_exists(int wg, int npt, int window_entries) {
@@ -685,15 +815,20 @@ bool spmv_lowp_variant_exists(int wg, int npt, int window_entries) {
 }
 
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s) {
+                       hipStream_t s, bool wave) {
+    if (wave) return launch_wave_any(a, wg, npt, window_entries, split, s);
     return launch_any(a, wg, npt, window_entries, tiled, split, s);
 }
 
-hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s) {
+hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s,
+                           bool wave) {
+    if (wave) return launch_wave_any(a, wg, npt, -1, split, s);
     return launch_any(a, wg, npt, -1, false, split, s);
 }
 
-hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s) {
+hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s,
+                            bool wave) {
+    if (wave) return launch_wave_any(a, wg, npt, -1, split, s);
     return launch_any(a, wg, npt, -1, false, split, s);
 }
 

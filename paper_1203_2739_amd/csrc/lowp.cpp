@@ -37,9 +37,12 @@ SpmvArgsT<V, float> lowp_args(const spx_plan_s &P, const V *vals, const float *x
     a.y = y;
     a.blk_desc = (const int32_t *)P.d_blk_desc->ptr;
     a.tiles = (const int32_t *)P.d_tiles->ptr;
-    a.ntiles = (int32_t)(P.blk_desc.size() / 4);
+    // workgroup blocks run untiled; wave blocks run the plan's tiles
+    const bool wave = P.tune.wave_blocks != 0;
+    a.ntiles = (int32_t)(wave ? P.tiles.size() / 4 : P.blk_desc.size() / 4);
     a.xcd_remap = P.tune.xcd_remap;
-    std::copy(P.xcd_blk_ptr.begin(), P.xcd_blk_ptr.end(), a.xcd_ptr);
+    const auto &gp = wave ? P.xcd_tile_ptr : P.xcd_blk_ptr;
+    std::copy(gp.begin(), gp.end(), a.xcd_ptr);
     a.n = P.n;
     a.long_seg_ptr = (const int32_t *)P.d_long_seg_ptr->ptr;
     a.partials = (double *)P.d_partials->ptr;
@@ -48,11 +51,16 @@ SpmvArgsT<V, float> lowp_args(const spx_plan_s &P, const V *vals, const float *x
 }
 
 hipError_t run_lowp(const spx_plan_s &P, int32_t prec, const float *x, float *y, hipStream_t s) {
-    const int wg = P.tune.wg, npt = P.tune.nnz_per_block / P.tune.wg;
+    const int wg = P.tune.wg, npt = P.tune.nnz_per_block / block_threads(P.tune);
+    const bool wave = P.tune.wave_blocks != 0;
     if (prec == SPX_PREC_F32)
-        return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s);
-    return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s);
+        return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s, wave);
+    return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s, wave);
 }
+
+// Schedules the precision mode runs: workgroup blocks without tiles, or
+// wave blocks without a window.
+bool lowp_schedule_ok(const Tune &t) { return t.wave_blocks ? t.window_entries <= 0 : !tiled(t); }
 }  // namespace spx
 
 namespace {
@@ -214,7 +222,8 @@ spx_status spx_spmv_lowp(spx_plan P, int32_t precision, const float *x, float *y
         check_lowp_plan(*P, precision, true);
         if (P->m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
         if (P->nnz > 0 && !x) fail(SPX_EINVAL, "x is NULL");
-        if (tiled(P->tune)) fail(SPX_EUNSUPPORTED, "the precision mode runs untiled schedules (blocks_per_tile 1, no window)");
+        if (!lowp_schedule_ok(P->tune))
+            fail(SPX_EUNSUPPORTED, "the precision mode runs untiled schedules or wave blocks without a window");
         hip_check(run_lowp(*P, precision, x, y, (hipStream_t)stream), "spmv_lowp launch");
     });
 }
@@ -230,7 +239,8 @@ spx_status spx_cg_ir(spx_plan P, int32_t precision, const double *b, double *x, 
         if (P->m != P->n) fail(SPX_EINVAL, "the matrix must be square");
         if (precision != SPX_PREC_F64) check_lowp_plan(*P, precision, true);
         if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");
-        if (tiled(P->tune)) fail(SPX_EUNSUPPORTED, "the solve runs untiled schedules (blocks_per_tile 1, no window)");
+        if (!lowp_schedule_ok(P->tune))
+            fail(SPX_EUNSUPPORTED, "the solve runs untiled schedules or wave blocks without a window");
         if (!(tol > 0) || !(inner_tol > 0) || max_outer < 1 || max_inner < 1)
             fail(SPX_EINVAL, "tol, inner_tol > 0 and max_outer, max_inner >= 1 required");
         if (P->n > 0 && (!b || !x)) fail(SPX_EINVAL, "NULL vector");

@@ -543,6 +543,7 @@ void build_schedule(spx_plan_s &P) {
     const Tune &T = P.tune;
     const int64_t span = T.nnz_per_block;
     const int32_t iters = T.reduce_iters;
+    const int32_t bt = block_threads(T);
     P.blk_slot.clear();
     P.blk_desc.clear();
     P.tiles.clear();
@@ -613,8 +614,8 @@ void build_schedule(spx_plan_s &P) {
             }
             const int64_t zb = P.slot_ptr[b_slo] & ~(int64_t)3;
             const int64_t lm = std::max(lmax, len);
-            const int32_t g = lanes_per_row(T.wg, nr + 1);
-            if (nr > 0 && (pe - zb > span || nr + 1 > T.wg || (lm + g - 1) / g > iters)) close(s);
+            const int32_t g = lanes_per_row(bt, nr + 1);
+            if (nr > 0 && (pe - zb > span || nr + 1 > bt || (lm + g - 1) / g > iters)) close(s);
             ++nr;
             lmax = std::max(lmax, len);
         }
@@ -622,7 +623,9 @@ void build_schedule(spx_plan_s &P) {
         int32_t last_blk = (int32_t)(P.blk_desc.size() / 4);
         // window of this unit
         int32_t wlo = 0, wlen = 0;
+        // tiles of blocks_per_tile blocks; wave blocks default to one per wave
         int32_t B = std::max(1, T.blocks_per_tile);
+        if (T.wave_blocks && T.blocks_per_tile <= 1) B = T.wg / 64;
         int32_t l = unit_leaf[u];
         if (T.window_entries > 0 && T.tiles_per_group == 0 && l >= 0 && last_blk > first_blk) {
             int64_t z0 = P.slot_ptr[s0], z1 = P.slot_ptr[s1];

@@ -85,10 +85,14 @@ DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream
 
 struct Tune {
     int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
-    int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0;
+    int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0, wave_blocks = 0;
 };
 Tune resolve_tune(const spx_tune *t, int form);
-inline bool tiled(const Tune &t) { return t.window_entries > 0 || t.blocks_per_tile > 1 || t.tiles_per_group > 0; }
+inline bool tiled(const Tune &t) {
+    return t.window_entries > 0 || t.blocks_per_tile > 1 || t.tiles_per_group > 0 || t.wave_blocks;
+}
+// Threads that run one row block: a wave in wave-block schedules.
+inline int32_t block_threads(const Tune &t) { return t.wave_blocks ? 64 : t.wg; }
 
 }  // namespace spx
 

@@ -12,17 +12,19 @@ using namespace spx;
 namespace spx {
 
 // Candidate schedules in the order they are tried: the one-block-per-
-// workgroup kernel at every workgroup size, then tiles per row group with an
-// LDS x window, sized so that the tiles of a group are about the workgroups
-// one XCD (32 CUs) keeps resident: one 1024- or 512-thread workgroup per CU
-// with a 120 or 128 KB window, two 256-thread workgroups with 64 KB.
+// workgroup kernel at every workgroup size; wave blocks at every workgroup
+// size; then wave blocks in tiles per row group with an LDS x window, sized
+// so that the tiles of a group are about the workgroups one XCD (32 CUs)
+// keeps resident: one 1024- or 512-thread workgroup per CU with a 120 or
+// 128 KB window, two 256-thread workgroups with 64 KB.
 const std::vector<spx_tune> &autotune_candidates() {
     static const std::vector<spx_tune> c = [] {
         std::vector<spx_tune> v;
-        auto add = [&v](int wg, int npt, int tiles = 0, int window = 0) {
+        auto add = [&v](int wg, int npt, int wave = 0, int tiles = 0, int window = 0) {
             spx_tune t{};
             t.wg_size = wg;
-            t.nnz_per_block = wg * npt;
+            t.nnz_per_block = (wave ? 64 : wg) * npt;
+            t.wave_blocks = wave;
             t.tiles_per_group = tiles;
             t.window_entries = window;
             v.push_back(t);
@@ -33,9 +35,13 @@ const std::vector<spx_tune> &autotune_candidates() {
         add(512, 4);
         add(128, 8);
         add(256, 8);
-        add(1024, 4, 32, 15360);
-        add(512, 4, 32, 16384);
-        add(256, 4, 64, 8192);
+        add(256, 4, 1);
+        add(512, 4, 1);
+        add(1024, 4, 1);
+        add(512, 8, 1);
+        add(1024, 4, 1, 32, 15360);
+        add(512, 4, 1, 32, 16384);
+        add(256, 4, 1, 64, 8192);
         return v;
     }();
     return c;
@@ -77,7 +83,7 @@ int32_t spx_autotune_candidate(int32_t i, spx_tune *out) {
 }
 
 spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void *y, int32_t reps,
-                             spx_tune *chosen, float *ms, void *stream) {
+                             spx_tune *chosen, float *ms, float *cand_ms, void *stream) {
     return guarded([&] {
         if (!P) fail(SPX_EINVAL, "NULL handle");
         if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy (host-only matrix)");
@@ -97,8 +103,11 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
         int best = -1;
         float best_ms = 0.0f;
         for (size_t c = 0; c < cands.size(); ++c) {
-            // the precision mode runs the one-block-per-workgroup schedules
-            if (precision != SPX_PREC_F64 && (cands[c].tiles_per_group > 0 || cands[c].window_entries > 0)) continue;
+            // the precision mode runs no tiles of workgroup blocks and no window
+            if (cand_ms) cand_ms[c] = -1.0f;
+            if (precision != SPX_PREC_F64 &&
+                (cands[c].window_entries > 0 || (!cands[c].wave_blocks && cands[c].tiles_per_group > 0)))
+                continue;
             retune_to(*P, cands[c]);
             for (int w = 0; w < 2; ++w) product();
             hip_check(hipEventRecord(ev.a, s), "event record");
@@ -108,6 +117,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
             float t = 0.0f;
             hip_check(hipEventElapsedTime(&t, ev.a, ev.b), "elapsed");
             t /= (float)reps;
+            if (cand_ms) cand_ms[c] = t;
             if (best < 0 || t < best_ms) {
                 best = (int)c;
                 best_ms = t;
@@ -123,6 +133,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
             chosen->xcd_remap = P->tune.xcd_remap ? 1 : -1;
             chosen->reduce_iters = P->tune.reduce_iters;
             chosen->tiles_per_group = P->tune.tiles_per_group;
+            chosen->wave_blocks = P->tune.wave_blocks;
         }
         if (ms) *ms = best_ms;
     });

@@ -2,9 +2,10 @@
 
   python -m paper_1203_2739_amd.rocprof_summary stats  <kernel_stats.csv>
   python -m paper_1203_2739_amd.rocprof_summary pmc    <counter_collection.csv> [name filter]
-  python -m paper_1203_2739_amd.rocprof_summary traffic <out dir> <form> <kernel filter> <nnz> <alg bytes> <plan sha256>
+  python -m paper_1203_2739_amd.rocprof_summary traffic <out dir> <form> <kernel filter> <nnz> <alg bytes> <plan sha256> <tune> <schedule>
 
-``traffic`` writes the summary that ``bench.py`` reads for roofline.traffic:
+``traffic`` writes the summary that ``bench.py`` reads for roofline.traffic
+(profiles/spmv_c2_<form>_traffic.txt):
 <out dir> holds the five runs listed in the summary (prof, pmcf, pmcw, calf,
 calw); FETCH_SIZE and WRITE_SIZE of the SpMV kernel are scaled by what they
 read for a copy kernel of 1 GiB.  <plan sha256> is the ``plan_sha256`` that
@@ -71,7 +72,10 @@ def _mean_by_kernel(path, filt):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(out, form, filt, nnz, alg, plan):
+def traffic(out, form, filt, nnz, alg, plan, tune, sched):
+    """Writes profiles/spmv_c2_<form>_traffic.txt from the five runs in <out>;
+    <tune> is the bench.py --tune argument the runs used and <sched> its
+    schedule name (bench.schedule_name)."""
     copy_kib = (1 << 30) / 1024
     calf = list(_mean_by_kernel(os.path.join(out, "calf", "pmc_counter_collection.csv"), "stream_copy").values())[0]
     calw = list(_mean_by_kernel(os.path.join(out, "calw", "pmc_counter_collection.csv"), "stream_copy").values())[0]
@@ -82,24 +86,23 @@ def traffic(out, form, filt, nnz, alg, plan):
     w_kib = wr[kname]
     st = [r for r in csv.DictReader(open(os.path.join(out, "prof", "run_kernel_stats.csv"))) if filt in r["Name"]][0]
     fb, wb = f_kib * 1024 * ff, w_kib * 1024 * fw
-    # workgroup size and nonzeros per thread from the kernel's template arguments
-    targs = kname.split("<", 1)[1].split(",")
-    sched = f"{int(targs[0])}x{int(targs[1])}"
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
-                        f"spmv_blocks_c2_{form}_traffic.txt")
+                        f"spmv_c2_{form}_traffic.txt")
+    args = f"--forms {form} --tune {tune} --no-cpu-baseline --no-stream"
     with open(path, "w") as o:
-        o.write(f"""SpMV kernel spmv_blocks ({form} form) on the n=10^6 irregular matrix (nnz={nnz}), K=64,
-schedule picked by bench.py's autotuning ({sched}: threads per workgroup x nonzeros per thread).
+        o.write(f"""SpMV kernel ({form} form) on the n=10^6 irregular matrix (nnz={nnz}), K=64, schedule {sched}
+(the one bench.py's autotuning picked: threads x nonzeros per thread, w = wave blocks,
+t = tiles per row group, W = LDS window entries).
 
 Commands (run from /tmp with TMPDIR=/tmp; R = repository root, OUT = output directory):
-  rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- python3 R/bench.py --forms {form} --steps 20 --warmup 3 --no-cpu-baseline --no-stream
-  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pmcf -o pmc -- python3 R/bench.py --forms {form} --steps 5 --warmup 1 --no-cpu-baseline --no-stream
-  rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmcw -o pmc -- python3 R/bench.py --forms {form} --steps 5 --warmup 1 --no-cpu-baseline --no-stream
+  rocprofv3 --kernel-trace --stats --output-format csv -d OUT/prof -o run -- python3 R/bench.py {args} --steps 20 --warmup 3
+  rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pmcf -o pmc -- python3 R/bench.py {args} --steps 5 --warmup 1
+  rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmcw -o pmc -- python3 R/bench.py {args} --steps 5 --warmup 1
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/calf -o pmc -- python3 R/bench.py --only-stream
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/calw -o pmc -- python3 R/bench.py --only-stream
-  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg} {plan}
+  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg} {plan} {tune} {sched}
 
-Kernel trace (--stats): {st['Name'][:90]}
+Kernel trace (--stats): {st['Name'][:100]}
   calls {st['Calls']}, mean {float(st['AverageNs']) / 1e3:.2f} us, min {float(st['MinNs']) / 1e3:.2f} us, max {float(st['MaxNs']) / 1e3:.2f} us
 
 Calibration on stream_copy_kernel of 1 GiB (reads 1 GiB, writes 1 GiB):
@@ -122,8 +125,9 @@ traffic_bytes_per_launch: {int(fb + wb)}
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 8 and sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]), sys.argv[7])
+    if len(sys.argv) >= 10 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]), sys.argv[7],
+                sys.argv[8], sys.argv[9])
         sys.exit(0)
     if len(sys.argv) < 3 or sys.argv[1] not in ("stats", "pmc"):
         print(__doc__)

@@ -138,6 +138,8 @@ def check_schedule(P):
     inf = P.info()
     bd, tiles = P.export_sched()
     nslots, NT, wg, it = inf["nslots"], inf["nnz_per_block"], inf["wg_size"], inf["reduce_iters"]
+    if inf["wave_blocks"]:
+        wg = 64  # a block is sized for one wave
     assert NT in (4 * wg, 8 * wg)
     if inf["form"] == 3:
         ex = P.export_split()
@@ -181,7 +183,10 @@ def check_schedule(P):
     assert tiles[0, 0] == 0 and tiles[-1, 1] == inf["nblocks"]
     assert np.all(tiles[1:, 0] == tiles[:-1, 1]) and np.all(tiles[:, 1] > tiles[:, 0])
     if inf["tiles_per_group"] == 0:
-        assert np.all(tiles[:, 1] - tiles[:, 0] <= max(1, inf["blocks_per_tile"]))
+        per_tile = inf["blocks_per_tile"]
+        if inf["wave_blocks"] and per_tile <= 1:
+            per_tile = inf["wg_size"] // 64
+        assert np.all(tiles[:, 1] - tiles[:, 0] <= max(1, per_tile))
     else:
         # at most tiles_per_group tiles start in each row group
         g_of_tile = (8 * sp[bd[tiles[:, 0], 0]]) // max(int(sp[-1]), 1)
@@ -370,7 +375,11 @@ def long_row_csr(lens, n, seed=0):
                                   dict(window_entries=4096, blocks_per_tile=8),
                                   dict(wg_size=512, tiles_per_group=3, window_entries=16384),
                                   dict(wg_size=1024, tiles_per_group=2, window_entries=15360),
-                                  dict(wg_size=256, tiles_per_group=40)])
+                                  dict(wg_size=256, tiles_per_group=40),
+                                  dict(wg_size=256, wave_blocks=1),
+                                  dict(wg_size=512, wave_blocks=1, nnz_per_block=512, reduce_iters=3),
+                                  dict(wg_size=512, wave_blocks=1, tiles_per_group=4, window_entries=16384),
+                                  dict(wg_size=512, wave_blocks=1, blocks_per_tile=3)])
 def test_schedule_rules(tune):
     """Schedules of matrices mixing empty, short, long and multi-segment rows
     obey the block rules for every tune."""

@@ -23,8 +23,10 @@ def test_traffic_lookup_checks_source_schedule_matrix_and_plan():
     import bench
     from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256
     keys = ("nnz", "schedule", "kernel_source_sha256", "plan_sha256", "traffic_bytes_per_launch")
-    for form in ("db", "split"):
-        path = os.path.join(ROOT, "profiles", f"spmv_blocks_c2_{form}_traffic.txt")
+    import glob
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "spmv_c2_*_traffic.txt")))
+    for path in paths:
+        form = os.path.basename(path)[len("spmv_c2_"):-len("_traffic.txt")]
         kv = {k: v.strip() for k, v in (line.split(": ", 1) for line in open(path).read().splitlines()
                                         if ": " in line and line.split(": ", 1)[0] in keys)}
         nnz, sched, plan = int(kv["nnz"]), kv["schedule"], kv.get("plan_sha256", "")
@@ -37,6 +39,14 @@ def test_traffic_lookup_checks_source_schedule_matrix_and_plan():
         assert bench.measured_traffic(form, nnz, "1x1", plan) is None
         assert bench.measured_traffic(form, nnz, sched, "0" * 64) is None
     assert bench.measured_traffic("no_such_form", 1, "1x1", "0" * 64) is None
+
+
+def test_schedule_names():
+    import bench
+    assert bench.schedule_name([512, 2048, 1, -1, 0, 0]) == "512x4"
+    assert bench.schedule_name([256, 256, 4, -1, 0, 1]) == "256x4w"
+    assert bench.schedule_name([1024, 256, 1, 15360, 32, 1]) == "1024x4wt32W15360"
+    assert bench.schedule_name([512, 2048, 1, 16384, 32, 0]) == "512x4t32W16384"
 
 
 def test_plan_hash_sees_every_part_of_the_layout():

@@ -51,7 +51,11 @@ TUNES = [None,
          dict(wg_size=128, nnz_per_block=1024, reduce_iters=7, blocks_per_tile=200),
          dict(wg_size=128, nnz_per_block=1024, xcd_remap=-1),
          dict(wg_size=256, tiles_per_group=5),
-         dict(wg_size=1024, tiles_per_group=4, window_entries=15360)]
+         dict(wg_size=1024, tiles_per_group=4, window_entries=15360),
+         dict(wg_size=256, wave_blocks=1),
+         dict(wg_size=512, wave_blocks=1, nnz_per_block=512, reduce_iters=5),
+         dict(wg_size=512, wave_blocks=1, tiles_per_group=3, xcd_remap=-1),
+         dict(wg_size=512, wave_blocks=1, blocks_per_tile=3)]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -93,7 +97,10 @@ WINDOW_TUNES = [dict(window_entries=4096, blocks_per_tile=64, wg_size=128),
                 dict(window_entries=16384, wg_size=512, blocks_per_tile=32),
                 dict(window_entries=16384, wg_size=512, tiles_per_group=1),
                 dict(window_entries=15360, wg_size=1024, tiles_per_group=1),
-                dict(window_entries=4096, wg_size=256, tiles_per_group=1)]
+                dict(window_entries=4096, wg_size=256, tiles_per_group=1),
+                dict(window_entries=15360, wg_size=1024, tiles_per_group=1, wave_blocks=1),
+                dict(window_entries=8192, wg_size=256, tiles_per_group=1, wave_blocks=1),
+                dict(window_entries=8192, wg_size=512, blocks_per_tile=64, wave_blocks=1, nnz_per_block=512)]
 
 
 @pytest.mark.parametrize("form", ["sb", "db", "split"])
