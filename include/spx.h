@@ -465,6 +465,17 @@ spx_status spx_mlp_loss_grad(const float *theta, const float *X, const int32_t *
                              float *loss, float *grad, void *stream);
 spx_status spx_mlp_adam(float *theta, const float *grad, float *m, float *v, int32_t t, float lr,
                         float beta1, float beta2, float eps, void *stream);
+/* spx_mlp_loss_grad_noalloc: spx_mlp_loss_grad for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid hipMalloc): the same kernels, with
+ * their workspace in a fixed device array of the library instead of an
+ * allocation, so the call allocates nothing.  B must be in 1..512
+ * (SPX_EINVAL otherwise).  Every GPU holds its own copy of the array until
+ * the process ends, and every call on a GPU shares it: calls that overlap
+ * on one GPU (different streams or threads) race.  Nothing in the
+ * workspace needs to start at zero. */
+spx_status spx_mlp_loss_grad_noalloc(const float *theta, const float *X, const int32_t *labels, int32_t B,
+                                     float *loss, float *grad, void *stream);
 
 /* Selection among the 24 choices (the paper picks the ordering by measuring
  * it, Section 5.2; here a trained network picks and measurement is the

@@ -74,6 +74,7 @@ _SIGS = {
     "spx_plan_autotune": ([_VP, _I32, _VP, _VP, _I32, _VP, _VP, _VP, _VP], _I32),
     "spx_autotune_candidate": ([_I32, _VP], _I32),
     "spx_choice_info": ([_I32, _VP, _VP, _VP], _I32),
+    "spx_mlp_loss_grad_noalloc": ([_VP, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
     "spx_order_bfs": ([_VP, _VP, _VP], _I32),
     "spx_order_rcm": ([_VP, _VP, _VP], _I32),
     "spx_plan_from_perm": ([_VP, _VP, _VP, _VP, _VP], _I32),
@@ -682,6 +683,23 @@ def mlp_loss_grad(theta, X, labels, loss, grad, stream=None):
     _check(lib().spx_mlp_loss_grad(_dev(theta, torch.float32, MLP_PARAMS), _dev(X, torch.float32, B * NFEATURES),
                                    _dev(labels, torch.int32, B), int(B), _dev(loss, torch.float32, 1),
                                    _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
+
+
+def mlp_loss_grad_noalloc(theta, X, labels, loss, grad, stream=None):
+    """mlp_loss_grad through the entry point that allocates nothing (batches of
+    at most 512 samples share one fixed device workspace per GPU)."""
+    import torch
+    B = X.shape[0]
+    if labels.numel() < B:
+        raise ValueError(f"{labels.numel()} labels for {B} samples")
+    if 0 < B <= 512:
+        lo, hi = int(labels[:B].min()), int(labels[:B].max())
+        if lo < 0 or hi >= NCHOICES:
+            raise ValueError(f"labels must lie in [0, {NCHOICES}), got [{lo}, {hi}]")
+    _check(lib().spx_mlp_loss_grad_noalloc(_dev(theta, torch.float32, MLP_PARAMS),
+                                           _dev(X, torch.float32, B * NFEATURES), _dev(labels, torch.int32, B),
+                                           int(B), _dev(loss, torch.float32, 1),
+                                           _dev(grad, torch.float32, MLP_PARAMS), _stream(stream)))
 
 
 def mlp_adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -5,6 +5,8 @@
 // a fixed order, so results are reproducible.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cstdint>
 
 #include "mlp.h"
@@ -153,6 +155,40 @@ hipError_t mlp_loss_grad(const float *theta, const float *X, const int32_t *labe
                        kMlpIn, B, gW1, gb1);
     return hipGetLastError();
 }
+
+// ------------------------------------------------- no-allocation entry point
+// Workspace of spx_mlp_loss_grad_noalloc: a file-scope device array sized
+// for batches of up to kNoAllocMaxBatch samples.  Every GPU the library runs
+// on holds its own copy until the process ends.  In host code the array's
+// name is only a host-side stand-in: its device address on each GPU comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr int kNoAllocMaxBatch = 512;
+constexpr size_t kNoAllocFloats = (size_t)kNoAllocMaxBatch * (6 * kMlpHid + 2 * kMlpOut) + 64;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+static_assert(kNoAllocFloats >= (size_t)kNoAllocMaxBatch * (6 * kMlpHid + 2 * kMlpOut) + 64,
+              "scratch must hold the workspace of the largest batch");
+
+hipError_t mlp_noalloc_scratch(float **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static float *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = (float *)p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
+int mlp_noalloc_max_batch() { return kNoAllocMaxBatch; }
 
 hipError_t mlp_adam(float *theta, const float *grad, float *m, float *v, int t, float lr, float b1, float b2,
                     float eps, hipStream_t s) {

@@ -182,6 +182,19 @@ spx_status spx_mlp_loss_grad(const float *theta, const float *X, const int32_t *
     });
 }
 
+spx_status spx_mlp_loss_grad_noalloc(const float *theta, const float *X, const int32_t *labels, int32_t B,
+                                     float *loss, float *grad, void *stream) {
+    return guarded([&] {
+        if (!theta || !X || !labels || !loss || !grad) fail(SPX_EINVAL, "bad arguments");
+        if (B < 1 || B > mlp_noalloc_max_batch())
+            fail(SPX_EINVAL, "B must be in 1.." + std::to_string(mlp_noalloc_max_batch()) +
+                                 " (the fixed workspace of the no-allocation entry point)");
+        float *ws = nullptr;
+        hip_check(mlp_noalloc_scratch(&ws), "no-allocation workspace address");
+        hip_check(mlp_loss_grad(theta, X, labels, B, loss, grad, ws, (hipStream_t)stream), "mlp backward");
+    });
+}
+
 spx_status spx_mlp_adam(float *theta, const float *grad, float *m, float *v, int32_t t, float lr, float beta1,
                         float beta2, float eps, void *stream) {
     return guarded([&] {
