@@ -33,6 +33,11 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+def kernel_source_sha256():
+    from paper_1203_2739_amd.rocprof_summary import kernel_source_sha256 as h
+    return h()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -706,7 +711,7 @@ def main():
                        "traffic": measured_traffic(best, A.nnz, schedule_name(hb["tune"]), hb["plan_sha256"]),
                        "kernel": f"{'spmv_waves' if hb['tune'][5] else 'spmv_blocks'} ({best}, "
                                  f"{schedule_name(hb['tune'])})",
-                       "alg_bytes_per_launch": nb}
+                       "alg_bytes_per_launch": nb, "kernel_source_sha256": kernel_source_sha256()}
     if not args.no_stream:
         out["stream_read_GBs"] = round(stream_ceiling(spx, torch), 1)
         out["pct_of_stream_ceiling"] = round(100 * hb["GBs"] / out["stream_read_GBs"], 2)

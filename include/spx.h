@@ -97,6 +97,14 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    wg_size 256, 512 or 1024; tiles hold blocks_per_tile
  *                    blocks (default wg_size / 64) or come from
  *                    tiles_per_group.
+ *   pipeline         0 (default) or 1: workgroup blocks in tiles (given by
+ *                    tiles_per_group or blocks_per_tile > 1), each
+ *                    workgroup issuing the index and value loads of its
+ *                    tile's next block before reducing the current one, so
+ *                    that a round of loads is always in flight; not with
+ *                    wave_blocks.  wg_size 256, 512 (4 or 8 nonzeros per
+ *                    thread for 256, 4 for 512) or 1024 (4); windows of up
+ *                    to 8192 (256 threads) or 16384 (512) entries.
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
@@ -108,6 +116,8 @@ typedef struct spx_tune_s {
     int32_t reduce_iters;
     int32_t tiles_per_group;
     int32_t wave_blocks;
+    int32_t pipeline;
+    int32_t reserved[3];
 } spx_tune;
 
 /* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
@@ -135,6 +145,7 @@ typedef struct spx_plan_info_s {
     int32_t nlong_rows;       /* slots too long for one block, run as one-round segments */
     int32_t tiles_per_group;  /* tiles of every row group (0: tiles follow leaves) */
     int32_t wave_blocks;      /* 1: blocks sized for and run by single waves */
+    int32_t pipeline;         /* 1: pipelined tiles */
 } spx_plan_info;
 
 const char *spx_last_error(void);

@@ -34,7 +34,8 @@ class Tune(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("nnz_per_block", ctypes.c_int32),
                 ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
-                ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32)]
+                ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
+                ("pipeline", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -50,7 +51,8 @@ class PlanInfo(ctypes.Structure):
                 ("bytes_window", ctypes.c_int64), ("window_nnz", ctypes.c_int64),
                 ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32),
-                ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32)]
+                ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
+                ("pipeline", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -440,7 +442,7 @@ def plan_retune(P: Plan, tune=None):
 
 
 _TUNE_FIELDS = ("wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "xcd_remap", "reduce_iters",
-                "tiles_per_group", "wave_blocks")
+                "tiles_per_group", "wave_blocks", "pipeline")
 
 
 def autotune_candidates():

@@ -62,13 +62,18 @@ Tune resolve_tune(const spx_tune *t, int form) {
         if (t->reduce_iters) r.reduce_iters = t->reduce_iters;
         if (t->tiles_per_group) r.tiles_per_group = t->tiles_per_group;
         if (t->wave_blocks) r.wave_blocks = t->wave_blocks > 0 ? 1 : 0;
+        if (t->pipeline) r.pipeline = t->pipeline > 0 ? 1 : 0;
     }
     if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512 && r.wg != 1024)
         fail(SPX_EINVAL, "wg_size must be 64, 128, 256, 512 or 1024");
     if (r.tiles_per_group < 0 || r.tiles_per_group > 4096) fail(SPX_EINVAL, "tiles_per_group must be in 0..4096");
     if (r.wave_blocks && r.wg < 256) fail(SPX_EINVAL, "wave_blocks needs wg_size 256, 512 or 1024");
-    if (!r.wave_blocks && r.wg == 1024 && (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
-        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only wave blocks or tiles per row group with an LDS window");
+    if (r.pipeline && r.wave_blocks) fail(SPX_EINVAL, "pipeline and wave_blocks exclude each other");
+    if (r.pipeline && r.tiles_per_group == 0 && r.blocks_per_tile <= 1)
+        fail(SPX_EINVAL, "pipeline needs tiles (tiles_per_group, or blocks_per_tile > 1)");
+    if (!r.wave_blocks && !r.pipeline && r.wg == 1024 && (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
+        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only wave blocks, pipelined tiles or tiles per row group "
+                               "with an LDS window");
     const int32_t bt = block_threads(r);
     if (!t || !t->nnz_per_block) r.nnz_per_block = (bt == 64 && !r.wave_blocks ? 8 : kDefaultNpt) * bt;
     if (r.nnz_per_block != 4 * bt && r.nnz_per_block != 8 * bt)
@@ -78,7 +83,8 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (r.blocks_per_tile < 1) fail(SPX_EINVAL, "blocks_per_tile must be >= 1");
     if (r.window_entries < 0) r.window_entries = -1;
     int wmax = 0;
-    if (!spmv_variant_exists(r.wg, r.nnz_per_block / bt, r.window_entries, &wmax, r.wave_blocks != 0))
+    if (!spmv_variant_exists(r.wg, r.nnz_per_block / bt, r.window_entries, &wmax, r.wave_blocks != 0,
+                             r.pipeline != 0))
         fail(SPX_EUNSUPPORTED, "no kernel variant for this wg_size / window");
     return r;
 }
@@ -259,7 +265,7 @@ hipError_t spx::run_product(spx_plan_s &P, const double *x, double *y, int32_t a
     }
 
     return launch_spmv(a, P.tune.wg, P.tune.nnz_per_block / block_threads(P.tune), P.tune.window_entries, tl, split,
-                       s, P.tune.wave_blocks != 0);
+                       s, P.tune.wave_blocks != 0, P.tune.pipeline != 0);
 }
 
 extern "C" {
@@ -430,6 +436,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->nlong_rows = P->long_seg_ptr.empty() ? 0 : (int32_t)P->long_seg_ptr.size() - 1;
         info->tiles_per_group = P->tune.tiles_per_group;
         info->wave_blocks = P->tune.wave_blocks;
+        info->pipeline = P->tune.pipeline;
     });
 }
 

@@ -65,17 +65,20 @@ int batch_grid();  // workgroups that are resident at once on the device
 // ntiles counts workgroups.  npt = nonzeros staged per thread.
 // wave = true: the wave-block kernel (tiles of wave-sized blocks, each wave
 // of a workgroup running its own blocks); npt is then the nonzeros per lane.
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave = false);
+// pipe = true: the pipelined-tile kernel (a workgroup per tile, the next
+// block's loads issued before the current block is reduced).
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave = false, bool pipe = false);
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s, bool wave = false);
+                       hipStream_t s, bool wave = false, bool pipe = false);
 // Low-precision products (binary32 or bfloat16 values, binary32 x, y and
 // accumulation): untiled workgroup blocks, or wave blocks without a window.
 bool spmv_lowp_variant_exists(int wg, int npt, int window_entries);
 bool spmv_lowp_wave_variant_exists(int wg, int npt);
+bool spmv_lowp_pipe_variant_exists(int wg, int npt);
 hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s,
-                           bool wave = false);
+                           bool wave = false, bool pipe = false);
 hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s,
-                            bool wave = false);
+                            bool wave = false, bool pipe = false);
 // Precision-mode vector kernels (see spx_cg_ir).  Dot products write their
 // result to *out (device) using part[dot_groups(n)] as scratch.
 int dot_groups(int64_t n);

@@ -200,6 +200,43 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
     if (grp < nr && lane == 0) store_row<SPLIT>(a, d.x + grp, sum);
 }
 
+// The partial sum `part` of segment [d.z, d.w) (aligned start zb) of long
+// slot d.x (number -1 - d.y): stored directly when the slot has one
+// segment, else combined by the segment that arrives last.  SPAN is the
+// nonzeros a segment spans from its aligned start.
+template <int SPAN, bool SPLIT, class V, class A>
+__device__ __forceinline__ void combine_segment(const SpmvArgsT<V, A> &a, const v4i d, int32_t zb, A part) {
+    const int32_t lr = -1 - d.y;
+    const int32_t base = a.long_seg_ptr[lr];
+    const int32_t nseg = a.long_seg_ptr[lr + 1] - base;
+    if (nseg == 1) {
+        store_row<SPLIT>(a, d.x, part);
+    } else {
+        const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / SPAN;
+        // The partial goes to the device-coherent level (an agent-scope
+        // atomic store writes through the XCD's L2) and must have landed
+        // before the counter moves: the wave waits until the store is
+        // acknowledged (vmcnt counts stores on gfx9 parts), and the
+        // signal fence keeps the compiler from moving the counter update
+        // above that wait.  The segment that sees the final count reads
+        // the partials with agent-scope loads issued after its update
+        // returned.  A release on the update would instead write back
+        // the whole L2 of the XCD (buffer_wbl2) for every segment.
+        __hip_atomic_store(&a.partials[base + seg], (double)part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): expcnt and lgkmcnt left unconstrained
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t done =
+            __hip_atomic_fetch_add(&a.counters[lr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == (uint32_t)nseg - 1) {
+            A sum = 0;
+            for (int32_t k = 0; k < nseg; ++k)
+                sum += (A)__hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            store_row<SPLIT>(a, d.x, sum);
+        }
+    }
+}
+
 // One segment [d.z, d.w) of long slot d.x: one load round like a multi-row
 // block, summed in registers and across waves.  A slot cut into several
 // segments combines them without atomics on y: each segment stores its
@@ -243,35 +280,7 @@ __device__ __forceinline__ void long_row_segment(const SpmvArgsT<V, A> &a, const
 #pragma unroll
             for (int w = 0; w < WG / 64; ++w) part += swave[w];
         }
-        const int32_t lr = -1 - d.y;
-        const int32_t base = a.long_seg_ptr[lr];
-        const int32_t nseg = a.long_seg_ptr[lr + 1] - base;
-        if (nseg == 1) {
-            store_row<SPLIT>(a, d.x, part);
-        } else {
-            const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / (NPT * WG);
-            // The partial goes to the device-coherent level (an agent-scope
-            // atomic store writes through the XCD's L2) and must have landed
-            // before the counter moves: the wave waits until the store is
-            // acknowledged (vmcnt counts stores on gfx9 parts), and the
-            // signal fence keeps the compiler from moving the counter update
-            // above that wait.  The segment that sees the final count reads
-            // the partials with agent-scope loads issued after its update
-            // returned.  A release on the update would instead write back
-            // the whole L2 of the XCD (buffer_wbl2) for every segment.
-            __hip_atomic_store(&a.partials[base + seg], (double)part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): expcnt and lgkmcnt left unconstrained
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            const uint32_t done =
-                __hip_atomic_fetch_add(&a.counters[lr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (done == (uint32_t)nseg - 1) {
-                A sum = 0;
-                for (int32_t k = 0; k < nseg; ++k)
-                    sum += (A)__hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&a.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                store_row<SPLIT>(a, d.x, sum);
-            }
-        }
+        combine_segment<NPT * WG, SPLIT>(a, d, zb, part);
     }
 }
 
@@ -304,6 +313,168 @@ __global__ __launch_bounds__(WG) void spmv_blocks(SpmvArgsT<V, A> a) {
         if (d.y >= 0) multi_row_block<WG, NPT, SPLIT, WMAX>(a, d, sprod, sptr, swin, wlo, wlen);
         else long_row_segment<WG, NPT, SPLIT, WMAX>(a, d, swave, swin, wlo, wlen);
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------- pipelined tiles
+// The stored values of four consecutive nonzeros as loaded (no widening, so
+// that holding them does not wait for the load): two 16-byte binary64
+// pairs, one 16-byte binary32 quad, or one 8-byte pair of bfloat16 pairs.
+template <class V> struct Raw4;
+template <> struct Raw4<double> { v2d a, b; };
+template <> struct Raw4<float> { v4f a; };
+template <> struct Raw4<uint16_t> { v2u a; };
+
+__device__ __forceinline__ Raw4<double> load_raw4(const double *vals, int32_t k0) {
+    const v2d *v2 = reinterpret_cast<const v2d *>(vals);
+    return {__builtin_nontemporal_load(&v2[k0 >> 1]), __builtin_nontemporal_load(&v2[(k0 >> 1) + 1])};
+}
+__device__ __forceinline__ Raw4<float> load_raw4(const float *vals, int32_t k0) {
+    return {__builtin_nontemporal_load(&reinterpret_cast<const v4f *>(vals)[k0 >> 2])};
+}
+__device__ __forceinline__ Raw4<uint16_t> load_raw4(const uint16_t *vals, int32_t k0) {
+    return {__builtin_nontemporal_load(&reinterpret_cast<const v2u *>(vals)[k0 >> 2])};
+}
+__device__ __forceinline__ Vals4d widen4(const Raw4<double> &r) { return {{r.a.x, r.a.y, r.b.x, r.b.y}}; }
+__device__ __forceinline__ Vals4f widen4(const Raw4<float> &r) { return {{r.a.x, r.a.y, r.a.z, r.a.w}}; }
+__device__ __forceinline__ Vals4f widen4(const Raw4<uint16_t> &r) {
+    return {{__uint_as_float(r.a.x << 16), __uint_as_float(r.a.x & 0xFFFF0000u), __uint_as_float(r.a.y << 16),
+             __uint_as_float(r.a.y & 0xFFFF0000u)}};
+}
+
+// Everything one thread loads for one block before the gathers: the
+// descriptor, its row pointers and its NPT indices and values.
+template <int NPT, class V>
+struct Stage {
+    v4i d;
+    int32_t rp0, rp1;
+    v4i cc[NPT / 4];
+    Raw4<V> vv[NPT / 4];
+};
+
+template <int WG, int NPT, class V, class A>
+__device__ __forceinline__ void load_stage(const SpmvArgsT<V, A> &a, int b, Stage<NPT, V> &st) {
+    const int tid = threadIdx.x;
+    st.d = reinterpret_cast<const v4i *>(a.blk_desc)[b];
+    const v4i d = st.d;
+    const int32_t zb = d.z & ~3;
+    const int32_t G = (d.w - zb + 3) >> 2;
+    st.rp0 = st.rp1 = 0;
+    if (d.y >= 0) {
+        const int32_t nr = d.y - d.x;
+        st.rp0 = a.slot_ptr[d.x + min(tid, nr)];
+        if (nr == WG && tid == 0) st.rp1 = a.slot_ptr[d.x + WG];
+    }
+    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
+#pragma unroll
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid + u * WG;
+        if (gi < G) {
+            st.cc[u] = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
+            st.vv[u] = load_raw4(a.vals, zb + 4 * gi);
+        }
+    }
+}
+
+// Pipelined tiles: one workgroup per tile of blocks (tiles per row group for
+// a persistent launch); the loads of block b + 1 are issued right after the
+// gathers of block b and before block b's products are reduced, so that a
+// round of index and value loads is in flight while the workgroup reduces
+// and stores.  The reduction is the one of multi_row_block and
+// long_row_segment.
+template <int WG, int NPT, bool SPLIT, int WMAX, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_pipe(SpmvArgsT<V, A> a) {
+    __shared__ A sprod[NPT * WG];
+    __shared__ int32_t sptr[WG + 1];
+    __shared__ A swave[WG / 64];
+    __shared__ A swin[WMAX > 0 ? WMAX : 1];
+    const int tid = threadIdx.x;
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
+    const v4i tl = reinterpret_cast<const v4i *>(a.tiles)[id];
+    const int32_t wlo = tl.z;
+    const int32_t wlen = WMAX > 0 ? tl.w : 0;
+    if (WMAX > 0 && wlen > 0) {
+        for (int i = tid; i < wlen; i += WG) swin[i] = a.x[wlo + i];
+        __syncthreads();
+    }
+    if (tl.x >= tl.y) return;
+    Stage<NPT, V> cur, nxt;
+    load_stage<WG, NPT>(a, tl.x, cur);
+    for (int b = tl.x; b < tl.y; ++b) {
+        const v4i d = cur.d;
+        const int32_t zb = d.z & ~3;
+        const int32_t G = (d.w - zb + 3) >> 2;
+        // gathers of this block
+        A xv[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT / 4; ++u) {
+            const int gi = tid + u * WG;
+            if (gi < G) {
+                xv[4 * u] = xval<WMAX>(a.x, swin, cur.cc[u].x, wlo, wlen);
+                xv[4 * u + 1] = xval<WMAX>(a.x, swin, cur.cc[u].y, wlo, wlen);
+                xv[4 * u + 2] = xval<WMAX>(a.x, swin, cur.cc[u].z, wlo, wlen);
+                xv[4 * u + 3] = xval<WMAX>(a.x, swin, cur.cc[u].w, wlo, wlen);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // the next block's loads go out before this block is reduced
+        if (b + 1 < tl.y) load_stage<WG, NPT>(a, b + 1, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        if (d.y >= 0) {
+            const int32_t nr = d.y - d.x;
+#pragma unroll
+            for (int u = 0; u < NPT / 4; ++u) {
+                const int gi = tid + u * WG;
+                if (gi < G) {
+                    const auto vv = widen4(cur.vv[u]);
+                    A *sp = &sprod[4 * gi];
+                    sp[0] = vv.v[0] * xv[4 * u];
+                    sp[1] = vv.v[1] * xv[4 * u + 1];
+                    sp[2] = vv.v[2] * xv[4 * u + 2];
+                    sp[3] = vv.v[3] * xv[4 * u + 3];
+                }
+            }
+            if (tid <= nr) sptr[tid] = cur.rp0 - zb;
+            if (nr == WG && tid == 0) sptr[WG] = cur.rp1 - zb;
+            __syncthreads();
+            const int q = WG / nr;
+            const int lg = q >= 64 ? 6 : 31 - __builtin_clz(q);
+            const int g = 1 << lg;
+            const int grp = tid >> lg, lane = tid & (g - 1);
+            A sum = 0;
+            if (grp < nr) {
+                const int k1 = sptr[grp + 1];
+                for (int k = sptr[grp] + lane; k < k1; k += g) sum += sprod[k];
+            }
+            sum = group_sum_unrolled(sum, g);
+            if (grp < nr && lane == 0) store_row<SPLIT>(a, d.x + grp, sum);
+        } else {
+            A acc = 0;
+#pragma unroll
+            for (int u = 0; u < NPT / 4; ++u) {
+                const int gi = tid + u * WG;
+                if (gi < G) {
+                    const int32_t k0 = zb + 4 * gi;
+                    const auto vv = widen4(cur.vv[u]);
+                    acc += (k0 >= d.z) ? vv.v[0] * xv[4 * u] : A(0);
+                    acc += (k0 + 1 >= d.z && k0 + 1 < d.w) ? vv.v[1] * xv[4 * u + 1] : A(0);
+                    acc += (k0 + 2 >= d.z && k0 + 2 < d.w) ? vv.v[2] * xv[4 * u + 2] : A(0);
+                    acc += (k0 + 3 >= d.z && k0 + 3 < d.w) ? vv.v[3] * xv[4 * u + 3] : A(0);
+                }
+            }
+            acc = group_sum_unrolled(acc, 64);
+            if ((tid & 63) == 0) swave[tid >> 6] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                A part = 0;
+#pragma unroll
+                for (int w = 0; w < WG / 64; ++w) part += swave[w];
+                combine_segment<NPT * WG, SPLIT>(a, d, zb, part);
+            }
+        }
+        __syncthreads();  // the next block rewrites sprod, sptr and swave
+        cur = nxt;
     }
 }
 
@@ -670,11 +841,50 @@ hipError_t launch_waves(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t
     return hipGetLastError();
 }
 
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_pipe(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
+    if (split)
+        hipLaunchKernelGGL((spmv_pipe<WG, NPT, true, WMAX, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((spmv_pipe<WG, NPT, false, WMAX, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
     hipError_t (*fn)(const SpmvArgsT<V, A> &, bool, bool, hipStream_t);
 };
+
+// pipelined-tile kernels (binary64 with optional windows; low precisions
+// without)
+template <class V, class A>
+struct PipeTable;
+template <>
+struct PipeTable<double, double> {
+    static constexpr Variant<double, double> v[] = {
+        {256, 4, 0, launch_pipe<256, 4, 0, double, double>},
+        {512, 4, 0, launch_pipe<512, 4, 0, double, double>},
+        {256, 8, 0, launch_pipe<256, 8, 0, double, double>},
+        {1024, 4, 0, launch_pipe<1024, 4, 0, double, double>},
+        {256, 4, 8192, launch_pipe<256, 4, 8192, double, double>},
+        {512, 4, 16384, launch_pipe<512, 4, 16384, double, double>},
+    };
+};
+template <class V>
+struct LowPipeTable {
+    static constexpr Variant<V, float> v[] = {
+        {256, 4, 0, launch_pipe<256, 4, 0, V, float>},
+        {512, 4, 0, launch_pipe<512, 4, 0, V, float>},
+    };
+};
+template <>
+struct PipeTable<float, float> : LowPipeTable<float> {};
+template <>
+struct PipeTable<uint16_t, float> : LowPipeTable<uint16_t> {};
 
 // wave-block kernels: workgroup size, nonzeros per lane, window capacity
 // (LDS: WG/64 slices of 64 NPT products and 65 row offsets, plus the window);
@@ -752,6 +962,29 @@ struct Table<float, float> : LowTable<float> {};
 template <>
 struct Table<uint16_t, float> : LowTable<uint16_t> {};
 
+template <class TableT>
+bool find_in(int wg, int npt, int window_entries, int *wmax_out) {
+    int best = -1;
+    for (const auto &v : TableT::v) {
+        if (v.wg != wg || v.npt != npt) continue;
+        if (window_entries <= 0 ? v.wmax == 0 : v.wmax >= window_entries) {
+            if (best < 0 || v.wmax < best) best = v.wmax;
+        }
+    }
+    if (best < 0) return false;
+    if (wmax_out) *wmax_out = best;
+    return true;
+}
+
+template <class TableT, class V, class A>
+hipError_t launch_in(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entries, bool split, hipStream_t s) {
+    int wmax = 0;
+    if (!find_in<TableT>(wg, npt, window_entries, &wmax)) return hipErrorInvalidValue;
+    for (const auto &v : TableT::v)
+        if (v.wg == wg && v.npt == npt && v.wmax == wmax) return v.fn(a, split, true, s);
+    return hipErrorInvalidValue;
+}
+
 template <class V, class A>
 bool find_wave_variant(int wg, int npt, int window_entries, int *wmax_out) {
     int best = -1;
@@ -801,10 +1034,13 @@ hipError_t launch_any(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entr
 }
 }  // namespace
 
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave) {
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave, bool pipe) {
+    if (pipe) return find_in<PipeTable<double, double>>(wg, npt, window_entries, wmax_out);
     return wave ? find_wave_variant<double, double>(wg, npt, window_entries, wmax_out)
                 : find_variant<double, double>(wg, npt, window_entries, wmax_out);
 }
+
+bool spmv_lowp_pipe_variant_exists(int wg, int npt) { return find_in<PipeTable<float, float>>(wg, npt, -1, nullptr); }
 
 bool spmv_lowp_wave_variant_exists(int wg, int npt) {
     return find_wave_variant<float, float>(wg, npt, -1, nullptr);
@@ -815,19 +1051,22 @@ bool spmv_lowp_variant_exists(int wg, int npt, int window_entries) {
 }
 
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s, bool wave) {
+                       hipStream_t s, bool wave, bool pipe) {
+    if (pipe) return launch_in<PipeTable<double, double>>(a, wg, npt, window_entries, split, s);
     if (wave) return launch_wave_any(a, wg, npt, window_entries, split, s);
     return launch_any(a, wg, npt, window_entries, tiled, split, s);
 }
 
 hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s,
-                           bool wave) {
+                           bool wave, bool pipe) {
+    if (pipe) return launch_in<PipeTable<float, float>>(a, wg, npt, -1, split, s);
     if (wave) return launch_wave_any(a, wg, npt, -1, split, s);
     return launch_any(a, wg, npt, -1, false, split, s);
 }
 
 hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s,
-                            bool wave) {
+                            bool wave, bool pipe) {
+    if (pipe) return launch_in<PipeTable<uint16_t, float>>(a, wg, npt, -1, split, s);
     if (wave) return launch_wave_any(a, wg, npt, -1, split, s);
     return launch_any(a, wg, npt, -1, false, split, s);
 }

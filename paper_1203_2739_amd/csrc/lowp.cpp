@@ -37,8 +37,9 @@ SpmvArgsT<V, float> lowp_args(const spx_plan_s &P, const V *vals, const float *x
     a.y = y;
     a.blk_desc = (const int32_t *)P.d_blk_desc->ptr;
     a.tiles = (const int32_t *)P.d_tiles->ptr;
-    // workgroup blocks run untiled; wave blocks run the plan's tiles
-    const bool wave = P.tune.wave_blocks != 0;
+    // workgroup blocks run untiled; wave blocks and pipelined tiles run the
+    // plan's tiles
+    const bool wave = P.tune.wave_blocks != 0 || P.tune.pipeline != 0;
     a.ntiles = (int32_t)(wave ? P.tiles.size() / 4 : P.blk_desc.size() / 4);
     a.xcd_remap = P.tune.xcd_remap;
     const auto &gp = wave ? P.xcd_tile_ptr : P.xcd_blk_ptr;
@@ -52,15 +53,20 @@ SpmvArgsT<V, float> lowp_args(const spx_plan_s &P, const V *vals, const float *x
 
 hipError_t run_lowp(const spx_plan_s &P, int32_t prec, const float *x, float *y, hipStream_t s) {
     const int wg = P.tune.wg, npt = P.tune.nnz_per_block / block_threads(P.tune);
-    const bool wave = P.tune.wave_blocks != 0;
+    const bool wave = P.tune.wave_blocks != 0, pipe = P.tune.pipeline != 0;
     if (prec == SPX_PREC_F32)
-        return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s, wave);
-    return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s, wave);
+        return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s, wave, pipe);
+    return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s, wave, pipe);
 }
 
-// Schedules the precision mode runs: workgroup blocks without tiles, or
-// wave blocks without a window.
-bool lowp_schedule_ok(const Tune &t) { return t.wave_blocks ? t.window_entries <= 0 : !tiled(t); }
+// Schedules the precision mode runs: workgroup blocks without tiles, wave
+// blocks without a window, or pipelined tiles without a window of a shape
+// that has a low-precision kernel.
+bool lowp_schedule_ok(const Tune &t) {
+    if (t.pipeline)
+        return t.window_entries <= 0 && spmv_lowp_pipe_variant_exists(t.wg, t.nnz_per_block / t.wg);
+    return t.wave_blocks ? t.window_entries <= 0 : !tiled(t);
+}
 }  // namespace spx
 
 namespace {

@@ -85,7 +85,7 @@ DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream
 
 struct Tune {
     int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
-    int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0, wave_blocks = 0;
+    int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0, wave_blocks = 0, pipeline = 0;
 };
 Tune resolve_tune(const spx_tune *t, int form);
 inline bool tiled(const Tune &t) {

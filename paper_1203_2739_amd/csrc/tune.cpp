@@ -13,20 +13,21 @@ namespace spx {
 
 // Candidate schedules in the order they are tried: the one-block-per-
 // workgroup kernel at every workgroup size; wave blocks at every workgroup
-// size; then wave blocks in tiles per row group with an LDS x window, sized
-// so that the tiles of a group are about the workgroups one XCD (32 CUs)
-// keeps resident: one 1024- or 512-thread workgroup per CU with a 120 or
-// 128 KB window, two 256-thread workgroups with 64 KB.
+// size; wave blocks in tiles per row group with an LDS x window, sized so
+// that the tiles of a group are about the workgroups one XCD (32 CUs) keeps
+// resident: one 1024- or 512-thread workgroup per CU with a 120 or 128 KB
+// window, two 256-thread workgroups with 64 KB; then pipelined tiles.
 const std::vector<spx_tune> &autotune_candidates() {
     static const std::vector<spx_tune> c = [] {
         std::vector<spx_tune> v;
-        auto add = [&v](int wg, int npt, int wave = 0, int tiles = 0, int window = 0) {
+        auto add = [&v](int wg, int npt, int wave = 0, int tiles = 0, int window = 0, int pipe = 0) {
             spx_tune t{};
             t.wg_size = wg;
             t.nnz_per_block = (wave ? 64 : wg) * npt;
             t.wave_blocks = wave;
             t.tiles_per_group = tiles;
             t.window_entries = window;
+            t.pipeline = pipe;
             v.push_back(t);
         };
         add(128, 4);
@@ -42,6 +43,12 @@ const std::vector<spx_tune> &autotune_candidates() {
         add(1024, 4, 1, 32, 15360);
         add(512, 4, 1, 32, 16384);
         add(256, 4, 1, 64, 8192);
+        // pipelined tiles, about as many per row group as one XCD keeps
+        // resident (4 workgroups of 512 or 8 of 256 threads on each of 32 CUs)
+        add(512, 4, 0, 128, 0, 1);
+        add(256, 4, 0, 256, 0, 1);
+        add(256, 8, 0, 128, 0, 1);
+        add(512, 4, 0, 64, 0, 1);
         return v;
     }();
     return c;
@@ -105,9 +112,18 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
         for (size_t c = 0; c < cands.size(); ++c) {
             // the precision mode runs no tiles of workgroup blocks and no window
             if (cand_ms) cand_ms[c] = -1.0f;
-            if (precision != SPX_PREC_F64 &&
-                (cands[c].window_entries > 0 || (!cands[c].wave_blocks && cands[c].tiles_per_group > 0)))
-                continue;
+            if (precision != SPX_PREC_F64) {
+                Tune r;
+                bool ok = true;
+                try {
+                    spx_tune u = cands[c];
+                    if (u.window_entries == 0) u.window_entries = -1;
+                    r = resolve_tune(&u, P->form);
+                } catch (const Error &) {
+                    ok = false;
+                }
+                if (!ok || !lowp_schedule_ok(r)) continue;
+            }
             retune_to(*P, cands[c]);
             for (int w = 0; w < 2; ++w) product();
             hip_check(hipEventRecord(ev.a, s), "event record");
@@ -134,6 +150,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
             chosen->reduce_iters = P->tune.reduce_iters;
             chosen->tiles_per_group = P->tune.tiles_per_group;
             chosen->wave_blocks = P->tune.wave_blocks;
+            chosen->pipeline = P->tune.pipeline;
         }
         if (ms) *ms = best_ms;
     });

@@ -72,10 +72,12 @@ def _mean_by_kernel(path, filt):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic(out, form, filt, nnz, alg, plan, tune, sched):
+def traffic(out, form, filt, nnz, alg, plan, tune, sched, src_sha=None):
     """Writes profiles/spmv_c2_<form>_traffic.txt from the five runs in <out>;
     <tune> is the bench.py --tune argument the runs used and <sched> its
-    schedule name (bench.schedule_name)."""
+    schedule name (bench.schedule_name); <src_sha> the kernel_source_sha256
+    the profiled bench run printed (the sources it ran), by default the hash
+    of the sources here."""
     copy_kib = (1 << 30) / 1024
     calf = list(_mean_by_kernel(os.path.join(out, "calf", "pmc_counter_collection.csv"), "stream_copy").values())[0]
     calw = list(_mean_by_kernel(os.path.join(out, "calw", "pmc_counter_collection.csv"), "stream_copy").values())[0]
@@ -100,7 +102,7 @@ Commands (run from /tmp with TMPDIR=/tmp; R = repository root, OUT = output dire
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pmcw -o pmc -- python3 R/bench.py {args} --steps 5 --warmup 1
   rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/calf -o pmc -- python3 R/bench.py --only-stream
   rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/calw -o pmc -- python3 R/bench.py --only-stream
-  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg} {plan} {tune} {sched}
+  python -m paper_1203_2739_amd.rocprof_summary traffic OUT {form} "{filt}" {nnz} {alg} {plan} {tune} {sched} {src_sha or kernel_source_sha256()}
 
 Kernel trace (--stats): {st['Name'][:100]}
   calls {st['Calls']}, mean {float(st['AverageNs']) / 1e3:.2f} us, min {float(st['MinNs']) / 1e3:.2f} us, max {float(st['MaxNs']) / 1e3:.2f} us
@@ -117,7 +119,7 @@ Counters per dispatch of the SpMV kernel (mean over dispatches):
 
 nnz: {nnz}
 schedule: {sched}
-kernel_source_sha256: {kernel_source_sha256()}
+kernel_source_sha256: {src_sha or kernel_source_sha256()}
 plan_sha256: {plan}
 traffic_bytes_per_launch: {int(fb + wb)}
 """)
@@ -127,7 +129,7 @@ traffic_bytes_per_launch: {int(fb + wb)}
 if __name__ == "__main__":
     if len(sys.argv) >= 10 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]), int(sys.argv[6]), sys.argv[7],
-                sys.argv[8], sys.argv[9])
+                sys.argv[8], sys.argv[9], sys.argv[10] if len(sys.argv) > 10 else None)
         sys.exit(0)
     if len(sys.argv) < 3 or sys.argv[1] not in ("stats", "pmc"):
         print(__doc__)

@@ -379,7 +379,9 @@ def long_row_csr(lens, n, seed=0):
                                   dict(wg_size=256, wave_blocks=1),
                                   dict(wg_size=512, wave_blocks=1, nnz_per_block=512, reduce_iters=3),
                                   dict(wg_size=512, wave_blocks=1, tiles_per_group=4, window_entries=16384),
-                                  dict(wg_size=512, wave_blocks=1, blocks_per_tile=3)])
+                                  dict(wg_size=512, wave_blocks=1, blocks_per_tile=3),
+                                  dict(wg_size=512, pipeline=1, tiles_per_group=5),
+                                  dict(wg_size=256, pipeline=1, blocks_per_tile=7, nnz_per_block=2048)])
 def test_schedule_rules(tune):
     """Schedules of matrices mixing empty, short, long and multi-segment rows
     obey the block rules for every tune."""

@@ -55,7 +55,10 @@ TUNES = [None,
          dict(wg_size=256, wave_blocks=1),
          dict(wg_size=512, wave_blocks=1, nnz_per_block=512, reduce_iters=5),
          dict(wg_size=512, wave_blocks=1, tiles_per_group=3, xcd_remap=-1),
-         dict(wg_size=512, wave_blocks=1, blocks_per_tile=3)]
+         dict(wg_size=512, wave_blocks=1, blocks_per_tile=3),
+         dict(wg_size=512, pipeline=1, tiles_per_group=7),
+         dict(wg_size=256, pipeline=1, blocks_per_tile=5, nnz_per_block=2048, reduce_iters=4),
+         dict(wg_size=1024, pipeline=1, tiles_per_group=2, xcd_remap=-1)]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -100,7 +103,9 @@ WINDOW_TUNES = [dict(window_entries=4096, blocks_per_tile=64, wg_size=128),
                 dict(window_entries=4096, wg_size=256, tiles_per_group=1),
                 dict(window_entries=15360, wg_size=1024, tiles_per_group=1, wave_blocks=1),
                 dict(window_entries=8192, wg_size=256, tiles_per_group=1, wave_blocks=1),
-                dict(window_entries=8192, wg_size=512, blocks_per_tile=64, wave_blocks=1, nnz_per_block=512)]
+                dict(window_entries=8192, wg_size=512, blocks_per_tile=64, wave_blocks=1, nnz_per_block=512),
+                dict(window_entries=16384, wg_size=512, tiles_per_group=1, pipeline=1),
+                dict(window_entries=8192, wg_size=256, blocks_per_tile=40, pipeline=1)]
 
 
 @pytest.mark.parametrize("form", ["sb", "db", "split"])
