@@ -238,16 +238,18 @@ def plan_sha256(rp, cp, parts, nleaves):
 def tune_list(t):
     """A schedule dict as the bench line's tune list."""
     return [t.get("wg_size", 0), t.get("nnz_per_block", 0), t.get("blocks_per_tile", 1),
-            t.get("window_entries", -1) or -1, t.get("tiles_per_group", 0), t.get("wave_blocks", 0)]
+            t.get("window_entries", -1) or -1, t.get("tiles_per_group", 0), t.get("wave_blocks", 0),
+            t.get("pipeline", 0), t.get("scan_reduce", 0)]
 
 
 def schedule_name(tune):
     """Short name of a schedule [wg, nnz_per_block, blocks_per_tile, window,
-    tiles_per_group, wave_blocks]: threads x nonzeros per thread (per lane
-    for wave blocks, marked w), then tiles per row group (t) and the LDS
-    window (W) when used."""
-    wg, nb, _, win, tpg, wave = (list(tune) + [0, 0])[:6]
-    name = f"{wg}x{nb // (64 if wave else wg)}" + ("w" if wave else "")
+    tiles_per_group, wave_blocks, pipeline, scan_reduce]: threads x nonzeros
+    per thread (per lane for wave blocks, marked w; s for scan row sums, p
+    for pipelined tiles), then tiles per row group (t) and the LDS window (W)
+    when used."""
+    wg, nb, _, win, tpg, wave, pipe, scan = (list(tune) + [0] * 8)[:8]
+    name = f"{wg}x{nb // (64 if wave else wg)}" + ("w" if wave else "") + ("s" if scan else "") + ("p" if pipe else "")
     if tpg:
         name += f"t{tpg}"
     if win and win > 0:
@@ -650,7 +652,8 @@ def main():
              "sum_lambda_col": inf["sum_lambda_col"], "sum_lambda_row": inf["sum_lambda_row"],
              "border_row_nnz": inf["border_row_nnz"], "bytes_matrix": inf["bytes_matrix"],
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
-                      inf["window_entries"], inf["tiles_per_group"], inf["wave_blocks"]],
+                      inf["window_entries"], inf["tiles_per_group"], inf["wave_blocks"], inf["pipeline"],
+                      inf["scan_reduce"]],
              "window_nnz": inf["window_nnz"],
              "plan_sha256": plan_key}
         if args.cold:

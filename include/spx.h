@@ -61,7 +61,7 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
 
 /* Kernel schedule.  Any field set to 0 takes the library default.
  *   wg_size          threads per workgroup: 64, 128 (default), 256, 512 (or
- *                    1024, see tiles_per_group)
+ *                    1024, see tiles_per_group and scan_reduce)
  *   nnz_per_block    nonzeros one workgroup stages per block: 4 * wg_size
  *                    (default; 8 * wg_size for wg_size 64) or 8 * wg_size
  *                    (every thread loads 4 or 8 consecutive nonzeros)
@@ -105,6 +105,15 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    wave_blocks.  wg_size 256, 512 (4 or 8 nonzeros per
  *                    thread for 256, 4 for 512) or 1024 (4); windows of up
  *                    to 8192 (256 threads) or 16384 (512) entries.
+ *   scan_reduce      0 (default) or 1: one workgroup per block, and the
+ *                    rows of a block are summed by a segmented scan over
+ *                    its products (every thread holds 4 or 8 consecutive
+ *                    products; the thread holding a row's last nonzero
+ *                    writes the row) instead of by lane groups per row;
+ *                    blocks are then cut by nonzeros and rows only
+ *                    (reduce_iters is ignored).  wg_size 128, 256, 512 or
+ *                    1024 with 4 nonzeros per thread; no tiles, windows,
+ *                    wave_blocks or pipeline.
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
@@ -117,7 +126,8 @@ typedef struct spx_tune_s {
     int32_t tiles_per_group;
     int32_t wave_blocks;
     int32_t pipeline;
-    int32_t reserved[3];
+    int32_t scan_reduce;
+    int32_t reserved[2];
 } spx_tune;
 
 /* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
@@ -146,6 +156,7 @@ typedef struct spx_plan_info_s {
     int32_t tiles_per_group;  /* tiles of every row group (0: tiles follow leaves) */
     int32_t wave_blocks;      /* 1: blocks sized for and run by single waves */
     int32_t pipeline;         /* 1: pipelined tiles */
+    int32_t scan_reduce;      /* 1: rows summed by a segmented scan per block */
 } spx_plan_info;
 
 const char *spx_last_error(void);

@@ -35,7 +35,7 @@ class Tune(ctypes.Structure):
                 ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -52,7 +52,7 @@ class PlanInfo(ctypes.Structure):
                 ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32)]
+                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -442,7 +442,7 @@ def plan_retune(P: Plan, tune=None):
 
 
 _TUNE_FIELDS = ("wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "xcd_remap", "reduce_iters",
-                "tiles_per_group", "wave_blocks", "pipeline")
+                "tiles_per_group", "wave_blocks", "pipeline", "scan_reduce")
 
 
 def autotune_candidates():

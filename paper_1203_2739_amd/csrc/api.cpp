@@ -63,6 +63,7 @@ Tune resolve_tune(const spx_tune *t, int form) {
         if (t->tiles_per_group) r.tiles_per_group = t->tiles_per_group;
         if (t->wave_blocks) r.wave_blocks = t->wave_blocks > 0 ? 1 : 0;
         if (t->pipeline) r.pipeline = t->pipeline > 0 ? 1 : 0;
+        if (t->scan_reduce) r.scan = t->scan_reduce > 0 ? 1 : 0;
     }
     if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512 && r.wg != 1024)
         fail(SPX_EINVAL, "wg_size must be 64, 128, 256, 512 or 1024");
@@ -71,9 +72,13 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (r.pipeline && r.wave_blocks) fail(SPX_EINVAL, "pipeline and wave_blocks exclude each other");
     if (r.pipeline && r.tiles_per_group == 0 && r.blocks_per_tile <= 1)
         fail(SPX_EINVAL, "pipeline needs tiles (tiles_per_group, or blocks_per_tile > 1)");
-    if (!r.wave_blocks && !r.pipeline && r.wg == 1024 && (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
-        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only wave blocks, pipelined tiles or tiles per row group "
-                               "with an LDS window");
+    if (r.scan && (r.wave_blocks || r.pipeline || r.tiles_per_group > 0 || r.blocks_per_tile > 1 ||
+                   (t && t->window_entries > 0)))
+        fail(SPX_EINVAL, "scan_reduce runs one block per workgroup: no tiles, windows, wave blocks or pipeline");
+    if (!r.wave_blocks && !r.pipeline && !r.scan && r.wg == 1024 &&
+        (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
+        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only scan blocks, wave blocks, pipelined tiles or tiles per "
+                               "row group with an LDS window");
     const int32_t bt = block_threads(r);
     if (!t || !t->nnz_per_block) r.nnz_per_block = (bt == 64 && !r.wave_blocks ? 8 : kDefaultNpt) * bt;
     if (r.nnz_per_block != 4 * bt && r.nnz_per_block != 8 * bt)
@@ -83,8 +88,7 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (r.blocks_per_tile < 1) fail(SPX_EINVAL, "blocks_per_tile must be >= 1");
     if (r.window_entries < 0) r.window_entries = -1;
     int wmax = 0;
-    if (!spmv_variant_exists(r.wg, r.nnz_per_block / bt, r.window_entries, &wmax, r.wave_blocks != 0,
-                             r.pipeline != 0))
+    if (!spmv_variant_exists(r.wg, r.nnz_per_block / bt, r.window_entries, &wmax, kind_of(r)))
         fail(SPX_EUNSUPPORTED, "no kernel variant for this wg_size / window");
     return r;
 }
@@ -265,7 +269,7 @@ hipError_t spx::run_product(spx_plan_s &P, const double *x, double *y, int32_t a
     }
 
     return launch_spmv(a, P.tune.wg, P.tune.nnz_per_block / block_threads(P.tune), P.tune.window_entries, tl, split,
-                       s, P.tune.wave_blocks != 0, P.tune.pipeline != 0);
+                       s, kind_of(P.tune));
 }
 
 extern "C" {
@@ -437,6 +441,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->tiles_per_group = P->tune.tiles_per_group;
         info->wave_blocks = P->tune.wave_blocks;
         info->pipeline = P->tune.pipeline;
+        info->scan_reduce = P->tune.scan;
     });
 }
 

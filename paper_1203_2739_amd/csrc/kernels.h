@@ -62,23 +62,23 @@ hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s);
 int batch_grid();  // workgroups that are resident at once on the device
 
 // One workgroup of wg threads per tile (tiled) or per block (not tiled);
-// ntiles counts workgroups.  npt = nonzeros staged per thread.
-// wave = true: the wave-block kernel (tiles of wave-sized blocks, each wave
-// of a workgroup running its own blocks); npt is then the nonzeros per lane.
-// pipe = true: the pipelined-tile kernel (a workgroup per tile, the next
-// block's loads issued before the current block is reduced).
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave = false, bool pipe = false);
+// ntiles counts workgroups.  npt = nonzeros staged per thread.  The kernel
+// kind: Blocks, the row-block kernel (rows summed from LDS by power-of-two
+// lane groups); Waves, the wave-block kernel (tiles of wave-sized blocks,
+// each wave of a workgroup running its own blocks; npt is then the nonzeros
+// per lane); Pipe, the pipelined-tile kernel (a workgroup per tile, the next
+// block's loads issued before the current block is reduced); Scan, one
+// workgroup per block with rows summed by a segmented scan over the block.
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, Kind k = Kind::Blocks);
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s, bool wave = false, bool pipe = false);
+                       hipStream_t s, Kind k = Kind::Blocks);
 // Low-precision products (binary32 or bfloat16 values, binary32 x, y and
-// accumulation): untiled workgroup blocks, or wave blocks without a window.
-bool spmv_lowp_variant_exists(int wg, int npt, int window_entries);
-bool spmv_lowp_wave_variant_exists(int wg, int npt);
-bool spmv_lowp_pipe_variant_exists(int wg, int npt);
+// accumulation): any kind without a window; row blocks untiled.
+bool spmv_lowp_variant_exists(int wg, int npt, Kind k);
 hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s,
-                           bool wave = false, bool pipe = false);
+                           Kind k = Kind::Blocks);
 hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s,
-                            bool wave = false, bool pipe = false);
+                            Kind k = Kind::Blocks);
 // Precision-mode vector kernels (see spx_cg_ir).  Dot products write their
 // result to *out (device) using part[dot_groups(n)] as scratch.
 int dot_groups(int64_t n);

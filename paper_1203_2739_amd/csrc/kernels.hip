@@ -200,19 +200,17 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
     if (grp < nr && lane == 0) store_row<SPLIT>(a, d.x + grp, sum);
 }
 
-// The partial sum `part` of segment [d.z, d.w) (aligned start zb) of long
-// slot d.x (number -1 - d.y): stored directly when the slot has one
-// segment, else combined by the segment that arrives last.  SPAN is the
-// nonzeros a segment spans from its aligned start.
-template <int SPAN, bool SPLIT, class V, class A>
-__device__ __forceinline__ void combine_segment(const SpmvArgsT<V, A> &a, const v4i d, int32_t zb, A part) {
-    const int32_t lr = -1 - d.y;
+// Partial sum number `seg` of long (or cut) slot number lr, which is slot
+// `slot`: stored directly when the slot has one partial, else combined by
+// the one that arrives last.
+template <bool SPLIT, class V, class A>
+__device__ __forceinline__ void combine_partial(const SpmvArgsT<V, A> &a, int32_t lr, int32_t seg, int32_t slot,
+                                                A part) {
     const int32_t base = a.long_seg_ptr[lr];
     const int32_t nseg = a.long_seg_ptr[lr + 1] - base;
     if (nseg == 1) {
-        store_row<SPLIT>(a, d.x, part);
+        store_row<SPLIT>(a, slot, part);
     } else {
-        const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / SPAN;
         // The partial goes to the device-coherent level (an agent-scope
         // atomic store writes through the XCD's L2) and must have landed
         // before the counter moves: the wave waits until the store is
@@ -232,9 +230,18 @@ __device__ __forceinline__ void combine_segment(const SpmvArgsT<V, A> &a, const 
             for (int32_t k = 0; k < nseg; ++k)
                 sum += (A)__hip_atomic_load(&a.partials[base + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&a.counters[lr], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            store_row<SPLIT>(a, d.x, sum);
+            store_row<SPLIT>(a, slot, sum);
         }
     }
+}
+
+// The partial sum `part` of segment [d.z, d.w) (aligned start zb) of long
+// slot d.x (number -1 - d.y).  SPAN is the nonzeros a segment spans from its
+// aligned start.
+template <int SPAN, bool SPLIT, class V, class A>
+__device__ __forceinline__ void combine_segment(const SpmvArgsT<V, A> &a, const v4i d, int32_t zb, A part) {
+    const int32_t seg = (zb - (a.slot_ptr[d.x] & ~3)) / SPAN;
+    combine_partial<SPLIT>(a, -1 - d.y, seg, d.x, part);
 }
 
 // One segment [d.z, d.w) of long slot d.x: one load round like a multi-row
@@ -507,6 +514,145 @@ __global__ __launch_bounds__(WG) void spmv_waves(SpmvArgsT<V, A> a) {
         else long_row_segment<64, NPT, SPLIT, WMAX, true>(a, d, sprod[w], swin, wlo, wlen, lane);
         block_sync<true>();  // the next block rewrites this wave's slices
     }
+}
+
+// ------------------------------------------------------------- scan blocks
+// Row sums by a segmented scan over the products of a block, in nonzero
+// order.  Thread t holds the NPT consecutive products of its chunk in
+// registers.  The owner of every non-empty row records the position of the
+// row's last nonzero; a chunk is summarised by (holds a row end, sum after
+// its last row end), and an exclusive scan of these pairs over the threads
+// (the sum restarts after every row end) gives each thread the partial sum
+// of the row that is open where its chunk begins.  The thread that holds
+// the last nonzero of a row writes it.  The work per thread no longer
+// depends on the longest row of the block, so the schedule cuts such blocks
+// by nonzeros and rows alone.
+
+// Inclusive scan of the chunk summaries (f, s) over the lanes of a wave in
+// lane order, where lanes a < b combine to (f_a | f_b, f_b ? s_b : s_a + s_b):
+// lane l ends with the sum of the products that follow the last row end in
+// lanes 0..l, and f = 1 when lanes 0..l hold a row end at all.
+template <class A>
+__device__ __forceinline__ void wave_seg_scan(A &s, int &f, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const A sp = __shfl_up(s, o, 64);
+        const int fp = __shfl_up(f, o, 64);
+        if (lane >= o) {
+            if (!f) s = sp + s;
+            f |= fp;
+        }
+    }
+}
+
+// One multi-row block summed by the scan.  send[r] is the block-relative
+// position of the last nonzero of row d.x + r (-1 for an empty row),
+// sowner[k] the row ending at position k.  sowner is not cleared between
+// blocks: a thread takes sowner[k] = r as a row end only when r is a row of
+// this block whose send[r] is k, and a row that ends at k has written
+// exactly that pair, so a stale entry is either rejected or right.
+template <int WG, int NPT, bool SPLIT, class V, class A>
+__device__ __forceinline__ void scan_row_block(const SpmvArgsT<V, A> &a, const v4i d, int16_t *send,
+                                               uint16_t *sowner, A *sws, int32_t *swf) {
+    static_assert(NPT == 4 || NPT == 8, "4 or 8 nonzeros per thread");
+    constexpr int NW = WG / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
+    const int32_t zb = d.z & ~3;
+    const int32_t nr = d.y - d.x;  // at most WG (schedule)
+    const int32_t G = (d.w - zb + 3) >> 2;
+    // row bounds first, so that their latency overlaps the data loads
+    const int32_t rb = tid < nr ? a.slot_ptr[d.x + tid] : 0;
+    const int32_t re = tid < nr ? a.slot_ptr[d.x + tid + 1] : 0;
+    A p[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid * (NPT / 4) + u;
+        const int32_t k0 = zb + 4 * gi;
+        A q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+        if (gi < G) {
+            const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
+            const auto vv = load4(a.vals, k0);
+            q0 = vv.v[0] * a.x[cc.x];
+            q1 = vv.v[1] * a.x[cc.y];
+            q2 = vv.v[2] * a.x[cc.z];
+            q3 = vv.v[3] * a.x[cc.w];
+        }
+        // entries of the aligned start before d.z, and from d.w on, belong
+        // to other blocks
+        p[4 * u + 0] = (k0 >= d.z && k0 < d.w) ? q0 : A(0);
+        p[4 * u + 1] = (k0 + 1 >= d.z && k0 + 1 < d.w) ? q1 : A(0);
+        p[4 * u + 2] = (k0 + 2 >= d.z && k0 + 2 < d.w) ? q2 : A(0);
+        p[4 * u + 3] = (k0 + 3 >= d.z && k0 + 3 < d.w) ? q3 : A(0);
+    }
+    if (tid < nr) {
+        // rows of a block lie in [d.z, d.w), which spans at most WG NPT
+        // entries from zb
+        send[tid] = re > rb ? (int16_t)(re - 1 - zb) : (int16_t)-1;
+        if (re > rb) sowner[re - 1 - zb] = (uint16_t)tid;
+        else store_row<SPLIT>(a, d.x + tid, A(0));
+    }
+    __syncthreads();  // row ends recorded
+    uint32_t ends = 0;
+    int32_t rows[NPT];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int k = tid * NPT + j;
+        const int r = sowner[k];
+        rows[j] = r;
+        if (r < nr && send[r] == k) ends |= 1u << j;
+    }
+    A s = 0;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) s = ((ends >> j) & 1u) ? A(0) : s + p[j];
+    int f = ends != 0u;
+    wave_seg_scan(s, f, lane);
+    // exclusive value of this lane, then the carry from the earlier waves
+    A carry = __shfl_up(s, 1, 64);
+    int fc = __shfl_up(f, 1, 64);
+    if (lane == 0) {
+        carry = 0;
+        fc = 0;
+    }
+    if (NW > 1) {
+        if (lane == 63) {
+            sws[w] = s;
+            swf[w] = f;
+        }
+        __syncthreads();
+        if (!fc) {
+            A c = 0;
+            for (int j = w - 1; j >= 0; --j) {
+                c = sws[j] + c;
+                if (swf[j]) break;
+            }
+            carry = c + carry;
+        }
+    }
+    A run = carry;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        run += p[j];
+        if ((ends >> j) & 1u) {
+            store_row<SPLIT>(a, d.x + rows[j], run);
+            run = 0;
+        }
+    }
+}
+
+// One workgroup per block (XCD mapping as in spmv_blocks); multi-row blocks
+// are summed by the segmented scan, long-slot segments as in spmv_blocks.
+template <int WG, int NPT, bool SPLIT, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_scan(SpmvArgsT<V, A> a) {
+    __shared__ int16_t send[WG];
+    __shared__ uint16_t sowner[WG * NPT];
+    __shared__ A sws[WG / 64];
+    __shared__ int32_t swf[WG / 64];
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
+    const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
+    if (d.y >= 0) scan_row_block<WG, NPT, SPLIT>(a, d, send, sowner, sws, swf);
+    else long_row_segment<WG, NPT, SPLIT, 0>(a, d, sws, sws, 0, 0);
 }
 
 // ------------------------------------------------------------------ batched
@@ -853,10 +999,37 @@ hipError_t launch_pipe(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t 
     return hipGetLastError();
 }
 
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_scan(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
+    static_assert(WMAX == 0, "scan blocks take no window");
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
+    if (split)
+        hipLaunchKernelGGL((spmv_scan<WG, NPT, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((spmv_scan<WG, NPT, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
     hipError_t (*fn)(const SpmvArgsT<V, A> &, bool, bool, hipStream_t);
+};
+
+// scan-block kernels (no window, 4 nonzeros per thread: with 8, the two
+// 16-byte loads of a thread's consecutive chunk leave every load
+// instruction of a wave half-used lines, measured 1.5x slower), every
+// precision
+template <class V, class A>
+struct ScanTable {
+    static constexpr Variant<V, A> v[] = {
+        {128, 4, 0, launch_scan<128, 4, 0, V, A>},
+        {256, 4, 0, launch_scan<256, 4, 0, V, A>},
+        {512, 4, 0, launch_scan<512, 4, 0, V, A>},
+        {1024, 4, 0, launch_scan<1024, 4, 0, V, A>},
+    };
 };
 
 // pipelined-tile kernels (binary64 with optional windows; low precisions
@@ -1034,41 +1207,53 @@ hipError_t launch_any(const SpmvArgsT<V, A> &a, int wg, int npt, int window_entr
 }
 }  // namespace
 
-bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, bool wave, bool pipe) {
-    if (pipe) return find_in<PipeTable<double, double>>(wg, npt, window_entries, wmax_out);
-    return wave ? find_wave_variant<double, double>(wg, npt, window_entries, wmax_out)
-                : find_variant<double, double>(wg, npt, window_entries, wmax_out);
+bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, Kind k) {
+    switch (k) {
+        case Kind::Pipe: return find_in<PipeTable<double, double>>(wg, npt, window_entries, wmax_out);
+        case Kind::Waves: return find_wave_variant<double, double>(wg, npt, window_entries, wmax_out);
+        case Kind::Scan: return find_in<ScanTable<double, double>>(wg, npt, window_entries, wmax_out);
+        default: return find_variant<double, double>(wg, npt, window_entries, wmax_out);
+    }
 }
 
-bool spmv_lowp_pipe_variant_exists(int wg, int npt) { return find_in<PipeTable<float, float>>(wg, npt, -1, nullptr); }
-
-bool spmv_lowp_wave_variant_exists(int wg, int npt) {
-    return find_wave_variant<float, float>(wg, npt, -1, nullptr);
-}
-
-bool spmv_lowp_variant_exists(int wg, int npt, int window_entries) {
-    return find_variant<float, float>(wg, npt, window_entries, nullptr);
+bool spmv_lowp_variant_exists(int wg, int npt, Kind k) {
+    switch (k) {
+        case Kind::Pipe: return find_in<PipeTable<float, float>>(wg, npt, -1, nullptr);
+        case Kind::Waves: return find_wave_variant<float, float>(wg, npt, -1, nullptr);
+        case Kind::Scan: return find_in<ScanTable<float, float>>(wg, npt, -1, nullptr);
+        default: return find_variant<float, float>(wg, npt, -1, nullptr);
+    }
 }
 
 hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, bool tiled, bool split,
-                       hipStream_t s, bool wave, bool pipe) {
-    if (pipe) return launch_in<PipeTable<double, double>>(a, wg, npt, window_entries, split, s);
-    if (wave) return launch_wave_any(a, wg, npt, window_entries, split, s);
-    return launch_any(a, wg, npt, window_entries, tiled, split, s);
+                       hipStream_t s, Kind k) {
+    switch (k) {
+        case Kind::Pipe: return launch_in<PipeTable<double, double>>(a, wg, npt, window_entries, split, s);
+        case Kind::Waves: return launch_wave_any(a, wg, npt, window_entries, split, s);
+        case Kind::Scan: return launch_in<ScanTable<double, double>>(a, wg, npt, window_entries, split, s);
+        default: return launch_any(a, wg, npt, window_entries, tiled, split, s);
+    }
 }
 
-hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s,
-                           bool wave, bool pipe) {
-    if (pipe) return launch_in<PipeTable<float, float>>(a, wg, npt, -1, split, s);
-    if (wave) return launch_wave_any(a, wg, npt, -1, split, s);
-    return launch_any(a, wg, npt, -1, false, split, s);
+namespace {
+template <class V>
+hipError_t launch_lowp(const SpmvArgsT<V, float> &a, int wg, int npt, bool split, hipStream_t s, Kind k) {
+    switch (k) {
+        case Kind::Pipe: return launch_in<PipeTable<V, float>>(a, wg, npt, -1, split, s);
+        case Kind::Waves: return launch_wave_any(a, wg, npt, -1, split, s);
+        case Kind::Scan: return launch_in<ScanTable<V, float>>(a, wg, npt, -1, split, s);
+        default: return launch_any(a, wg, npt, -1, false, split, s);
+    }
+}
+}  // namespace
+
+hipError_t launch_spmv_f32(const SpmvArgsT<float, float> &a, int wg, int npt, bool split, hipStream_t s, Kind k) {
+    return launch_lowp(a, wg, npt, split, s, k);
 }
 
 hipError_t launch_spmv_bf16(const SpmvArgsT<uint16_t, float> &a, int wg, int npt, bool split, hipStream_t s,
-                            bool wave, bool pipe) {
-    if (pipe) return launch_in<PipeTable<uint16_t, float>>(a, wg, npt, -1, split, s);
-    if (wave) return launch_wave_any(a, wg, npt, -1, split, s);
-    return launch_any(a, wg, npt, -1, false, split, s);
+                            Kind k) {
+    return launch_lowp(a, wg, npt, split, s, k);
 }
 
 hipError_t launch_batch(const BatchArgs &b, int grid, hipStream_t s) {

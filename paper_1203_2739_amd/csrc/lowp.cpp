@@ -53,19 +53,18 @@ SpmvArgsT<V, float> lowp_args(const spx_plan_s &P, const V *vals, const float *x
 
 hipError_t run_lowp(const spx_plan_s &P, int32_t prec, const float *x, float *y, hipStream_t s) {
     const int wg = P.tune.wg, npt = P.tune.nnz_per_block / block_threads(P.tune);
-    const bool wave = P.tune.wave_blocks != 0, pipe = P.tune.pipeline != 0;
+    const Kind k = kind_of(P.tune);
     if (prec == SPX_PREC_F32)
-        return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s, wave, pipe);
-    return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s, wave, pipe);
+        return launch_spmv_f32(lowp_args(P, (const float *)P.d_vals32->ptr, x, y), wg, npt, false, s, k);
+    return launch_spmv_bf16(lowp_args(P, (const uint16_t *)P.d_vals16->ptr, x, y), wg, npt, false, s, k);
 }
 
-// Schedules the precision mode runs: workgroup blocks without tiles, wave
-// blocks without a window, or pipelined tiles without a window of a shape
-// that has a low-precision kernel.
+// Schedules the precision mode runs: any kernel kind without an LDS window,
+// row blocks untiled, of a shape that has a low-precision kernel.
 bool lowp_schedule_ok(const Tune &t) {
-    if (t.pipeline)
-        return t.window_entries <= 0 && spmv_lowp_pipe_variant_exists(t.wg, t.nnz_per_block / t.wg);
-    return t.wave_blocks ? t.window_entries <= 0 : !tiled(t);
+    const Kind k = kind_of(t);
+    if (t.window_entries > 0 || (k == Kind::Blocks && tiled(t))) return false;
+    return spmv_lowp_variant_exists(t.wg, t.nnz_per_block / block_threads(t), k);
 }
 }  // namespace spx
 
@@ -229,7 +228,7 @@ spx_status spx_spmv_lowp(spx_plan P, int32_t precision, const float *x, float *y
         if (P->m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
         if (P->nnz > 0 && !x) fail(SPX_EINVAL, "x is NULL");
         if (!lowp_schedule_ok(P->tune))
-            fail(SPX_EUNSUPPORTED, "the precision mode runs untiled schedules or wave blocks without a window");
+            fail(SPX_EUNSUPPORTED, "the precision mode runs schedules without an LDS window (row blocks untiled)");
         hip_check(run_lowp(*P, precision, x, y, (hipStream_t)stream), "spmv_lowp launch");
     });
 }
@@ -246,7 +245,7 @@ spx_status spx_cg_ir(spx_plan P, int32_t precision, const double *b, double *x, 
         if (precision != SPX_PREC_F64) check_lowp_plan(*P, precision, true);
         if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");
         if (!lowp_schedule_ok(P->tune))
-            fail(SPX_EUNSUPPORTED, "the solve runs untiled schedules or wave blocks without a window");
+            fail(SPX_EUNSUPPORTED, "the solve runs schedules without an LDS window (row blocks untiled)");
         if (!(tol > 0) || !(inner_tol > 0) || max_outer < 1 || max_inner < 1)
             fail(SPX_EINVAL, "tol, inner_tol > 0 and max_outer, max_inner >= 1 required");
         if (P->n > 0 && (!b || !x)) fail(SPX_EINVAL, "NULL vector");

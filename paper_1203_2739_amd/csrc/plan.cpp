@@ -532,7 +532,8 @@ static int32_t lanes_per_row(int32_t wg, int32_t nr) {
 // Row blocks and tiles.  A multi-row block holds whole consecutive slots of
 // one unit (a leaf, or the rows outside all leaves) while (i) its nonzeros
 // span at most nnz_per_block entries from the 4-aligned start, (ii) it has at most
-// wg slots and (iii) ceil(longest / lanes_per_row) <= reduce_iters.  A slot
+// wg slots and (iii) ceil(longest / lanes_per_row) <= reduce_iters (not
+// with scan_reduce, whose row sums do not depend on row lengths).  A slot
 // that cannot form a block alone is a long slot: it is cut at 4-aligned
 // offsets into segments of one load round each (at most nnz_per_block
 // entries from the aligned start).  Descriptors are {first slot, end slot,
@@ -542,7 +543,8 @@ static int32_t lanes_per_row(int32_t wg, int32_t nr) {
 void build_schedule(spx_plan_s &P) {
     const Tune &T = P.tune;
     const int64_t span = T.nnz_per_block;
-    const int32_t iters = T.reduce_iters;
+    // the scan kernel's row sums take the same steps whatever the row lengths
+    const int32_t iters = T.scan ? INT32_MAX : T.reduce_iters;
     const int32_t bt = block_threads(T);
     P.blk_slot.clear();
     P.blk_desc.clear();

@@ -16,4 +16,7 @@ constexpr int kReduceIters = 64;
 // floor(kXcdGroups * s / nnz)); the kernels run the blocks of group g on XCD
 // g of the MI355X, and the plans order columns by the groups that read them.
 constexpr int kXcdGroups = 8;
+// Kernel that runs a schedule: row blocks, wave blocks, pipelined tiles, or
+// row blocks summed by a segmented scan.
+enum class Kind : int { Blocks = 0, Waves = 1, Pipe = 2, Scan = 3 };
 }  // namespace spx

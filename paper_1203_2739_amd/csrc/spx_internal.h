@@ -86,6 +86,7 @@ DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream
 struct Tune {
     int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
     int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0, wave_blocks = 0, pipeline = 0;
+    int32_t scan = 0;
 };
 Tune resolve_tune(const spx_tune *t, int form);
 inline bool tiled(const Tune &t) {
@@ -93,6 +94,9 @@ inline bool tiled(const Tune &t) {
 }
 // Threads that run one row block: a wave in wave-block schedules.
 inline int32_t block_threads(const Tune &t) { return t.wave_blocks ? 64 : t.wg; }
+inline Kind kind_of(const Tune &t) {
+    return t.pipeline ? Kind::Pipe : t.wave_blocks ? Kind::Waves : t.scan ? Kind::Scan : Kind::Blocks;
+}
 
 }  // namespace spx
 

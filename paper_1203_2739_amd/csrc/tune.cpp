@@ -12,7 +12,8 @@ using namespace spx;
 namespace spx {
 
 // Candidate schedules in the order they are tried: the one-block-per-
-// workgroup kernel at every workgroup size; wave blocks at every workgroup
+// workgroup kernel at every workgroup size, with lane groups per row and
+// with the segmented-scan row sums; wave blocks at every workgroup
 // size; wave blocks in tiles per row group with an LDS x window, sized so
 // that the tiles of a group are about the workgroups one XCD (32 CUs) keeps
 // resident: one 1024- or 512-thread workgroup per CU with a 120 or 128 KB
@@ -20,7 +21,8 @@ namespace spx {
 const std::vector<spx_tune> &autotune_candidates() {
     static const std::vector<spx_tune> c = [] {
         std::vector<spx_tune> v;
-        auto add = [&v](int wg, int npt, int wave = 0, int tiles = 0, int window = 0, int pipe = 0) {
+        auto add = [&v](int wg, int npt, int wave = 0, int tiles = 0, int window = 0, int pipe = 0,
+                        int scan = 0) {
             spx_tune t{};
             t.wg_size = wg;
             t.nnz_per_block = (wave ? 64 : wg) * npt;
@@ -28,6 +30,7 @@ const std::vector<spx_tune> &autotune_candidates() {
             t.tiles_per_group = tiles;
             t.window_entries = window;
             t.pipeline = pipe;
+            t.scan_reduce = scan;
             v.push_back(t);
         };
         add(128, 4);
@@ -36,6 +39,7 @@ const std::vector<spx_tune> &autotune_candidates() {
         add(512, 4);
         add(128, 8);
         add(256, 8);
+        for (int wg : {128, 256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 1);
         add(256, 4, 1);
         add(512, 4, 1);
         add(1024, 4, 1);
@@ -151,6 +155,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
             chosen->tiles_per_group = P->tune.tiles_per_group;
             chosen->wave_blocks = P->tune.wave_blocks;
             chosen->pipeline = P->tune.pipeline;
+            chosen->scan_reduce = P->tune.scan;
         }
         if (ms) *ms = best_ms;
     });

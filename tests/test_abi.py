@@ -72,6 +72,11 @@ def test_bad_arguments():
         spx.plan_plain(M, tune=dict(reduce_iters=65))
     with pytest.raises(spx.SpxError):
         spx.plan_plain(M, tune=dict(window_entries=40000))
+    for bad in (dict(scan_reduce=1, blocks_per_tile=2), dict(scan_reduce=1, window_entries=4096),
+                dict(scan_reduce=1, wg_size=256, wave_blocks=1), dict(scan_reduce=1, wg_size=512, tiles_per_group=4),
+                dict(scan_reduce=1, wg_size=64), dict(scan_reduce=1, wg_size=256, nnz_per_block=2048)):
+        with pytest.raises(spx.SpxError):
+            spx.plan_plain(M, tune=bad)
     with pytest.raises(spx.SpxError):
         spx.set_num_threads(0)
 
@@ -138,6 +143,8 @@ def check_schedule(P):
     inf = P.info()
     bd, tiles = P.export_sched()
     nslots, NT, wg, it = inf["nslots"], inf["nnz_per_block"], inf["wg_size"], inf["reduce_iters"]
+    if inf["scan_reduce"]:
+        it = 1 << 40  # scan row sums: blocks are bounded by nonzeros and rows only
     if inf["wave_blocks"]:
         wg = 64  # a block is sized for one wave
     assert NT in (4 * wg, 8 * wg)
@@ -381,7 +388,10 @@ def long_row_csr(lens, n, seed=0):
                                   dict(wg_size=512, wave_blocks=1, tiles_per_group=4, window_entries=16384),
                                   dict(wg_size=512, wave_blocks=1, blocks_per_tile=3),
                                   dict(wg_size=512, pipeline=1, tiles_per_group=5),
-                                  dict(wg_size=256, pipeline=1, blocks_per_tile=7, nnz_per_block=2048)])
+                                  dict(wg_size=256, pipeline=1, blocks_per_tile=7, nnz_per_block=2048),
+                                  dict(wg_size=512, scan_reduce=1), dict(wg_size=1024, scan_reduce=1),
+                                  dict(wg_size=256, scan_reduce=1),
+                                  dict(wg_size=128, scan_reduce=1, reduce_iters=1)])
 def test_schedule_rules(tune):
     """Schedules of matrices mixing empty, short, long and multi-segment rows
     obey the block rules for every tune."""
@@ -581,3 +591,29 @@ def test_row_net_border_rows_are_the_cut_rows(orc):
     pairs = np.unique(cols.astype(np.int64) * 16 + parts)
     assert np.unique(pairs // 16).size == pairs.size
     check_rowparts(orc, A, P, rp, cp, pp, 8, True)
+
+
+def test_scan_blocks_are_cut_by_nonzeros_and_rows_only():
+    """With scan row sums a block closes only when the next slot would push
+    it past nnz_per_block entries from its aligned start or past wg slots
+    (or at a unit's end, or before a long slot), so it never has more blocks
+    than the lane-group schedule of the same shape."""
+    A = gen_uniform_zipf(5, 20000, 20000, 400)
+    M = spx.from_csr(A, device=False)
+    for wg in (128, 512):
+        P = spx.plan_plain(M, tune=dict(wg_size=wg, scan_reduce=1))
+        Q = spx.plan_plain(M, tune=dict(wg_size=wg))
+        check_schedule(P)
+        assert P.info()["scan_reduce"] == 1 and Q.info()["scan_reduce"] == 0
+        assert P.info()["nblocks"] <= Q.info()["nblocks"]
+        bd, _ = P.export_sched()
+        sp = P.export_csr()[0].astype(np.int64)
+        NT = 4 * wg
+        total = int(sp[-1])
+        grp = lambda s: (8 * sp[s]) // max(total, 1)
+        for b in range(bd.shape[0] - 1):
+            s_lo, s_hi = int(bd[b, 0]), int(bd[b, 1])
+            if s_hi < 0 or bd[b + 1, 1] < 0 or grp(s_hi) != grp(s_lo):
+                continue
+            # the next slot would not fit: too many entries or too many slots
+            assert sp[s_hi + 1] - (sp[s_lo] & ~3) > NT or s_hi + 1 - s_lo > wg

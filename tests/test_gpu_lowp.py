@@ -40,7 +40,8 @@ def plans(A, form):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("form", ["plain", "sb", "db"])
-@pytest.mark.parametrize("tune", [None, dict(wg_size=64), dict(wg_size=512), dict(reduce_iters=2, wg_size=256)])
+@pytest.mark.parametrize("tune", [None, dict(wg_size=64), dict(wg_size=512), dict(reduce_iters=2, wg_size=256),
+                                  dict(wg_size=512, scan_reduce=1), dict(wg_size=128, scan_reduce=1)])
 def test_lowp_integer_exact(orc, prec, form, tune):
     A0 = gen_uniform_zipf(51, 20_000, 300_000, 4000, diagonal=True)
     A, x = integer_problem(A0, 13)
@@ -55,10 +56,13 @@ def test_lowp_integer_exact(orc, prec, form, tune):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_lowp_rounding_bound(orc, prec):
+@pytest.mark.parametrize("tune", [None, dict(wg_size=1024, scan_reduce=1)])
+def test_lowp_rounding_bound(orc, prec, tune):
     A = gen_uniform_zipf(52, 30_000, 500_000, 5000, diagonal=True)
     x = gen_vectors(120, A.n)[0].astype(np.float32)
     P, Ah, cp = plans(A, "plain")
+    if tune:
+        spx.plan_retune(P, tune)
     spx.plan_add_lowp(P, prec)
     y = lowp_y(P, prec, x, A.m).astype(np.float64)
     ref, vq = oracle_lowp(orc, Ah, Ah.vals, x, prec)

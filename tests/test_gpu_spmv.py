@@ -58,7 +58,12 @@ TUNES = [None,
          dict(wg_size=512, wave_blocks=1, blocks_per_tile=3),
          dict(wg_size=512, pipeline=1, tiles_per_group=7),
          dict(wg_size=256, pipeline=1, blocks_per_tile=5, nnz_per_block=2048, reduce_iters=4),
-         dict(wg_size=1024, pipeline=1, tiles_per_group=2, xcd_remap=-1)]
+         dict(wg_size=1024, pipeline=1, tiles_per_group=2, xcd_remap=-1),
+         dict(wg_size=128, scan_reduce=1),
+         dict(wg_size=512, scan_reduce=1),
+         dict(wg_size=1024, scan_reduce=1, xcd_remap=-1),
+         dict(wg_size=256, scan_reduce=1, reduce_iters=1)]
+SCAN_TUNES = [t for t in TUNES if t and t.get("scan_reduce")]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -72,6 +77,8 @@ def test_plain_c1(orc, ti):
 def test_plain_c1_integer_exact(orc):
     A, x = integer_problem(gen_c1(), 5)
     assert np.array_equal(run_plain(A, x), orc.spmv(A, x))
+    for t in SCAN_TUNES:
+        assert np.array_equal(run_plain(A, x, t), orc.spmv(A, x)), t
 
 
 @pytest.mark.parametrize("form", ["sb", "db", "split", "rn"])
@@ -90,6 +97,8 @@ def test_reordered_c1(orc, form, K):
 def test_reordered_c1_integer_exact(orc, form):
     A, x = integer_problem(gen_c1(), 9)
     y, rp, cp, part, P = run_reordered(A, x, form, 8)
+    assert np.array_equal(y, orc.spmv(A, x)[rp])
+    y, rp, cp, part, P = run_reordered(A, x, form, 8, tune=SCAN_TUNES[1])
     assert np.array_equal(y, orc.spmv(A, x)[rp])
 
 
@@ -178,7 +187,7 @@ def test_edge_shapes(orc, shape, long_len):
     m, n = shape
     A = odd_matrix(m * 7 + n, m, n, long_len=long_len if n >= long_len else 0)
     x = gen_vectors(107, n)[0]
-    for ti in (0, 1, 3, 5):
+    for ti in (0, 1, 3, 5, len(TUNES) - 4, len(TUNES) - 1):
         y = run_plain(A, x, TUNES[ti])
         assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), f"plain {shape} {long_len}")
     if A.nnz:
@@ -246,7 +255,7 @@ def test_rows_cut_into_segments(orc):
     A = CSR(len(lens), n, rp, cols.astype(np.int32), rng.uniform(-1, 1, cols.size))
     x = gen_vectors(110, n)[0]
     ref, den = orc.spmv(A, x), orc.abs_rowsum(A, x)
-    for t in (None, dict(wg_size=64), dict(wg_size=512), dict(blocks_per_tile=3)):
+    for t in (None, dict(wg_size=64), dict(wg_size=512), dict(blocks_per_tile=3), dict(wg_size=256, scan_reduce=1)):
         M = spx.from_csr(A)
         P = spx.plan_plain(M, tune=t)
         assert P.info()["nlong_rows"] >= 4
@@ -292,7 +301,8 @@ def test_split_deterministic_and_retune(orc):
     xh = torch.empty_like(xd)
     spx.permute_x(P, xd, xh)
     ref, den = orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp]
-    for t in (None, dict(wg_size=512), dict(wg_size=64), dict(reduce_iters=2, wg_size=256)):
+    for t in (None, dict(wg_size=512), dict(wg_size=64), dict(reduce_iters=2, wg_size=256),
+              dict(wg_size=512, scan_reduce=1)):
         spx.plan_retune(P, t)
         outs = []
         for rep in range(3):
