@@ -458,17 +458,35 @@ def main_selector(args, torch, spx):
     N = args.train + args.test
     fams = ["F1", "F2", "F3", "F4"]
     sizes = [int(round(np.exp(rng.uniform(np.log(args.n_lo), np.log(args.n_hi))))) for _ in range(N)]
+    lo, hi = (int(v) for v in args.index_range.split(":")) if args.index_range else (0, N)
+    tree_file = lambda i: os.path.join(args.trees or args.save_trees, f"sel_{i:05d}.npz")  # noqa: E731
+    if args.save_trees:
+        # the three K = 256 partitions of every matrix, on the host only
+        os.makedirs(args.save_trees, exist_ok=True)
+        t = time.time()
+        for i in range(lo, hi):
+            if os.path.exists(tree_file(i)):
+                continue
+            tr = selector.partition_trees(gen_family(fams[i % 4], 9000 + i, sizes[i]), seed=i)
+            np.savez_compressed(tree_file(i), sb=tr["sb"].astype(np.uint8), db=tr["db"].astype(np.uint16),
+                                split=tr["split"].astype(np.uint8), seconds=tr["seconds"])
+            log(f"trees {i + 1}/{hi} n={sizes[i]} ({tr['seconds']:.1f} s, {time.time() - t:.0f} s in all)")
+        return
     if args.selector_data:
         zs = [np.load(f) for f in args.selector_data.split(",")]
         F, T, tpart, nbytes = (np.concatenate([z[k] for z in zs]) for k in ("F", "T", "tpart", "nbytes"))
         assert F.shape[0] == N
     else:
-        lo, hi = (int(v) for v in args.index_range.split(":")) if args.index_range else (0, N)
         mats, T, tpart = [], [], []
         t = time.time()
         for i in range(lo, hi):
             A = gen_family(fams[i % 4], 9000 + i, sizes[i])
-            times, tp = selector.measure(A, seed=i)
+            trees = None
+            if args.trees:
+                with np.load(tree_file(i)) as z:
+                    trees = {f: z[f].astype(np.int32) for f in ("sb", "db", "split")}
+                    trees["seconds"] = float(z["seconds"])
+            times, tp = selector.measure(A, seed=i, trees=trees)
             mats.append(A)
             T.append(times)
             tpart.append(tp)
@@ -555,6 +573,12 @@ def main():
     ap.add_argument("--save-selector-data", default="", help="selector: save features and timings here")
     ap.add_argument("--index-range", default="",
                     help="selector: measure only matrices a:b of the sequence (with --save-selector-data)")
+    ap.add_argument("--save-trees", default="",
+                    help="selector: compute the three K = 256 partitions of every matrix on the host (no GPU) "
+                         "into this folder, then stop")
+    ap.add_argument("--trees", default="",
+                    help="selector: take the partitions from this folder (written by --save-trees) instead of "
+                         "partitioning during the measurement")
     ap.add_argument("--only-stream", action="store_true",
                     help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()
@@ -568,6 +592,9 @@ def main():
     import paper_1203_2739_amd as spx
     from synth import gen_vectors
 
+    if args.workload == "selector" and args.save_trees:
+        spx.set_num_threads(min(16, os.cpu_count() or 1))
+        return main_selector(args, torch, spx)  # host partitions only
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.workload == "precision":

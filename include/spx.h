@@ -530,7 +530,18 @@ spx_status spx_mlp_loss_grad_noalloc(const float *theta, const float *X, const i
  *   order.  ms (host, 24, may be NULL) receives the milliseconds per
  *   product of every choice, *choice the fastest, *partition_seconds (may
  *   be NULL) the host time of the three K = 256 partitions.  SPX_ENODEVICE
- *   for a host-only matrix. */
+ *   for a host-only matrix.
+ * spx_partition_tree: the K = 256 recursive bisection that the reordered
+ *   choices of `form` (SPX_FORM_SB, _DB or _SPLIT) are cut from (the
+ *   column-net model, Sec. 3.1; the enhanced row-column-net model, Sec. 3.2;
+ *   the row-column-net model, Sec. 4.1), on the host, also for host-only
+ *   matrices: parts (host) receives r2p[m] in 0..255 (SB), r2p[m] in 0..256
+ *   with 256 for R_B (DB), or nz_part[nnz] in 0..255 in A's CSR order
+ *   (split); *seconds (may be NULL) its host time.
+ * spx_select_exhaustive_trees: spx_select_exhaustive with the three trees
+ *   given (as spx_partition_tree returns them for the same A), so that the
+ *   partitioning can run apart from the timing; values out of range fail
+ *   with SPX_EINVAL. */
 spx_status spx_choice_info(int32_t choice, int32_t *form, int32_t *K, spx_tune *tune);
 spx_status spx_select(spx_mat A, const float *theta, const double *mu, const double *sd, int32_t *choice,
                       float *logits, void *stream);
@@ -540,6 +551,10 @@ spx_status spx_plan_for_choice(spx_mat A, int32_t choice, uint64_t seed, int32_t
                                spx_plan *out);
 spx_status spx_select_exhaustive(spx_mat A, const double *x, double *y, int32_t reps, uint64_t seed, float *ms,
                                  int32_t *choice, double *partition_seconds, void *stream);
+spx_status spx_partition_tree(spx_mat A, int32_t form, uint64_t seed, int32_t *parts, double *seconds);
+spx_status spx_select_exhaustive_trees(spx_mat A, const int32_t *tree_sb, const int32_t *tree_db,
+                                       const int32_t *tree_split, const double *x, double *y, int32_t reps,
+                                       float *ms, int32_t *choice, void *stream);
 
 /* ----------------------------------------------------------------------
  * Inspection (host arrays, caller-allocated; any pointer may be NULL).

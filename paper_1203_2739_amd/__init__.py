@@ -84,6 +84,8 @@ _SIGS = {
     "spx_select_features": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], _I32),
     "spx_plan_for_choice": ([_VP, _I32, ctypes.c_uint64, _VP, _VP, _VP], _I32),
     "spx_select_exhaustive": ([_VP, _VP, _VP, _I32, ctypes.c_uint64, _VP, _VP, _VP, _VP], _I32),
+    "spx_partition_tree": ([_VP, _I32, ctypes.c_uint64, _VP, _VP], _I32),
+    "spx_select_exhaustive_trees": ([_VP, _VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP], _I32),
     "spx_plan_destroy": ([_VP], None),
     "spx_plan_info_get": ([_VP, _VP], _I32),
     "spx_spmv": ([_VP, _VP, _VP, _VP], _I32),
@@ -788,6 +790,33 @@ def select_exhaustive(A: Mat, x, y, reps=10, seed=0, stream=None):
                                        int(reps), ctypes.c_uint64(int(seed)), _hp(ms), ctypes.byref(c),
                                        ctypes.byref(tp), _stream(stream)))
     return c.value, ms.astype(np.float64), tp.value
+
+
+_TREE_FORMS = {"sb": 1, "db": 2, "split": 3}
+
+
+def partition_tree(A: Mat, form, seed=0):
+    """The K = 256 bisection the reordered choices of form ("sb", "db",
+    "split") are cut from, computed on the host: (parts int32, seconds)."""
+    n = A.nnz if form == "split" else A.m
+    parts = np.empty(max(n, 1), np.int32)
+    sec = ctypes.c_double()
+    _check(lib().spx_partition_tree(A.handle, _TREE_FORMS[form], ctypes.c_uint64(int(seed)), _hp(parts),
+                                    ctypes.byref(sec)))
+    return parts[:n], sec.value
+
+
+def select_exhaustive_trees(A: Mat, trees, x, y, reps=10, stream=None):
+    """select_exhaustive with the three trees given (dict form -> parts as
+    partition_tree returns them): (fastest choice, ms[24])."""
+    import torch
+    ts = [np.ascontiguousarray(trees[f], dtype=np.int32) for f in ("sb", "db", "split")]
+    ms = np.empty(NCHOICES, np.float32)
+    c = ctypes.c_int32()
+    _check(lib().spx_select_exhaustive_trees(A.handle, _hp(ts[0]), _hp(ts[1]), _hp(ts[2]),
+                                             _dev(x, torch.float64, A.n), _dev(y, torch.float64, A.m), int(reps),
+                                             _hp(ms), ctypes.byref(c), _stream(stream)))
+    return c.value, ms.astype(np.float64)
 
 
 # ---------------------------------------------------------------- comparison orderings

@@ -104,6 +104,44 @@ float *mlp_ws(int B) {
     return (float *)ws->ptr;
 }
 
+void check_exhaustive_args(spx_mat A, const double *x, const double *y, int32_t reps, const int32_t *choice) {
+    if (!A || !choice) fail(SPX_EINVAL, "NULL argument");
+    if (!A->on_device) fail(SPX_ENODEVICE, "matrix has no device copy");
+    if (reps < 1) fail(SPX_EINVAL, "reps must be >= 1");
+    if (A->h.m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
+    if (A->h.nnz > 0 && !x) fail(SPX_EINVAL, "x is NULL");
+}
+
+// Every choice built (the reordered ones cut from the tree of their form)
+// and timed over `reps` products after two warm-up products.
+void time_choices(spx_mat_s &A, const PartitionResult trees[3], const double *x, double *y, int32_t reps, float *ms,
+                  int32_t *choice, hipStream_t s) {
+    DevPtr xh = dev_alloc((size_t)std::max<int32_t>(A.h.n, 1) * sizeof(double));
+    Events ev;
+    float t[SPX_NCHOICES];
+    for (int c = 0; c < SPX_NCHOICES; ++c) {
+        const Choice ch = choice_of(c);
+        std::unique_ptr<spx_plan_s> P(plan_of_choice(A, ch, ch.form == SPX_FORM_PLAIN ? nullptr : &trees[ch.form - 1]));
+        const double *xp = x;
+        if (ch.form != SPX_FORM_PLAIN) {
+            hip_check(launch_gather(x, (const int32_t *)P->d_col_perm->ptr, (double *)xh->ptr, P->n, s), "permute x");
+            xp = (const double *)xh->ptr;
+        }
+        for (int w = 0; w < 2; ++w) hip_check(run_product(*P, xp, y, 0, s), "product");
+        hip_check(hipEventRecord(ev.a, s), "event record");
+        for (int r = 0; r < reps; ++r) hip_check(run_product(*P, xp, y, 0, s), "product");
+        hip_check(hipEventRecord(ev.b, s), "event record");
+        hip_check(hipEventSynchronize(ev.b), "event sync");
+        hip_check(hipEventElapsedTime(&t[c], ev.a, ev.b), "elapsed");
+        t[c] /= (float)reps;
+    }
+    int best = 0;
+    for (int c = 1; c < SPX_NCHOICES; ++c)
+        if (t[c] < t[best]) best = c;
+    *choice = best;
+    if (ms) std::copy(t, t + SPX_NCHOICES, ms);
+}
+
 }  // namespace
 
 extern "C" {
@@ -279,43 +317,47 @@ spx_status spx_plan_for_choice(spx_mat A, int32_t choice, uint64_t seed, int32_t
 spx_status spx_select_exhaustive(spx_mat A, const double *x, double *y, int32_t reps, uint64_t seed, float *ms,
                                  int32_t *choice, double *partition_seconds, void *stream) {
     return guarded([&] {
-        if (!A || !choice) fail(SPX_EINVAL, "NULL argument");
-        if (!A->on_device) fail(SPX_ENODEVICE, "matrix has no device copy");
-        if (reps < 1) fail(SPX_EINVAL, "reps must be >= 1");
-        if (A->h.m > 0 && !y) fail(SPX_EINVAL, "y is NULL");
-        if (A->h.nnz > 0 && !x) fail(SPX_EINVAL, "x is NULL");
-        hipStream_t s = (hipStream_t)stream;
+        check_exhaustive_args(A, x, y, reps, choice);
         auto t0 = std::chrono::steady_clock::now();
         PartitionResult trees[3];
         for (int f = 0; f < 3; ++f)
             trees[f] = partition(A->h, model_of(f + 1), 256, 0, seed);
         const double tpart = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        DevPtr xh = dev_alloc((size_t)std::max<int32_t>(A->h.n, 1) * sizeof(double));
-        Events ev;
-        float t[SPX_NCHOICES];
-        for (int c = 0; c < SPX_NCHOICES; ++c) {
-            const Choice ch = choice_of(c);
-            std::unique_ptr<spx_plan_s> P(plan_of_choice(*A, ch, ch.form == SPX_FORM_PLAIN ? nullptr : &trees[ch.form - 1]));
-            const double *xp = x;
-            if (ch.form != SPX_FORM_PLAIN) {
-                hip_check(launch_gather(x, (const int32_t *)P->d_col_perm->ptr, (double *)xh->ptr, P->n, s),
-                          "permute x");
-                xp = (const double *)xh->ptr;
-            }
-            for (int w = 0; w < 2; ++w) hip_check(run_product(*P, xp, y, 0, s), "product");
-            hip_check(hipEventRecord(ev.a, s), "event record");
-            for (int r = 0; r < reps; ++r) hip_check(run_product(*P, xp, y, 0, s), "product");
-            hip_check(hipEventRecord(ev.b, s), "event record");
-            hip_check(hipEventSynchronize(ev.b), "event sync");
-            hip_check(hipEventElapsedTime(&t[c], ev.a, ev.b), "elapsed");
-            t[c] /= (float)reps;
-        }
-        int best = 0;
-        for (int c = 1; c < SPX_NCHOICES; ++c)
-            if (t[c] < t[best]) best = c;
-        *choice = best;
-        if (ms) std::copy(t, t + SPX_NCHOICES, ms);
+        time_choices(*A, trees, x, y, reps, ms, choice, (hipStream_t)stream);
         if (partition_seconds) *partition_seconds = tpart;
+    });
+}
+
+spx_status spx_partition_tree(spx_mat A, int32_t form, uint64_t seed, int32_t *parts, double *seconds) {
+    return guarded([&] {
+        if (!A) fail(SPX_EINVAL, "NULL handle");
+        if (form != SPX_FORM_SB && form != SPX_FORM_DB && form != SPX_FORM_SPLIT)
+            fail(SPX_EINVAL, "form must be SPX_FORM_SB, SPX_FORM_DB or SPX_FORM_SPLIT");
+        const size_t len = form == SPX_FORM_SPLIT ? (size_t)A->h.nnz : (size_t)A->h.m;
+        if (len && !parts) fail(SPX_EINVAL, "parts is NULL");
+        auto t0 = std::chrono::steady_clock::now();
+        const PartitionResult tree = partition(A->h, model_of(form), 256, 0, seed);
+        std::copy(tree.part.begin(), tree.part.begin() + std::min(len, tree.part.size()), parts);
+        if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    });
+}
+
+spx_status spx_select_exhaustive_trees(spx_mat A, const int32_t *tree_sb, const int32_t *tree_db,
+                                       const int32_t *tree_split, const double *x, double *y, int32_t reps,
+                                       float *ms, int32_t *choice, void *stream) {
+    return guarded([&] {
+        check_exhaustive_args(A, x, y, reps, choice);
+        const int32_t *given[3] = {tree_sb, tree_db, tree_split};
+        PartitionResult trees[3];
+        for (int f = 0; f < 3; ++f) {
+            const size_t len = f == 2 ? (size_t)A->h.nnz : (size_t)A->h.m;
+            const int32_t hi = f == 1 ? 256 : 255;  // DB: 256 is the row border
+            if (len && !given[f]) fail(SPX_EINVAL, "tree is NULL");
+            if (len) trees[f].part.assign(given[f], given[f] + len);
+            for (int32_t p : trees[f].part)
+                if (p < 0 || p > hi) fail(SPX_EINVAL, "tree part out of range");
+        }
+        time_choices(*A, trees, x, y, reps, ms, choice, (hipStream_t)stream);
     });
 }
 

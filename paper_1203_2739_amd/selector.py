@@ -14,8 +14,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (choice_info, features, from_csr, mlp_adam, mlp_loss_grad, select_exhaustive, select_features,
-               MLP_PARAMS, NCHOICES, NFEATURES)
+from . import (choice_info, features, from_csr, mlp_adam, mlp_loss_grad, partition_tree, select_exhaustive,
+               select_exhaustive_trees, select_features, MLP_PARAMS, NCHOICES, NFEATURES)
 
 
 def choice_name(c):
@@ -23,16 +23,32 @@ def choice_name(c):
     return f"plain{c}" if form == "plain" else f"{form}{K}"
 
 
-def measure(A, seed=0, reps=10):
+def measure(A, seed=0, reps=10, trees=None):
     """Milliseconds per product of every choice on matrix A (a synth CSR),
-    timed by the library, and the host seconds of the three partitions."""
+    timed by the library, and the host seconds of the three partitions.
+    trees: the three K = 256 partitions computed beforehand (dict form ->
+    parts, with their seconds under "seconds"), as partition_trees gives."""
     import torch
     M = from_csr(A)
     rng = np.random.default_rng(seed)
     x = torch.from_numpy(rng.uniform(-1, 1, A.n)).cuda()
     y = torch.empty(max(A.m, 1), dtype=torch.float64, device="cuda")
+    if trees is not None:
+        _, times = select_exhaustive_trees(M, trees, x, y, reps=reps)
+        return times, float(trees["seconds"])
     _, times, tpart = select_exhaustive(M, x, y, reps=reps, seed=seed)
     return times, tpart
+
+
+def partition_trees(A, seed=0):
+    """The three K = 256 partitions of A (host only, no GPU) for measure."""
+    M = from_csr(A, device=False)
+    out, sec = {}, 0.0
+    for f in ("sb", "db", "split"):
+        out[f], s = partition_tree(M, f, seed)
+        sec += s
+    out["seconds"] = sec
+    return out
 
 
 def feature_matrix(mats):

@@ -617,3 +617,20 @@ def test_scan_blocks_are_cut_by_nonzeros_and_rows_only():
                 continue
             # the next slot would not fit: too many entries or too many slots
             assert sp[s_hi + 1] - (sp[s_lo] & ~3) > NT or s_hi + 1 - s_lo > wg
+
+
+@pytest.mark.parametrize("form", ["sb", "db", "split"])
+def test_partition_tree_is_the_k256_partition(form):
+    """spx_partition_tree returns, on a host-only matrix, the partition of
+    the K = 256 plan of the same form and seed (parts in 0..255, and 256 for
+    the DB row border), which the selector's reordered choices are cut from."""
+    A = gen_uniform_zipf(61, 3000, 3000, 200)
+    M = spx.from_csr(A, device=False)
+    parts, sec = spx.partition_tree(M, form, 5)
+    fn = {"sb": spx.reorder_sb, "db": spx.reorder_db, "split": spx.split}[form]
+    P = fn(M, 256, 0, 5)[0]
+    ref, _ = P.export_parts()
+    assert np.array_equal(parts, ref) and sec >= 0
+    assert parts.size == (A.nnz if form == "split" else A.m)
+    assert parts.min() >= 0 and parts.max() <= (256 if form == "db" else 255)
+    assert spx.lib().spx_partition_tree(M.handle, 0, 0, None, None) == -1  # the plain form has no tree

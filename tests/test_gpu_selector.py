@@ -100,3 +100,27 @@ def test_selector_gains_on_held_out_matrices():
     print(f"held-out mean regret: network {r_net:.3f}, best fixed {selector.choice_name(fixed)} {r_fix:.3f}, "
           f"plain {r_plain:.3f}; settings {settings}")
     assert r_net <= r_fix + 0.03 and r_net <= r_plain + 1e-9, (r_net, r_fix, r_plain)
+
+
+def test_exhaustive_timing_from_given_trees():
+    """The selector's timing with the three K = 256 partitions computed
+    beforehand on the host (spx_partition_tree, then
+    spx_select_exhaustive_trees) times all 24 choices and returns the fastest;
+    a tree with a part out of range is refused before anything runs."""
+    from paper_1203_2739_amd import selector
+    from synth import gen_family
+    A = gen_family("F2", 77, 15000)
+    trees = selector.partition_trees(A, seed=3)
+    assert trees["seconds"] > 0
+    T, tp = selector.measure(A, seed=3, reps=3, trees=trees)
+    assert T.shape == (spx.NCHOICES,) and np.all(T > 0) and tp == trees["seconds"]
+    M = spx.from_csr(A)
+    x = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    c, ms = spx.select_exhaustive_trees(M, trees, x, y, reps=2)
+    assert c == int(np.argmin(ms))
+    bad = dict(trees)
+    bad["db"] = trees["db"].copy()
+    bad["db"][0] = 257
+    with pytest.raises(spx.SpxError):
+        spx.select_exhaustive_trees(M, bad, x, y, reps=1)
