@@ -239,17 +239,18 @@ def tune_list(t):
     """A schedule dict as the bench line's tune list."""
     return [t.get("wg_size", 0), t.get("nnz_per_block", 0), t.get("blocks_per_tile", 1),
             t.get("window_entries", -1) or -1, t.get("tiles_per_group", 0), t.get("wave_blocks", 0),
-            t.get("pipeline", 0), t.get("scan_reduce", 0)]
+            t.get("pipeline", 0), t.get("scan_reduce", 0), t.get("sort_gathers", 0)]
 
 
 def schedule_name(tune):
     """Short name of a schedule [wg, nnz_per_block, blocks_per_tile, window,
-    tiles_per_group, wave_blocks, pipeline, scan_reduce]: threads x nonzeros
-    per thread (per lane for wave blocks, marked w; s for scan row sums, p
-    for pipelined tiles), then tiles per row group (t) and the LDS window (W)
-    when used."""
-    wg, nb, _, win, tpg, wave, pipe, scan = (list(tune) + [0] * 8)[:8]
-    name = f"{wg}x{nb // (64 if wave else wg)}" + ("w" if wave else "") + ("s" if scan else "") + ("p" if pipe else "")
+    tiles_per_group, wave_blocks, pipeline, scan_reduce, sort_gathers]:
+    threads x nonzeros per thread (per lane for wave blocks, marked w; s for
+    scan row sums, g for gather-sorted blocks, p for pipelined tiles), then
+    tiles per row group (t) and the LDS window (W) when used."""
+    wg, nb, _, win, tpg, wave, pipe, scan, srt = (list(tune) + [0] * 9)[:9]
+    name = (f"{wg}x{nb // (64 if wave else wg)}" + ("w" if wave else "") + ("s" if scan else "")
+            + ("g" if srt else "") + ("p" if pipe else ""))
     if tpg:
         name += f"t{tpg}"
     if win and win > 0:
@@ -555,7 +556,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tune", default="",
-                    help="wg,nnz_per_block[,blocks_per_tile,window_entries,tiles_per_group,wave_blocks]")
+                    help="wg,nnz_per_block[,blocks_per_tile,window_entries,tiles_per_group,wave_blocks,pipeline,"
+                         "scan_reduce,sort_gathers]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
@@ -631,7 +633,8 @@ def main():
     tune = None
     if args.tune:
         f = [int(v) for v in args.tune.split(",")]
-        keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group", "wave_blocks"]
+        keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group", "wave_blocks",
+                "pipeline", "scan_reduce", "sort_gathers"]
         tune = dict(zip(keys, f))
 
     results = {}
@@ -680,7 +683,7 @@ def main():
              "border_row_nnz": inf["border_row_nnz"], "bytes_matrix": inf["bytes_matrix"],
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
                       inf["window_entries"], inf["tiles_per_group"], inf["wave_blocks"], inf["pipeline"],
-                      inf["scan_reduce"]],
+                      inf["scan_reduce"], inf["sort_gathers"]],
              "window_nnz": inf["window_nnz"],
              "plan_sha256": plan_key}
         if args.cold:

@@ -114,6 +114,16 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    (reduce_iters is ignored).  wg_size 128, 256, 512 or
  *                    1024 with 4 nonzeros per thread; no tiles, windows,
  *                    wave_blocks or pipeline.
+ *   sort_gathers     0 (default) or 1: binary64 products from a second
+ *                    device copy in which the nonzeros of every multi-row
+ *                    block are sorted by column, each index carrying the
+ *                    nonzero's row-order offset in its upper 11 bits; the
+ *                    x gathers of a quarter wave then read 16 consecutive
+ *                    columns of the block, so lanes that hit one cache line
+ *                    share one request.  wg_size 128, 256 or 512 with 4 nonzeros per
+ *                    thread; at most 2^21 columns (SPX_EUNSUPPORTED
+ *                    otherwise); no tiles, windows, wave_blocks, pipeline or
+ *                    scan_reduce; not for the precision mode.
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
@@ -127,7 +137,8 @@ typedef struct spx_tune_s {
     int32_t wave_blocks;
     int32_t pipeline;
     int32_t scan_reduce;
-    int32_t reserved[2];
+    int32_t sort_gathers;
+    int32_t reserved[1];
 } spx_tune;
 
 /* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
@@ -157,6 +168,7 @@ typedef struct spx_plan_info_s {
     int32_t wave_blocks;      /* 1: blocks sized for and run by single waves */
     int32_t pipeline;         /* 1: pipelined tiles */
     int32_t scan_reduce;      /* 1: rows summed by a segmented scan per block */
+    int32_t sort_gathers;     /* 1: blocks stored sorted by column for the x gathers */
 } spx_plan_info;
 
 const char *spx_last_error(void);
@@ -574,6 +586,12 @@ spx_status spx_select_exhaustive_trees(spx_mat A, const int32_t *tree_sb, const 
  *   row may continue from one block into the next of the same tile) and
  *   tiles[4*ntiles] = {first block, end block, window first column, window
  *   length} per tile.
+ * spx_plan_export_gather_order: the gather-sorted copy of a plan tuned with
+ *   sort_gathers: *len entries in all, ofs[nblocks] (offset of every
+ *   multi-row block, -1 for long-slot segments), colidx[len] (column |
+ *   row-order offset << 21, all ones for padding: chunk k of a block holds
+ *   sorted entry 64 k + 16 j + l at 64 k + 4 l + j) and vals[len];
+ *   SPX_EUNSUPPORTED for other schedules.
  */
 spx_status spx_plan_export_csr(spx_plan P, int32_t *rowptr, int32_t *colidx, double *vals);
 spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *slot_row,
@@ -581,6 +599,7 @@ spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *sl
 spx_status spx_plan_export_parts(spx_plan P, int32_t *a, int32_t *b);
 spx_status spx_plan_export_perm(spx_plan P, int32_t *row_perm, int32_t *col_perm);
 spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_desc, int32_t *tiles);
+spx_status spx_plan_export_gather_order(spx_plan P, int64_t *len, int32_t *ofs, uint32_t *colidx, double *vals);
 
 /* ----------------------------------------------------------------------
  * Measurement helpers.

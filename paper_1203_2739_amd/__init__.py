@@ -35,7 +35,8 @@ class Tune(ctypes.Structure):
                 ("blocks_per_tile", ctypes.c_int32), ("window_entries", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("sort_gathers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -52,7 +53,7 @@ class PlanInfo(ctypes.Structure):
                 ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32)]
+                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("sort_gathers", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -98,6 +99,7 @@ _SIGS = {
     "spx_plan_export_parts": ([_VP, _VP, _VP], _I32),
     "spx_plan_export_perm": ([_VP, _VP, _VP], _I32),
     "spx_plan_export_sched": ([_VP, _VP, _VP], _I32),
+    "spx_plan_export_gather_order": ([_VP, _VP, _VP, _VP, _VP], _I32),
     "spx_stream_sink_len": ([_I64], _I64),
     "spx_stream_read": ([_VP, _I64, _VP, _VP], _I32),
     "spx_stream_copy": ([_VP, _VP, _I64, _VP], _I32),
@@ -387,6 +389,17 @@ class Plan:
         _check(lib().spx_plan_export_sched(self._h, _hp(bd), _hp(tl)))
         return bd[:4 * inf["nblocks"]].reshape(-1, 4), tl[:4 * inf["ntiles"]].reshape(-1, 4)
 
+    def export_gather_order(self):
+        """(ofs[nblocks], colidx uint32[len], vals[len]) of the gather-sorted copy."""
+        n = ctypes.c_int64()
+        _check(lib().spx_plan_export_gather_order(self._h, ctypes.byref(n), None, None, None))
+        nb = self.info()["nblocks"]
+        o = np.empty(max(nb, 1), np.int32)
+        c = np.empty(max(n.value, 1), np.uint32)
+        v = np.empty(max(n.value, 1), np.float64)
+        _check(lib().spx_plan_export_gather_order(self._h, None, _hp(o), _hp(c), _hp(v)))
+        return o[:nb], c[:n.value], v[:n.value]
+
 
 def _tune_ptr(tune):
     if tune is None:
@@ -444,7 +457,7 @@ def plan_retune(P: Plan, tune=None):
 
 
 _TUNE_FIELDS = ("wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "xcd_remap", "reduce_iters",
-                "tiles_per_group", "wave_blocks", "pipeline", "scan_reduce")
+                "tiles_per_group", "wave_blocks", "pipeline", "scan_reduce", "sort_gathers")
 
 
 def autotune_candidates():

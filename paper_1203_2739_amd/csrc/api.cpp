@@ -64,6 +64,7 @@ Tune resolve_tune(const spx_tune *t, int form) {
         if (t->wave_blocks) r.wave_blocks = t->wave_blocks > 0 ? 1 : 0;
         if (t->pipeline) r.pipeline = t->pipeline > 0 ? 1 : 0;
         if (t->scan_reduce) r.scan = t->scan_reduce > 0 ? 1 : 0;
+        if (t->sort_gathers) r.sort_gathers = t->sort_gathers > 0 ? 1 : 0;
     }
     if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512 && r.wg != 1024)
         fail(SPX_EINVAL, "wg_size must be 64, 128, 256, 512 or 1024");
@@ -75,6 +76,10 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (r.scan && (r.wave_blocks || r.pipeline || r.tiles_per_group > 0 || r.blocks_per_tile > 1 ||
                    (t && t->window_entries > 0)))
         fail(SPX_EINVAL, "scan_reduce runs one block per workgroup: no tiles, windows, wave blocks or pipeline");
+    if (r.sort_gathers && (r.scan || r.wave_blocks || r.pipeline || r.tiles_per_group > 0 ||
+                           r.blocks_per_tile > 1 || (t && t->window_entries > 0)))
+        fail(SPX_EINVAL, "sort_gathers runs one block per workgroup: no tiles, windows, wave blocks, pipeline "
+                         "or scan_reduce");
     if (!r.wave_blocks && !r.pipeline && !r.scan && r.wg == 1024 &&
         (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
         fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only scan blocks, wave blocks, pipelined tiles or tiles per "
@@ -171,6 +176,15 @@ void upload_plan(spx_plan_s &P, const spx_mat_s &A, void *stream) {
 // and arrival counters, which start at zero).
 void upload_schedule(spx_plan_s &P, void *stream) {
     P.d_blk_desc = dev_upload(P.blk_desc.data(), P.blk_desc.size() * 4, 16, stream);
+    if (P.tune.sort_gathers) {
+        P.d_colidx_sorted = dev_upload(P.colidx_sorted.data(), P.colidx_sorted.size() * 4, 16, stream);
+        P.d_vals_sorted = dev_upload(P.vals_sorted.data(), P.vals_sorted.size() * 8, 16, stream);
+        P.d_sorted_ofs = dev_upload(P.sorted_ofs.data(), P.sorted_ofs.size() * 4, 16, stream);
+    } else {
+        P.d_colidx_sorted.reset();
+        P.d_vals_sorted.reset();
+        P.d_sorted_ofs.reset();
+    }
     P.d_tiles = dev_upload(P.tiles.data(), P.tiles.size() * 4, 16, stream);
     P.d_long_seg_ptr = dev_upload(P.long_seg_ptr.data(), P.long_seg_ptr.size() * 4, 16, stream);
     size_t nlong = P.long_seg_ptr.empty() ? 0 : P.long_seg_ptr.size() - 1;
@@ -245,6 +259,11 @@ hipError_t spx::run_product(spx_plan_s &P, const double *x, double *y, int32_t a
     a.slot_row = P.d_slot_row ? (const int32_t *)P.d_slot_row->ptr : nullptr;
     a.colidx = (const int32_t *)P.d_colidx->ptr;
     a.vals = (const double *)P.d_vals->ptr;
+    if (P.tune.sort_gathers) {
+        a.scol = (const int32_t *)P.d_colidx_sorted->ptr;
+        a.sval = (const double *)P.d_vals_sorted->ptr;
+        a.sofs = (const int32_t *)P.d_sorted_ofs->ptr;
+    }
     a.x = x;
     a.y = y;
     a.blk_desc = (const int32_t *)P.d_blk_desc->ptr;
@@ -442,6 +461,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->wave_blocks = P->tune.wave_blocks;
         info->pipeline = P->tune.pipeline;
         info->scan_reduce = P->tune.scan;
+        info->sort_gathers = P->tune.sort_gathers;
     });
 }
 
@@ -549,6 +569,17 @@ spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_desc, int32_t *tiles) 
         if (!P) fail(SPX_EINVAL, "NULL handle");
         if (blk_desc) std::copy(P->blk_desc.begin(), P->blk_desc.end(), blk_desc);
         if (tiles) std::copy(P->tiles.begin(), P->tiles.end(), tiles);
+    });
+}
+
+spx_status spx_plan_export_gather_order(spx_plan P, int64_t *len, int32_t *ofs, uint32_t *colidx, double *vals) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (!P->tune.sort_gathers) fail(SPX_EUNSUPPORTED, "the plan is not tuned with sort_gathers");
+        if (len) *len = (int64_t)P->colidx_sorted.size();
+        if (ofs) std::copy(P->sorted_ofs.begin(), P->sorted_ofs.end(), ofs);
+        if (colidx) std::copy(P->colidx_sorted.begin(), P->colidx_sorted.end(), colidx);
+        if (vals) std::copy(P->vals_sorted.begin(), P->vals_sorted.end(), vals);
     });
 }
 

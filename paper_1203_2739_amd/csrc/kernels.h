@@ -29,6 +29,9 @@ struct SpmvArgsT {
     int32_t xcd_remap;        // 1: workgroup w runs unit xcd_ptr[w % 8] + w / 8 of row group w % 8
     int32_t n;                // columns
     int32_t xcd_ptr[kXcdGroups + 1];  // first unit (tile or block) of every row group
+    const int32_t *scol;          // gather-sorted copy (sort_gathers): packed indices, interleaved chunks
+    const V *sval;                // its values
+    const int32_t *sofs;          // its 64-aligned offset of every multi-row block
     const int32_t *long_seg_ptr;  // [nlong+1] partial-sum entries of each long slot
     double *partials;             // one per long-slot segment
     uint32_t *counters;           // one per long slot, zero between products

@@ -154,6 +154,27 @@ __device__ __forceinline__ void block_sync() {
     }
 }
 
+// Row sums of a block whose products sit in row order in sprod (offsets
+// from the block's aligned start), with the row offsets in sptr: each row
+// is summed by 2^floor(log2(WG / rows)) lanes (at most a wave).
+template <int WG, bool SPLIT, class V, class A>
+__device__ __forceinline__ void sum_rows(const SpmvArgsT<V, A> &a, const v4i d, const A *sprod, const int32_t *sptr,
+                                         const int tid) {
+    const int32_t nr = d.y - d.x;
+    // lanes per row: the largest power of two <= WG / nr, at most 64
+    const int q = WG / nr;
+    const int lg = q >= 64 ? 6 : 31 - __builtin_clz(q);
+    const int g = 1 << lg;
+    const int grp = tid >> lg, lane = tid & (g - 1);
+    A sum = 0;
+    if (grp < nr) {
+        const int k1 = sptr[grp + 1];
+        for (int k = sptr[grp] + lane; k < k1; k += g) sum += sprod[k];
+    }
+    sum = group_sum_unrolled(sum, g);
+    if (grp < nr && lane == 0) store_row<SPLIT>(a, d.x + grp, sum);
+}
+
 // One multi-row block: whole slots [d.x, d.y) with nonzeros [d.z, d.w), run
 // by the WG threads of a workgroup (tid = threadIdx.x) or, with WAVE, by the
 // 64 lanes of one wave (WG = 64, tid = lane) on the wave's own LDS slices.
@@ -186,18 +207,45 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
     if (tid <= nr) sptr[tid] = rp0 - zb;
     if (nr == WG && tid == 0) sptr[WG] = rp1 - zb;
     block_sync<WAVE>();
-    // lanes per row: the largest power of two <= WG / nr, at most 64
-    const int q = WG / nr;
-    const int lg = q >= 64 ? 6 : 31 - __builtin_clz(q);
-    const int g = 1 << lg;
-    const int grp = tid >> lg, lane = tid & (g - 1);
-    A sum = 0;
-    if (grp < nr) {
-        const int k1 = sptr[grp + 1];
-        for (int k = sptr[grp] + lane; k < k1; k += g) sum += sprod[k];
+    sum_rows<WG, SPLIT>(a, d, sprod, sptr, tid);
+}
+
+// Gather-sorted blocks: the nonzeros of every multi-row block also live in
+// a second device copy (scol, sval), sorted by column, at a 64-aligned
+// offset sofs[block]; every index carries in its upper bits the nonzero's
+// offset in row order from the block's aligned start.  The copy is
+// interleaved in chunks of 64 sorted entries: the 16 lanes of a quarter
+// wave load one chunk with the usual 16-byte loads, lane l of the quarter
+// holding sorted entries 16 j + l (j = 0..3), so the j-th gather
+// instruction of a quarter reads 16 consecutive sorted columns and lanes
+// that hit one cache line of x share one request.  The last chunk is padded
+// with all-ones indices.  The products go back to their row-order slots in
+// LDS and the rows are summed as in multi_row_block.
+template <int WG, bool SPLIT, class V, class A>
+__device__ __forceinline__ void sorted_row_block(const SpmvArgsT<V, A> &a, const v4i d, int32_t so, A *sprod,
+                                                 int32_t *sptr) {
+    const int tid = threadIdx.x;
+    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.scol);
+    const int32_t zb = d.z & ~3;
+    const int32_t nr = d.y - d.x;  // at most WG (schedule)
+    const int32_t ngroups = ((d.w - d.z + 63) & ~63) >> 2;  // 16-byte groups of the padded chunks
+    const int32_t rp0 = a.slot_ptr[d.x + min(tid, nr)];
+    const int32_t rp1 = (nr == WG && tid == 0) ? a.slot_ptr[d.x + WG] : 0;
+    if (tid < ngroups) {
+        const v4i cc = __builtin_nontemporal_load(&c4[(so >> 2) + tid]);
+        const auto vv = load4(a.sval, so + 4 * tid);
+        const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+        A xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = c[j] != -1 ? a.x[c[j] & kPackColMask] : A(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (c[j] != -1) sprod[(uint32_t)c[j] >> kPackShift] = vv.v[j] * xv[j];
     }
-    sum = group_sum_unrolled(sum, g);
-    if (grp < nr && lane == 0) store_row<SPLIT>(a, d.x + grp, sum);
+    if (tid <= nr) sptr[tid] = rp0 - zb;
+    if (nr == WG && tid == 0) sptr[WG] = rp1 - zb;
+    __syncthreads();
+    sum_rows<WG, SPLIT>(a, d, sprod, sptr, tid);
 }
 
 // Partial sum number `seg` of long (or cut) slot number lr, which is slot
@@ -514,6 +562,20 @@ __global__ __launch_bounds__(WG) void spmv_waves(SpmvArgsT<V, A> a) {
         else long_row_segment<64, NPT, SPLIT, WMAX, true>(a, d, sprod[w], swin, wlo, wlen, lane);
         block_sync<true>();  // the next block rewrites this wave's slices
     }
+}
+
+// One workgroup per gather-sorted block (XCD mapping as in spmv_blocks);
+// long-slot segments as in spmv_blocks, from the stored order.
+template <int WG, bool SPLIT, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_sorted(SpmvArgsT<V, A> a) {
+    __shared__ A sprod[4 * WG];
+    __shared__ int32_t sptr[WG + 1];
+    __shared__ A swave[WG / 64];
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
+    const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
+    if (d.y >= 0) sorted_row_block<WG, SPLIT>(a, d, a.sofs[id], sprod, sptr);
+    else long_row_segment<WG, 4, SPLIT, 0>(a, d, swave, swave, 0, 0);
 }
 
 // ------------------------------------------------------------- scan blocks
@@ -1012,6 +1074,19 @@ hipError_t launch_scan(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t 
     return hipGetLastError();
 }
 
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_sorted(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
+    static_assert(WMAX == 0 && NPT == 4, "gather-sorted blocks: 4 nonzeros per thread, no window");
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
+    if (split)
+        hipLaunchKernelGGL((spmv_sorted<WG, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((spmv_sorted<WG, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
@@ -1029,6 +1104,16 @@ struct ScanTable {
         {256, 4, 0, launch_scan<256, 4, 0, V, A>},
         {512, 4, 0, launch_scan<512, 4, 0, V, A>},
         {1024, 4, 0, launch_scan<1024, 4, 0, V, A>},
+    };
+};
+
+// gather-sorted kernels (binary64; at most 2048 nonzeros per block, so that
+// the offset fits the upper bits of an index)
+struct SortedTable {
+    static constexpr Variant<double, double> v[] = {
+        {128, 4, 0, launch_sorted<128, 4, 0, double, double>},
+        {256, 4, 0, launch_sorted<256, 4, 0, double, double>},
+        {512, 4, 0, launch_sorted<512, 4, 0, double, double>},
     };
 };
 
@@ -1212,6 +1297,7 @@ bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, Kin
         case Kind::Pipe: return find_in<PipeTable<double, double>>(wg, npt, window_entries, wmax_out);
         case Kind::Waves: return find_wave_variant<double, double>(wg, npt, window_entries, wmax_out);
         case Kind::Scan: return find_in<ScanTable<double, double>>(wg, npt, window_entries, wmax_out);
+        case Kind::Sorted: return find_in<SortedTable>(wg, npt, window_entries, wmax_out);
         default: return find_variant<double, double>(wg, npt, window_entries, wmax_out);
     }
 }
@@ -1221,6 +1307,7 @@ bool spmv_lowp_variant_exists(int wg, int npt, Kind k) {
         case Kind::Pipe: return find_in<PipeTable<float, float>>(wg, npt, -1, nullptr);
         case Kind::Waves: return find_wave_variant<float, float>(wg, npt, -1, nullptr);
         case Kind::Scan: return find_in<ScanTable<float, float>>(wg, npt, -1, nullptr);
+        case Kind::Sorted: return false;
         default: return find_variant<float, float>(wg, npt, -1, nullptr);
     }
 }
@@ -1231,6 +1318,7 @@ hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, b
         case Kind::Pipe: return launch_in<PipeTable<double, double>>(a, wg, npt, window_entries, split, s);
         case Kind::Waves: return launch_wave_any(a, wg, npt, window_entries, split, s);
         case Kind::Scan: return launch_in<ScanTable<double, double>>(a, wg, npt, window_entries, split, s);
+        case Kind::Sorted: return launch_in<SortedTable>(a, wg, npt, window_entries, split, s);
         default: return launch_any(a, wg, npt, window_entries, tiled, split, s);
     }
 }
@@ -1242,6 +1330,7 @@ hipError_t launch_lowp(const SpmvArgsT<V, float> &a, int wg, int npt, bool split
         case Kind::Pipe: return launch_in<PipeTable<V, float>>(a, wg, npt, -1, split, s);
         case Kind::Waves: return launch_wave_any(a, wg, npt, -1, split, s);
         case Kind::Scan: return launch_in<ScanTable<V, float>>(a, wg, npt, -1, split, s);
+        case Kind::Sorted: return hipErrorInvalidValue;
         default: return launch_any(a, wg, npt, -1, false, split, s);
     }
 }

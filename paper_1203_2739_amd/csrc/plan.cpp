@@ -521,6 +521,52 @@ static void group_tiles(spx_plan_s &P, const std::vector<int32_t> &xb, int32_t T
 }
 
 
+// Gather-sorted storage (sort_gathers): the nonzeros of every multi-row
+// block sorted by column (ties by position) at a 64-aligned offset, each
+// index carrying in its upper bits the nonzero's offset in row order from
+// the block's 4-aligned start, interleaved in chunks of 64 sorted entries
+// (stored entry 64 k + 4 l + j holds sorted entry 64 k + 16 j + l) and the
+// last chunk padded with all-ones indices and zero values.  Long-slot
+// segments stay in the stored order.  Empty without sort_gathers.
+static void gather_sorted_storage(spx_plan_s &P) {
+    P.colidx_sorted.clear();
+    P.vals_sorted.clear();
+    P.sorted_ofs.clear();
+    if (!P.tune.sort_gathers) return;
+    if (P.n > (1 << kPackShift)) fail(SPX_EUNSUPPORTED, "sort_gathers needs at most 2^21 columns");
+    const int64_t nb = (int64_t)(P.blk_desc.size() / 4);
+    P.sorted_ofs.assign((size_t)nb, -1);
+    int64_t total = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int32_t *d = &P.blk_desc[4 * (size_t)b];
+        if (d[1] < 0) continue;
+        P.sorted_ofs[(size_t)b] = (int32_t)total;
+        total += (d[3] - d[2] + 63) & ~63;
+    }
+    if (total > INT32_MAX) fail(SPX_EUNSUPPORTED, "gather-sorted copy too large");
+    P.colidx_sorted.assign((size_t)total, 0xFFFFFFFFu);
+    P.vals_sorted.assign((size_t)total, 0.0);
+    parallel_for(nb, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> idx;
+        for (int64_t b = lo; b < hi; ++b) {
+            const int32_t *d = &P.blk_desc[4 * (size_t)b];
+            if (d[1] < 0) continue;
+            const int32_t z0 = d[2], z1 = d[3], zb = z0 & ~3;
+            const size_t so = (size_t)P.sorted_ofs[(size_t)b];
+            idx.resize((size_t)(z1 - z0));
+            std::iota(idx.begin(), idx.end(), z0);
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int32_t u, int32_t v) { return P.colidx[u] < P.colidx[v]; });
+            for (int32_t s = 0; s < z1 - z0; ++s) {
+                const int32_t src = idx[(size_t)s];
+                const size_t dst = so + (size_t)(s & ~63) + 4 * (size_t)(s & 15) + (size_t)((s >> 4) & 3);
+                P.colidx_sorted[dst] = (uint32_t)P.colidx[src] | ((uint32_t)(src - zb) << kPackShift);
+                P.vals_sorted[dst] = P.vals[src];
+            }
+        }
+    });
+}
+
 // Lanes the kernel gives to each row of a block of nr rows: the largest
 // power of two <= wg / nr, at most a wave.
 static int32_t lanes_per_row(int32_t wg, int32_t nr) {
@@ -679,6 +725,7 @@ void build_schedule(spx_plan_s &P) {
     group_ptr(false, P.xcd_blk_ptr);
     if (T.tiles_per_group > 0) group_tiles(P, P.xcd_blk_ptr, T.tiles_per_group, T.window_entries);
     group_ptr(true, P.xcd_tile_ptr);
+    gather_sorted_storage(P);
 }
 
 }  // namespace spx

@@ -16,7 +16,12 @@ constexpr int kReduceIters = 64;
 // floor(kXcdGroups * s / nnz)); the kernels run the blocks of group g on XCD
 // g of the MI355X, and the plans order columns by the groups that read them.
 constexpr int kXcdGroups = 8;
-// Kernel that runs a schedule: row blocks, wave blocks, pipelined tiles, or
-// row blocks summed by a segmented scan.
-enum class Kind : int { Blocks = 0, Waves = 1, Pipe = 2, Scan = 3 };
+// Kernel that runs a schedule: row blocks, wave blocks, pipelined tiles, row
+// blocks summed by a segmented scan, or row blocks stored sorted by column.
+enum class Kind : int { Blocks = 0, Waves = 1, Pipe = 2, Scan = 3, Sorted = 4 };
+// Gather-sorted storage: a column index keeps the nonzero's offset in row
+// order from its block's aligned start (below 2048) in its upper 11 bits,
+// so columns must be below 2^21.
+constexpr int kPackShift = 21;
+constexpr int kPackColMask = (1 << kPackShift) - 1;
 }  // namespace spx

@@ -86,7 +86,7 @@ DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream
 struct Tune {
     int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
     int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0, wave_blocks = 0, pipeline = 0;
-    int32_t scan = 0;
+    int32_t scan = 0, sort_gathers = 0;
 };
 Tune resolve_tune(const spx_tune *t, int form);
 inline bool tiled(const Tune &t) {
@@ -95,7 +95,11 @@ inline bool tiled(const Tune &t) {
 // Threads that run one row block: a wave in wave-block schedules.
 inline int32_t block_threads(const Tune &t) { return t.wave_blocks ? 64 : t.wg; }
 inline Kind kind_of(const Tune &t) {
-    return t.pipeline ? Kind::Pipe : t.wave_blocks ? Kind::Waves : t.scan ? Kind::Scan : Kind::Blocks;
+    return t.pipeline      ? Kind::Pipe
+           : t.wave_blocks ? Kind::Waves
+           : t.scan        ? Kind::Scan
+           : t.sort_gathers ? Kind::Sorted
+                            : Kind::Blocks;
 }
 
 }  // namespace spx
@@ -129,12 +133,19 @@ struct spx_plan_s {
     std::vector<int32_t> tiles;                 // 4 per tile
     std::vector<int32_t> long_seg_ptr;          // [nlong+1] first partial-sum entry of each long slot
     std::vector<int32_t> xcd_blk_ptr, xcd_tile_ptr;  // [kXcdGroups+1] first block / tile of each row group
+    // sort_gathers: the nonzeros of every multi-row block sorted by column,
+    // indices carrying the row-order offset in their upper bits, in
+    // interleaved 64-entry chunks at the block's offset sorted_ofs[b]
+    std::vector<uint32_t> colidx_sorted;
+    std::vector<double> vals_sorted;
+    std::vector<int32_t> sorted_ofs;
     std::vector<float> vals32;                  // precision mode: values rounded to binary32
     std::vector<uint16_t> vals16;               // precision mode: binary32 values rounded to bfloat16
     int64_t window_nnz = 0, window_bytes_fill = 0;
     // device copies
     spx::DevPtr d_slot_ptr, d_slot_row, d_colidx, d_vals, d_row_perm, d_col_perm;
     spx::DevPtr d_blk_desc, d_tiles, d_long_seg_ptr, d_partials, d_counters;
+    spx::DevPtr d_colidx_sorted, d_vals_sorted, d_sorted_ofs;
     spx::DevPtr d_vals32, d_vals16;
     // statistics
     int64_t sum_lambda_col = 0, sum_lambda_row = 0, border_row_nnz = 0, cut = 0;

@@ -12,8 +12,9 @@ using namespace spx;
 namespace spx {
 
 // Candidate schedules in the order they are tried: the one-block-per-
-// workgroup kernel at every workgroup size, with lane groups per row and
-// with the segmented-scan row sums; wave blocks at every workgroup
+// workgroup kernel at every workgroup size, with lane groups per row, with
+// the segmented-scan row sums and with gather-sorted blocks; wave blocks at
+// every workgroup
 // size; wave blocks in tiles per row group with an LDS x window, sized so
 // that the tiles of a group are about the workgroups one XCD (32 CUs) keeps
 // resident: one 1024- or 512-thread workgroup per CU with a 120 or 128 KB
@@ -22,7 +23,7 @@ const std::vector<spx_tune> &autotune_candidates() {
     static const std::vector<spx_tune> c = [] {
         std::vector<spx_tune> v;
         auto add = [&v](int wg, int npt, int wave = 0, int tiles = 0, int window = 0, int pipe = 0,
-                        int scan = 0) {
+                        int scan = 0, int sorted = 0) {
             spx_tune t{};
             t.wg_size = wg;
             t.nnz_per_block = (wave ? 64 : wg) * npt;
@@ -31,6 +32,7 @@ const std::vector<spx_tune> &autotune_candidates() {
             t.window_entries = window;
             t.pipeline = pipe;
             t.scan_reduce = scan;
+            t.sort_gathers = sorted;
             v.push_back(t);
         };
         add(128, 4);
@@ -40,6 +42,7 @@ const std::vector<spx_tune> &autotune_candidates() {
         add(128, 8);
         add(256, 8);
         for (int wg : {128, 256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 1);
+        for (int wg : {128, 256, 512}) add(wg, 4, 0, 0, 0, 0, 0, 1);
         add(256, 4, 1);
         add(512, 4, 1);
         add(1024, 4, 1);
@@ -128,6 +131,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
                 }
                 if (!ok || !lowp_schedule_ok(r)) continue;
             }
+            if (cands[c].sort_gathers && P->n > (1 << kPackShift)) continue;  // indices cannot carry offsets
             retune_to(*P, cands[c]);
             for (int w = 0; w < 2; ++w) product();
             hip_check(hipEventRecord(ev.a, s), "event record");
@@ -156,6 +160,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
             chosen->wave_blocks = P->tune.wave_blocks;
             chosen->pipeline = P->tune.pipeline;
             chosen->scan_reduce = P->tune.scan;
+            chosen->sort_gathers = P->tune.sort_gathers;
         }
         if (ms) *ms = best_ms;
     });

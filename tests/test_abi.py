@@ -634,3 +634,90 @@ def test_partition_tree_is_the_k256_partition(form):
     assert parts.size == (A.nnz if form == "split" else A.m)
     assert parts.min() >= 0 and parts.max() <= (256 if form == "db" else 255)
     assert spx.lib().spx_partition_tree(M.handle, 0, 0, None, None) == -1  # the plain form has no tree
+
+
+@pytest.mark.parametrize("form", ["plain", "db", "split"])
+@pytest.mark.parametrize("wg", [128, 512])
+def test_gather_sorted_storage(orc, form, wg):
+    """sort_gathers: every multi-row block has, at its own 64-aligned offset
+    of the second copy, a permutation of its entries in column order, each
+    index holding the column in its low 21 bits and the entry's row-order
+    offset from the block's aligned start above, interleaved in chunks of 64
+    (stored 64 k + 4 l + j holds sorted 64 k + 16 j + l) with all-ones
+    padding; long-slot segments have none.  Placing every product at its
+    offset and summing rows as the kernel does gives the oracle's product."""
+    lens = [0, 3, 1, 1021, 1022, 0, 5, 2045, 7000, 7, 2, 300, 299, 64, 65] + [1, 2, 3, 40] * 400
+    A = long_row_csr(lens, 9000)
+    x = np.random.default_rng(8).uniform(-1, 1, A.n)
+    M = spx.from_csr(A, device=False)
+    tune = dict(wg_size=wg, sort_gathers=1)
+    if form == "plain":
+        P, rq, cq = spx.plan_plain(M, tune=tune), np.arange(A.m), np.arange(A.n)
+    else:
+        P, rq, cq, _ = (spx.reorder_db if form == "db" else spx.split)(M, 4, 0, 2, tune=tune)
+    assert P.info()["sort_gathers"] == 1
+    check_schedule(P)
+    if form == "split":
+        ex = P.export_split()
+        sp, ci, va, srow = ex["slot_ptr"].astype(np.int64), ex["colidx"], ex["vals"], ex["slot_row"]
+    else:
+        sp, ci, va = P.export_csr()
+        sp, srow = sp.astype(np.int64), np.arange(A.m)
+    ofs, cs, vs = P.export_gather_order()
+    bd, _ = P.export_sched()
+    xs = x[cq]
+    slot_sum = np.zeros(sp.size - 1)
+    seen = np.zeros(ci.size, np.int64)
+    used = np.zeros(cs.size, np.int64)
+    for b, (s_lo, s_hi, z0, z1) in enumerate(bd):
+        if s_hi < 0:
+            assert ofs[b] == -1
+            slot_sum[s_lo] += (va[z0:z1] * xs[ci[z0:z1]]).sum()
+            continue
+        so, L = int(ofs[b]), int(z1 - z0)
+        Lp = (L + 63) & ~63
+        assert so % 64 == 0 and so + Lp <= cs.size
+        used[so:so + Lp] += 1
+        s = np.arange(Lp)
+        where = so + (s & ~63) + 4 * (s & 15) + ((s >> 4) & 3)
+        S, V = cs[where[:L]], vs[where[:L]]
+        assert np.all(cs[where[L:]] == 0xFFFFFFFF) and np.all(vs[where[L:]] == 0)
+        col, off = (S & ((1 << 21) - 1)).astype(np.int64), (S >> 21).astype(np.int64)
+        zb = z0 & ~3
+        src = zb + off
+        assert np.all(np.diff(col) >= 0) and np.all(col < A.n)  # column order
+        assert np.all((src >= z0) & (src < z1))
+        np.add.at(seen, src, 1)
+        assert np.array_equal(ci[src], col) and np.array_equal(va[src], V)
+        prod = np.zeros(z1 - zb)
+        prod[off] = V * xs[col]
+        for r in range(s_lo, s_hi):
+            slot_sum[r] = prod[sp[r] - zb:sp[r + 1] - zb].sum()
+    assert np.all(used <= 1)
+    multi = np.zeros(ci.size, bool)
+    for s_lo, s_hi, z0, z1 in bd:
+        if s_hi >= 0:
+            multi[z0:z1] = True
+    assert np.all(seen[multi] == 1)
+    y = np.zeros(A.m)
+    np.add.at(y, srow, slot_sum)
+    ref, den = orc.spmv(A, x)[rq], orc.abs_rowsum(A, x)[rq]
+    assert np.all(np.abs(y - ref) <= 1e-12 * den)
+
+
+def test_gather_sorted_limits():
+    """sort_gathers needs column indices below 2^21 and runs only untiled
+    binary64 workgroup blocks of 4 nonzeros per thread."""
+    A = CSR(2, (1 << 21) + 1, np.array([0, 1, 2]), np.array([0, 1 << 21], np.int32), np.ones(2))
+    M = spx.from_csr(A, device=False)
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M, tune=dict(sort_gathers=1))
+    M = spx.from_csr(small_csr(), device=False)
+    for bad in (dict(sort_gathers=1, scan_reduce=1), dict(sort_gathers=1, blocks_per_tile=2),
+                dict(sort_gathers=1, wg_size=1024), dict(sort_gathers=1, wg_size=256, nnz_per_block=2048),
+                dict(sort_gathers=1, wg_size=64)):
+        with pytest.raises(spx.SpxError):
+            spx.plan_plain(M, tune=bad)
+    P = spx.plan_plain(M)
+    with pytest.raises(spx.SpxError):
+        P.export_gather_order()

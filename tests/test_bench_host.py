@@ -49,6 +49,7 @@ def test_schedule_names():
     assert bench.schedule_name([512, 2048, 1, 16384, 32, 0]) == "512x4t32W16384"
     assert bench.schedule_name([512, 2048, 1, -1, 0, 0, 0, 1]) == "512x4s"
     assert bench.schedule_name([512, 2048, 1, -1, 128, 0, 1, 0]) == "512x4pt128"
+    assert bench.schedule_name([512, 2048, 1, -1, 0, 0, 0, 0, 1]) == "512x4g"
 
 
 def test_plan_hash_sees_every_part_of_the_layout():

@@ -62,8 +62,12 @@ TUNES = [None,
          dict(wg_size=128, scan_reduce=1),
          dict(wg_size=512, scan_reduce=1),
          dict(wg_size=1024, scan_reduce=1, xcd_remap=-1),
-         dict(wg_size=256, scan_reduce=1, reduce_iters=1)]
+         dict(wg_size=256, scan_reduce=1, reduce_iters=1),
+         dict(wg_size=128, sort_gathers=1),
+         dict(wg_size=512, sort_gathers=1),
+         dict(wg_size=256, sort_gathers=1, xcd_remap=-1, reduce_iters=3)]
 SCAN_TUNES = [t for t in TUNES if t and t.get("scan_reduce")]
+SORTED_TUNES = [t for t in TUNES if t and t.get("sort_gathers")]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNES)))
@@ -77,7 +81,7 @@ def test_plain_c1(orc, ti):
 def test_plain_c1_integer_exact(orc):
     A, x = integer_problem(gen_c1(), 5)
     assert np.array_equal(run_plain(A, x), orc.spmv(A, x))
-    for t in SCAN_TUNES:
+    for t in SCAN_TUNES + SORTED_TUNES:
         assert np.array_equal(run_plain(A, x, t), orc.spmv(A, x)), t
 
 
@@ -98,8 +102,9 @@ def test_reordered_c1_integer_exact(orc, form):
     A, x = integer_problem(gen_c1(), 9)
     y, rp, cp, part, P = run_reordered(A, x, form, 8)
     assert np.array_equal(y, orc.spmv(A, x)[rp])
-    y, rp, cp, part, P = run_reordered(A, x, form, 8, tune=SCAN_TUNES[1])
-    assert np.array_equal(y, orc.spmv(A, x)[rp])
+    for t in (SCAN_TUNES[1], SORTED_TUNES[1]):
+        y, rp, cp, part, P = run_reordered(A, x, form, 8, tune=t)
+        assert np.array_equal(y, orc.spmv(A, x)[rp]), t
 
 
 WINDOW_TUNES = [dict(window_entries=4096, blocks_per_tile=64, wg_size=128),
@@ -187,7 +192,7 @@ def test_edge_shapes(orc, shape, long_len):
     m, n = shape
     A = odd_matrix(m * 7 + n, m, n, long_len=long_len if n >= long_len else 0)
     x = gen_vectors(107, n)[0]
-    for ti in (0, 1, 3, 5, len(TUNES) - 4, len(TUNES) - 1):
+    for ti in (0, 1, 3, 5, TUNES.index(SCAN_TUNES[0]), TUNES.index(SCAN_TUNES[-1]), len(TUNES) - 1):
         y = run_plain(A, x, TUNES[ti])
         assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), f"plain {shape} {long_len}")
     if A.nnz:
@@ -240,6 +245,11 @@ def test_larger_irregular(orc):
     y, rp, cp, part, P = run_reordered(A, x, "db", 16, window_bytes=8192 * 8,
                                        tune=dict(window_entries=8192, blocks_per_tile=16))
     assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], "zipf 200k db window")
+    for t in SORTED_TUNES + SCAN_TUNES:
+        y = run_plain(A, x, t)
+        assert_close_rowwise(y, orc.spmv(A, x), orc.abs_rowsum(A, x), f"zipf 200k {t}")
+    y, rp, cp, part, P = run_reordered(A, x, "split", 16, tune=SORTED_TUNES[1])
+    assert_close_rowwise(y, orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp], "zipf 200k split sorted")
 
 
 def test_rows_cut_into_segments(orc):
@@ -255,7 +265,8 @@ def test_rows_cut_into_segments(orc):
     A = CSR(len(lens), n, rp, cols.astype(np.int32), rng.uniform(-1, 1, cols.size))
     x = gen_vectors(110, n)[0]
     ref, den = orc.spmv(A, x), orc.abs_rowsum(A, x)
-    for t in (None, dict(wg_size=64), dict(wg_size=512), dict(blocks_per_tile=3), dict(wg_size=256, scan_reduce=1)):
+    for t in (None, dict(wg_size=64), dict(wg_size=512), dict(blocks_per_tile=3), dict(wg_size=256, scan_reduce=1),
+              dict(wg_size=512, sort_gathers=1)):
         M = spx.from_csr(A)
         P = spx.plan_plain(M, tune=t)
         assert P.info()["nlong_rows"] >= 4
@@ -302,7 +313,7 @@ def test_split_deterministic_and_retune(orc):
     spx.permute_x(P, xd, xh)
     ref, den = orc.spmv(A, x)[rp], orc.abs_rowsum(A, x)[rp]
     for t in (None, dict(wg_size=512), dict(wg_size=64), dict(reduce_iters=2, wg_size=256),
-              dict(wg_size=512, scan_reduce=1)):
+              dict(wg_size=512, scan_reduce=1), dict(wg_size=512, sort_gathers=1), dict(wg_size=128)):
         spx.plan_retune(P, t)
         outs = []
         for rep in range(3):
