@@ -117,12 +117,15 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *   sort_gathers     0 (default) or 1: binary64 products from a second
  *                    device copy in which the nonzeros of every multi-row
  *                    block are sorted by column, each index carrying the
- *                    nonzero's row-order offset in its upper 11 bits; the
- *                    x gathers of a quarter wave then read 16 consecutive
- *                    columns of the block, so lanes that hit one cache line
- *                    share one request.  wg_size 128, 256 or 512 with 4 nonzeros per
- *                    thread; at most 2^21 columns (SPX_EUNSUPPORTED
- *                    otherwise); no tiles, windows, wave_blocks, pipeline or
+ *                    nonzero's row-order offset in its upper
+ *                    ceil(log2 nnz_per_block) bits; the x gathers of a
+ *                    quarter wave then read 16 consecutive columns of the
+ *                    block, so lanes that hit one cache line share one
+ *                    request, more often the larger the block.  wg_size
+ *                    128, 256, 512 or 1024 with 4 nonzeros per thread, 256
+ *                    or 512 with 8; at most 2^(32 - ceil(log2
+ *                    nnz_per_block)) columns (SPX_EUNSUPPORTED otherwise);
+ *                    no tiles, windows, wave_blocks, pipeline or
  *                    scan_reduce; not for the precision mode.
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
@@ -589,7 +592,8 @@ spx_status spx_select_exhaustive_trees(spx_mat A, const int32_t *tree_sb, const 
  * spx_plan_export_gather_order: the gather-sorted copy of a plan tuned with
  *   sort_gathers: *len entries in all, ofs[nblocks] (offset of every
  *   multi-row block, -1 for long-slot segments), colidx[len] (column |
- *   row-order offset << 21, all ones for padding: chunk k of a block holds
+ *   row-order offset << (32 - ceil(log2 nnz_per_block)), all ones for
+ *   padding: chunk k of a block holds
  *   sorted entry 64 k + 16 j + l at 64 k + 4 l + j) and vals[len];
  *   SPX_EUNSUPPORTED for other schedules.
  */

@@ -80,10 +80,10 @@ Tune resolve_tune(const spx_tune *t, int form) {
                            r.blocks_per_tile > 1 || (t && t->window_entries > 0)))
         fail(SPX_EINVAL, "sort_gathers runs one block per workgroup: no tiles, windows, wave blocks, pipeline "
                          "or scan_reduce");
-    if (!r.wave_blocks && !r.pipeline && !r.scan && r.wg == 1024 &&
+    if (!r.wave_blocks && !r.pipeline && !r.scan && !r.sort_gathers && r.wg == 1024 &&
         (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
-        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only scan blocks, wave blocks, pipelined tiles or tiles per "
-                               "row group with an LDS window");
+        fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only scan blocks, gather-sorted blocks, wave blocks, pipelined "
+                               "tiles or tiles per row group with an LDS window");
     const int32_t bt = block_threads(r);
     if (!t || !t->nnz_per_block) r.nnz_per_block = (bt == 64 && !r.wave_blocks ? 8 : kDefaultNpt) * bt;
     if (r.nnz_per_block != 4 * bt && r.nnz_per_block != 8 * bt)

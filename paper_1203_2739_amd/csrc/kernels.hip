@@ -221,9 +221,11 @@ __device__ __forceinline__ void multi_row_block(const SpmvArgsT<V, A> &a, const 
 // that hit one cache line of x share one request.  The last chunk is padded
 // with all-ones indices.  The products go back to their row-order slots in
 // LDS and the rows are summed as in multi_row_block.
-template <int WG, bool SPLIT, class V, class A>
+template <int WG, int NPT, bool SPLIT, class V, class A>
 __device__ __forceinline__ void sorted_row_block(const SpmvArgsT<V, A> &a, const v4i d, int32_t so, A *sprod,
                                                  int32_t *sptr) {
+    constexpr int SH = pack_shift(WG * NPT);
+    constexpr int MASK = (1 << SH) - 1;
     const int tid = threadIdx.x;
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.scol);
     const int32_t zb = d.z & ~3;
@@ -231,16 +233,20 @@ __device__ __forceinline__ void sorted_row_block(const SpmvArgsT<V, A> &a, const
     const int32_t ngroups = ((d.w - d.z + 63) & ~63) >> 2;  // 16-byte groups of the padded chunks
     const int32_t rp0 = a.slot_ptr[d.x + min(tid, nr)];
     const int32_t rp1 = (nr == WG && tid == 0) ? a.slot_ptr[d.x + WG] : 0;
-    if (tid < ngroups) {
-        const v4i cc = __builtin_nontemporal_load(&c4[(so >> 2) + tid]);
-        const auto vv = load4(a.sval, so + 4 * tid);
-        const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
-        A xv[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = c[j] != -1 ? a.x[c[j] & kPackColMask] : A(0);
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid + u * WG;
+        if (gi < ngroups) {
+            const v4i cc = __builtin_nontemporal_load(&c4[(so >> 2) + gi]);
+            const auto vv = load4(a.sval, so + 4 * gi);
+            const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+            A xv[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (c[j] != -1) sprod[(uint32_t)c[j] >> kPackShift] = vv.v[j] * xv[j];
+            for (int j = 0; j < 4; ++j) xv[j] = c[j] != -1 ? a.x[c[j] & MASK] : A(0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c[j] != -1) sprod[(uint32_t)c[j] >> SH] = vv.v[j] * xv[j];
+        }
     }
     if (tid <= nr) sptr[tid] = rp0 - zb;
     if (nr == WG && tid == 0) sptr[WG] = rp1 - zb;
@@ -566,16 +572,16 @@ __global__ __launch_bounds__(WG) void spmv_waves(SpmvArgsT<V, A> a) {
 
 // One workgroup per gather-sorted block (XCD mapping as in spmv_blocks);
 // long-slot segments as in spmv_blocks, from the stored order.
-template <int WG, bool SPLIT, class V, class A>
+template <int WG, int NPT, bool SPLIT, class V, class A>
 __global__ __launch_bounds__(WG) void spmv_sorted(SpmvArgsT<V, A> a) {
-    __shared__ A sprod[4 * WG];
+    __shared__ A sprod[NPT * WG];
     __shared__ int32_t sptr[WG + 1];
     __shared__ A swave[WG / 64];
     const int id = unit_of(a, blockIdx.x);
     if (id < 0) return;
     const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
-    if (d.y >= 0) sorted_row_block<WG, SPLIT>(a, d, a.sofs[id], sprod, sptr);
-    else long_row_segment<WG, 4, SPLIT, 0>(a, d, swave, swave, 0, 0);
+    if (d.y >= 0) sorted_row_block<WG, NPT, SPLIT>(a, d, a.sofs[id], sprod, sptr);
+    else long_row_segment<WG, NPT, SPLIT, 0>(a, d, swave, swave, 0, 0);
 }
 
 // ------------------------------------------------------------- scan blocks
@@ -1076,14 +1082,14 @@ hipError_t launch_scan(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t 
 
 template <int WG, int NPT, int WMAX, class V, class A>
 hipError_t launch_sorted(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
-    static_assert(WMAX == 0 && NPT == 4, "gather-sorted blocks: 4 nonzeros per thread, no window");
+    static_assert(WMAX == 0, "gather-sorted blocks take no window");
     if (a0.ntiles <= 0) return hipSuccess;
     SpmvArgsT<V, A> a = a0;
     const unsigned grid = grid_of_units(a);
     if (split)
-        hipLaunchKernelGGL((spmv_sorted<WG, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((spmv_sorted<WG, NPT, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
     else
-        hipLaunchKernelGGL((spmv_sorted<WG, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((spmv_sorted<WG, NPT, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1107,13 +1113,15 @@ struct ScanTable {
     };
 };
 
-// gather-sorted kernels (binary64; at most 2048 nonzeros per block, so that
-// the offset fits the upper bits of an index)
+// gather-sorted kernels (binary64)
 struct SortedTable {
     static constexpr Variant<double, double> v[] = {
         {128, 4, 0, launch_sorted<128, 4, 0, double, double>},
         {256, 4, 0, launch_sorted<256, 4, 0, double, double>},
         {512, 4, 0, launch_sorted<512, 4, 0, double, double>},
+        {1024, 4, 0, launch_sorted<1024, 4, 0, double, double>},
+        {256, 8, 0, launch_sorted<256, 8, 0, double, double>},
+        {512, 8, 0, launch_sorted<512, 8, 0, double, double>},
     };
 };
 

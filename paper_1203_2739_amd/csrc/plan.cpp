@@ -523,8 +523,9 @@ static void group_tiles(spx_plan_s &P, const std::vector<int32_t> &xb, int32_t T
 
 // Gather-sorted storage (sort_gathers): the nonzeros of every multi-row
 // block sorted by column (ties by position) at a 64-aligned offset, each
-// index carrying in its upper bits the nonzero's offset in row order from
-// the block's 4-aligned start, interleaved in chunks of 64 sorted entries
+// index carrying in its upper bits (from bit pack_shift(nnz_per_block)) the
+// nonzero's offset in row order from the block's 4-aligned start,
+// interleaved in chunks of 64 sorted entries
 // (stored entry 64 k + 4 l + j holds sorted entry 64 k + 16 j + l) and the
 // last chunk padded with all-ones indices and zero values.  Long-slot
 // segments stay in the stored order.  Empty without sort_gathers.
@@ -533,7 +534,10 @@ static void gather_sorted_storage(spx_plan_s &P) {
     P.vals_sorted.clear();
     P.sorted_ofs.clear();
     if (!P.tune.sort_gathers) return;
-    if (P.n > (1 << kPackShift)) fail(SPX_EUNSUPPORTED, "sort_gathers needs at most 2^21 columns");
+    const int sh = pack_shift(P.tune.nnz_per_block);
+    if ((int64_t)P.n > ((int64_t)1 << sh))
+        fail(SPX_EUNSUPPORTED, "sort_gathers: too many columns for the block's offsets (at most 2^(32 - "
+                               "log2 nnz_per_block))");
     const int64_t nb = (int64_t)(P.blk_desc.size() / 4);
     P.sorted_ofs.assign((size_t)nb, -1);
     int64_t total = 0;
@@ -560,7 +564,7 @@ static void gather_sorted_storage(spx_plan_s &P) {
             for (int32_t s = 0; s < z1 - z0; ++s) {
                 const int32_t src = idx[(size_t)s];
                 const size_t dst = so + (size_t)(s & ~63) + 4 * (size_t)(s & 15) + (size_t)((s >> 4) & 3);
-                P.colidx_sorted[dst] = (uint32_t)P.colidx[src] | ((uint32_t)(src - zb) << kPackShift);
+                P.colidx_sorted[dst] = (uint32_t)P.colidx[src] | ((uint32_t)(src - zb) << sh);
                 P.vals_sorted[dst] = P.vals[src];
             }
         }

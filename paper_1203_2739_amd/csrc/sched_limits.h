@@ -20,8 +20,12 @@ constexpr int kXcdGroups = 8;
 // blocks summed by a segmented scan, or row blocks stored sorted by column.
 enum class Kind : int { Blocks = 0, Waves = 1, Pipe = 2, Scan = 3, Sorted = 4 };
 // Gather-sorted storage: a column index keeps the nonzero's offset in row
-// order from its block's aligned start (below 2048) in its upper 11 bits,
-// so columns must be below 2^21.
-constexpr int kPackShift = 21;
-constexpr int kPackColMask = (1 << kPackShift) - 1;
+// order from its block's aligned start (below nt, the block's capacity) in
+// its upper bits; the column takes the low pack_shift(nt) bits, so columns
+// must be below 2^pack_shift(nt).
+constexpr int pack_shift(int nt) {
+    int b = 0;
+    while ((1 << b) < nt) ++b;
+    return 32 - b;
+}
 }  // namespace spx

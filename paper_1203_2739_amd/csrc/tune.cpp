@@ -42,7 +42,9 @@ const std::vector<spx_tune> &autotune_candidates() {
         add(128, 8);
         add(256, 8);
         for (int wg : {128, 256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 1);
-        for (int wg : {128, 256, 512}) add(wg, 4, 0, 0, 0, 0, 0, 1);
+        for (int wg : {128, 256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 0, 1);
+        add(256, 8, 0, 0, 0, 0, 0, 1);
+        add(512, 8, 0, 0, 0, 0, 0, 1);
         add(256, 4, 1);
         add(512, 4, 1);
         add(1024, 4, 1);
@@ -131,7 +133,8 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
                 }
                 if (!ok || !lowp_schedule_ok(r)) continue;
             }
-            if (cands[c].sort_gathers && P->n > (1 << kPackShift)) continue;  // indices cannot carry offsets
+            // indices cannot carry the offsets
+            if (cands[c].sort_gathers && (int64_t)P->n > ((int64_t)1 << pack_shift(cands[c].nnz_per_block))) continue;
             retune_to(*P, cands[c]);
             for (int w = 0; w < 2; ++w) product();
             hip_check(hipEventRecord(ev.a, s), "event record");

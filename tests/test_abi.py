@@ -637,12 +637,13 @@ def test_partition_tree_is_the_k256_partition(form):
 
 
 @pytest.mark.parametrize("form", ["plain", "db", "split"])
-@pytest.mark.parametrize("wg", [128, 512])
-def test_gather_sorted_storage(orc, form, wg):
+@pytest.mark.parametrize("wg,npt", [(128, 4), (512, 4), (512, 8), (1024, 4)])
+def test_gather_sorted_storage(orc, form, wg, npt):
     """sort_gathers: every multi-row block has, at its own 64-aligned offset
     of the second copy, a permutation of its entries in column order, each
-    index holding the column in its low 21 bits and the entry's row-order
-    offset from the block's aligned start above, interleaved in chunks of 64
+    index holding the column in its low 32 - ceil(log2 nnz_per_block) bits
+    and the entry's row-order offset from the block's aligned start above,
+    interleaved in chunks of 64
     (stored 64 k + 4 l + j holds sorted 64 k + 16 j + l) with all-ones
     padding; long-slot segments have none.  Placing every product at its
     offset and summing rows as the kernel does gives the oracle's product."""
@@ -650,7 +651,8 @@ def test_gather_sorted_storage(orc, form, wg):
     A = long_row_csr(lens, 9000)
     x = np.random.default_rng(8).uniform(-1, 1, A.n)
     M = spx.from_csr(A, device=False)
-    tune = dict(wg_size=wg, sort_gathers=1)
+    tune = dict(wg_size=wg, nnz_per_block=wg * npt, sort_gathers=1)
+    sh = 32 - int(np.ceil(np.log2(wg * npt)))
     if form == "plain":
         P, rq, cq = spx.plan_plain(M, tune=tune), np.arange(A.m), np.arange(A.n)
     else:
@@ -682,7 +684,7 @@ def test_gather_sorted_storage(orc, form, wg):
         where = so + (s & ~63) + 4 * (s & 15) + ((s >> 4) & 3)
         S, V = cs[where[:L]], vs[where[:L]]
         assert np.all(cs[where[L:]] == 0xFFFFFFFF) and np.all(vs[where[L:]] == 0)
-        col, off = (S & ((1 << 21) - 1)).astype(np.int64), (S >> 21).astype(np.int64)
+        col, off = (S & ((1 << sh) - 1)).astype(np.int64), (S >> sh).astype(np.int64)
         zb = z0 & ~3
         src = zb + off
         assert np.all(np.diff(col) >= 0) and np.all(col < A.n)  # column order
@@ -706,15 +708,16 @@ def test_gather_sorted_storage(orc, form, wg):
 
 
 def test_gather_sorted_limits():
-    """sort_gathers needs column indices below 2^21 and runs only untiled
-    binary64 workgroup blocks of 4 nonzeros per thread."""
+    """sort_gathers needs column indices below 2^(32 - ceil(log2
+    nnz_per_block)) and runs only untiled binary64 workgroup blocks."""
     A = CSR(2, (1 << 21) + 1, np.array([0, 1, 2]), np.array([0, 1 << 21], np.int32), np.ones(2))
     M = spx.from_csr(A, device=False)
     with pytest.raises(spx.SpxError):
-        spx.plan_plain(M, tune=dict(sort_gathers=1))
+        spx.plan_plain(M, tune=dict(wg_size=512, sort_gathers=1))
+    assert spx.plan_plain(M, tune=dict(wg_size=256, sort_gathers=1)).info()["sort_gathers"] == 1
     M = spx.from_csr(small_csr(), device=False)
     for bad in (dict(sort_gathers=1, scan_reduce=1), dict(sort_gathers=1, blocks_per_tile=2),
-                dict(sort_gathers=1, wg_size=1024), dict(sort_gathers=1, wg_size=256, nnz_per_block=2048),
+                dict(sort_gathers=1, wg_size=1024, nnz_per_block=8192), dict(sort_gathers=1, wg_size=128, nnz_per_block=1024),
                 dict(sort_gathers=1, wg_size=64)):
         with pytest.raises(spx.SpxError):
             spx.plan_plain(M, tune=bad)

@@ -65,7 +65,9 @@ TUNES = [None,
          dict(wg_size=256, scan_reduce=1, reduce_iters=1),
          dict(wg_size=128, sort_gathers=1),
          dict(wg_size=512, sort_gathers=1),
-         dict(wg_size=256, sort_gathers=1, xcd_remap=-1, reduce_iters=3)]
+         dict(wg_size=256, sort_gathers=1, xcd_remap=-1, reduce_iters=3),
+         dict(wg_size=512, nnz_per_block=4096, sort_gathers=1),
+         dict(wg_size=1024, sort_gathers=1)]
 SCAN_TUNES = [t for t in TUNES if t and t.get("scan_reduce")]
 SORTED_TUNES = [t for t in TUNES if t and t.get("sort_gathers")]
 
