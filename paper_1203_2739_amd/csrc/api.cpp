@@ -76,10 +76,9 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (r.scan && (r.wave_blocks || r.pipeline || r.tiles_per_group > 0 || r.blocks_per_tile > 1 ||
                    (t && t->window_entries > 0)))
         fail(SPX_EINVAL, "scan_reduce runs one block per workgroup: no tiles, windows, wave blocks or pipeline");
-    if (r.sort_gathers && (r.scan || r.wave_blocks || r.pipeline || r.tiles_per_group > 0 ||
-                           r.blocks_per_tile > 1 || (t && t->window_entries > 0)))
-        fail(SPX_EINVAL, "sort_gathers runs one block per workgroup: no tiles, windows, wave blocks, pipeline "
-                         "or scan_reduce");
+    if (r.sort_gathers && (r.wave_blocks || r.pipeline || r.tiles_per_group > 0 || r.blocks_per_tile > 1 ||
+                           (t && t->window_entries > 0)))
+        fail(SPX_EINVAL, "sort_gathers runs one block per workgroup: no tiles, windows, wave blocks or pipeline");
     if (!r.wave_blocks && !r.pipeline && !r.scan && !r.sort_gathers && r.wg == 1024 &&
         (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
         fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only scan blocks, gather-sorted blocks, wave blocks, pipelined "

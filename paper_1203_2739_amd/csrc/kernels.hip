@@ -613,54 +613,36 @@ __device__ __forceinline__ void wave_seg_scan(A &s, int &f, int lane) {
     }
 }
 
-// One multi-row block summed by the scan.  send[r] is the block-relative
-// position of the last nonzero of row d.x + r (-1 for an empty row),
-// sowner[k] the row ending at position k.  sowner is not cleared between
-// blocks: a thread takes sowner[k] = r as a row end only when r is a row of
-// this block whose send[r] is k, and a row that ends at k has written
-// exactly that pair, so a stale entry is either rejected or right.
-template <int WG, int NPT, bool SPLIT, class V, class A>
-__device__ __forceinline__ void scan_row_block(const SpmvArgsT<V, A> &a, const v4i d, int16_t *send,
-                                               uint16_t *sowner, A *sws, int32_t *swf) {
-    static_assert(NPT == 4 || NPT == 8, "4 or 8 nonzeros per thread");
-    constexpr int NW = WG / 64;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
+// Records the ends of the rows of a block for the scan: send[r] is the
+// block-relative position of the last nonzero of row d.x + r (-1 for an
+// empty row, which is written as zero here), sowner[k] the row ending at
+// position k.  sowner is not cleared between blocks: the scan takes
+// sowner[k] = r as a row end only when r is a row of this block whose
+// send[r] is k, and a row that ends at k has written exactly that pair, so
+// a stale entry is either rejected or right.  rb, re: the row's bounds.
+template <bool SPLIT, class V, class A>
+__device__ __forceinline__ void mark_row_ends(const SpmvArgsT<V, A> &a, const v4i d, int32_t rb, int32_t re,
+                                              int16_t *send, uint16_t *sowner) {
+    const int tid = threadIdx.x;
     const int32_t zb = d.z & ~3;
-    const int32_t nr = d.y - d.x;  // at most WG (schedule)
-    const int32_t G = (d.w - zb + 3) >> 2;
-    // row bounds first, so that their latency overlaps the data loads
-    const int32_t rb = tid < nr ? a.slot_ptr[d.x + tid] : 0;
-    const int32_t re = tid < nr ? a.slot_ptr[d.x + tid + 1] : 0;
-    A p[NPT];
-#pragma unroll
-    for (int u = 0; u < NPT / 4; ++u) {
-        const int gi = tid * (NPT / 4) + u;
-        const int32_t k0 = zb + 4 * gi;
-        A q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-        if (gi < G) {
-            const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
-            const auto vv = load4(a.vals, k0);
-            q0 = vv.v[0] * a.x[cc.x];
-            q1 = vv.v[1] * a.x[cc.y];
-            q2 = vv.v[2] * a.x[cc.z];
-            q3 = vv.v[3] * a.x[cc.w];
-        }
-        // entries of the aligned start before d.z, and from d.w on, belong
-        // to other blocks
-        p[4 * u + 0] = (k0 >= d.z && k0 < d.w) ? q0 : A(0);
-        p[4 * u + 1] = (k0 + 1 >= d.z && k0 + 1 < d.w) ? q1 : A(0);
-        p[4 * u + 2] = (k0 + 2 >= d.z && k0 + 2 < d.w) ? q2 : A(0);
-        p[4 * u + 3] = (k0 + 3 >= d.z && k0 + 3 < d.w) ? q3 : A(0);
-    }
-    if (tid < nr) {
+    if (tid < d.y - d.x) {
         // rows of a block lie in [d.z, d.w), which spans at most WG NPT
         // entries from zb
         send[tid] = re > rb ? (int16_t)(re - 1 - zb) : (int16_t)-1;
         if (re > rb) sowner[re - 1 - zb] = (uint16_t)tid;
         else store_row<SPLIT>(a, d.x + tid, A(0));
     }
-    __syncthreads();  // row ends recorded
+}
+
+// Row sums of a block by the segmented scan, once the row ends are marked
+// (mark_row_ends, then a barrier): p holds the products of this thread's
+// NPT consecutive positions (zero outside the block's nonzeros).
+template <int WG, int NPT, bool SPLIT, class V, class A>
+__device__ __forceinline__ void scan_sum_rows(const SpmvArgsT<V, A> &a, const v4i d, const A *p, const int16_t *send,
+                                              const uint16_t *sowner, A *sws, int32_t *swf) {
+    constexpr int NW = WG / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int32_t nr = d.y - d.x;
     uint32_t ends = 0;
     int32_t rows[NPT];
 #pragma unroll
@@ -708,6 +690,82 @@ __device__ __forceinline__ void scan_row_block(const SpmvArgsT<V, A> &a, const v
     }
 }
 
+// One multi-row block summed by the scan, products computed in registers.
+template <int WG, int NPT, bool SPLIT, class V, class A>
+__device__ __forceinline__ void scan_row_block(const SpmvArgsT<V, A> &a, const v4i d, int16_t *send,
+                                               uint16_t *sowner, A *sws, int32_t *swf) {
+    static_assert(NPT == 4 || NPT == 8, "4 or 8 nonzeros per thread");
+    const int tid = threadIdx.x;
+    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.colidx);
+    const int32_t zb = d.z & ~3;
+    const int32_t nr = d.y - d.x;  // at most WG (schedule)
+    const int32_t G = (d.w - zb + 3) >> 2;
+    // row bounds first, so that their latency overlaps the data loads
+    const int32_t rb = tid < nr ? a.slot_ptr[d.x + tid] : 0;
+    const int32_t re = tid < nr ? a.slot_ptr[d.x + tid + 1] : 0;
+    A p[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid * (NPT / 4) + u;
+        const int32_t k0 = zb + 4 * gi;
+        A q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+        if (gi < G) {
+            const v4i cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
+            const auto vv = load4(a.vals, k0);
+            q0 = vv.v[0] * a.x[cc.x];
+            q1 = vv.v[1] * a.x[cc.y];
+            q2 = vv.v[2] * a.x[cc.z];
+            q3 = vv.v[3] * a.x[cc.w];
+        }
+        // entries of the aligned start before d.z, and from d.w on, belong
+        // to other blocks
+        p[4 * u + 0] = (k0 >= d.z && k0 < d.w) ? q0 : A(0);
+        p[4 * u + 1] = (k0 + 1 >= d.z && k0 + 1 < d.w) ? q1 : A(0);
+        p[4 * u + 2] = (k0 + 2 >= d.z && k0 + 2 < d.w) ? q2 : A(0);
+        p[4 * u + 3] = (k0 + 3 >= d.z && k0 + 3 < d.w) ? q3 : A(0);
+    }
+    mark_row_ends<SPLIT>(a, d, rb, re, send, sowner);
+    __syncthreads();  // row ends recorded
+    scan_sum_rows<WG, NPT, SPLIT>(a, d, p, send, sowner, sws, swf);
+}
+
+// One gather-sorted block summed by the scan: the products of the sorted
+// loads go to their row-order slots in LDS (as in sorted_row_block), and
+// every thread then takes its 4 consecutive row-order products from there.
+template <int WG, bool SPLIT, class V, class A>
+__device__ __forceinline__ void sorted_scan_block(const SpmvArgsT<V, A> &a, const v4i d, int32_t so, A *sprod,
+                                                  int16_t *send, uint16_t *sowner, A *sws, int32_t *swf) {
+    constexpr int SH = pack_shift(WG * 4);
+    constexpr int MASK = (1 << SH) - 1;
+    const int tid = threadIdx.x;
+    const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.scol);
+    const int32_t zb = d.z & ~3;
+    const int32_t nr = d.y - d.x;  // at most WG (schedule)
+    const int32_t ngroups = ((d.w - d.z + 63) & ~63) >> 2;
+    const int32_t rb = tid < nr ? a.slot_ptr[d.x + tid] : 0;
+    const int32_t re = tid < nr ? a.slot_ptr[d.x + tid + 1] : 0;
+    if (tid < ngroups) {
+        const v4i cc = __builtin_nontemporal_load(&c4[(so >> 2) + tid]);
+        const auto vv = load4(a.sval, so + 4 * tid);
+        const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+        A xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = c[j] != -1 ? a.x[c[j] & MASK] : A(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (c[j] != -1) sprod[(uint32_t)c[j] >> SH] = vv.v[j] * xv[j];
+    }
+    mark_row_ends<SPLIT>(a, d, rb, re, send, sowner);
+    __syncthreads();  // products in place, row ends recorded
+    A p[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t k = zb + 4 * tid + j;
+        p[j] = (k >= d.z && k < d.w) ? sprod[4 * tid + j] : A(0);
+    }
+    scan_sum_rows<WG, 4, SPLIT>(a, d, p, send, sowner, sws, swf);
+}
+
 // One workgroup per block (XCD mapping as in spmv_blocks); multi-row blocks
 // are summed by the segmented scan, long-slot segments as in spmv_blocks.
 template <int WG, int NPT, bool SPLIT, class V, class A>
@@ -721,6 +779,22 @@ __global__ __launch_bounds__(WG) void spmv_scan(SpmvArgsT<V, A> a) {
     const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
     if (d.y >= 0) scan_row_block<WG, NPT, SPLIT>(a, d, send, sowner, sws, swf);
     else long_row_segment<WG, NPT, SPLIT, 0>(a, d, sws, sws, 0, 0);
+}
+
+// One workgroup per gather-sorted block summed by the scan (XCD mapping as
+// in spmv_blocks); long-slot segments from the stored order.
+template <int WG, bool SPLIT, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_sorted_scan(SpmvArgsT<V, A> a) {
+    __shared__ A sprod[4 * WG];
+    __shared__ int16_t send[WG];
+    __shared__ uint16_t sowner[4 * WG];
+    __shared__ A sws[WG / 64];
+    __shared__ int32_t swf[WG / 64];
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
+    const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
+    if (d.y >= 0) sorted_scan_block<WG, SPLIT>(a, d, a.sofs[id], sprod, send, sowner, sws, swf);
+    else long_row_segment<WG, 4, SPLIT, 0>(a, d, sws, sws, 0, 0);
 }
 
 // ------------------------------------------------------------------ batched
@@ -1093,6 +1167,19 @@ hipError_t launch_sorted(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_
     return hipGetLastError();
 }
 
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_sorted_scan(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
+    static_assert(WMAX == 0 && NPT == 4, "gather-sorted scan blocks: 4 nonzeros per thread, no window");
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
+    if (split)
+        hipLaunchKernelGGL((spmv_sorted_scan<WG, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((spmv_sorted_scan<WG, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
@@ -1122,6 +1209,15 @@ struct SortedTable {
         {1024, 4, 0, launch_sorted<1024, 4, 0, double, double>},
         {256, 8, 0, launch_sorted<256, 8, 0, double, double>},
         {512, 8, 0, launch_sorted<512, 8, 0, double, double>},
+    };
+};
+
+// gather-sorted scan kernels (binary64)
+struct SortedScanTable {
+    static constexpr Variant<double, double> v[] = {
+        {256, 4, 0, launch_sorted_scan<256, 4, 0, double, double>},
+        {512, 4, 0, launch_sorted_scan<512, 4, 0, double, double>},
+        {1024, 4, 0, launch_sorted_scan<1024, 4, 0, double, double>},
     };
 };
 
@@ -1306,6 +1402,7 @@ bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, Kin
         case Kind::Waves: return find_wave_variant<double, double>(wg, npt, window_entries, wmax_out);
         case Kind::Scan: return find_in<ScanTable<double, double>>(wg, npt, window_entries, wmax_out);
         case Kind::Sorted: return find_in<SortedTable>(wg, npt, window_entries, wmax_out);
+        case Kind::SortedScan: return find_in<SortedScanTable>(wg, npt, window_entries, wmax_out);
         default: return find_variant<double, double>(wg, npt, window_entries, wmax_out);
     }
 }
@@ -1315,7 +1412,8 @@ bool spmv_lowp_variant_exists(int wg, int npt, Kind k) {
         case Kind::Pipe: return find_in<PipeTable<float, float>>(wg, npt, -1, nullptr);
         case Kind::Waves: return find_wave_variant<float, float>(wg, npt, -1, nullptr);
         case Kind::Scan: return find_in<ScanTable<float, float>>(wg, npt, -1, nullptr);
-        case Kind::Sorted: return false;
+        case Kind::Sorted:
+        case Kind::SortedScan: return false;
         default: return find_variant<float, float>(wg, npt, -1, nullptr);
     }
 }
@@ -1327,6 +1425,7 @@ hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, b
         case Kind::Waves: return launch_wave_any(a, wg, npt, window_entries, split, s);
         case Kind::Scan: return launch_in<ScanTable<double, double>>(a, wg, npt, window_entries, split, s);
         case Kind::Sorted: return launch_in<SortedTable>(a, wg, npt, window_entries, split, s);
+        case Kind::SortedScan: return launch_in<SortedScanTable>(a, wg, npt, window_entries, split, s);
         default: return launch_any(a, wg, npt, window_entries, tiled, split, s);
     }
 }
@@ -1338,7 +1437,8 @@ hipError_t launch_lowp(const SpmvArgsT<V, float> &a, int wg, int npt, bool split
         case Kind::Pipe: return launch_in<PipeTable<V, float>>(a, wg, npt, -1, split, s);
         case Kind::Waves: return launch_wave_any(a, wg, npt, -1, split, s);
         case Kind::Scan: return launch_in<ScanTable<V, float>>(a, wg, npt, -1, split, s);
-        case Kind::Sorted: return hipErrorInvalidValue;
+        case Kind::Sorted:
+        case Kind::SortedScan: return hipErrorInvalidValue;
         default: return launch_any(a, wg, npt, -1, false, split, s);
     }
 }

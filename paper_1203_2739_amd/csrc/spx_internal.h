@@ -97,6 +97,7 @@ inline int32_t block_threads(const Tune &t) { return t.wave_blocks ? 64 : t.wg; 
 inline Kind kind_of(const Tune &t) {
     return t.pipeline      ? Kind::Pipe
            : t.wave_blocks ? Kind::Waves
+           : t.scan && t.sort_gathers ? Kind::SortedScan
            : t.scan        ? Kind::Scan
            : t.sort_gathers ? Kind::Sorted
                             : Kind::Blocks;

@@ -45,6 +45,7 @@ const std::vector<spx_tune> &autotune_candidates() {
         for (int wg : {128, 256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 0, 1);
         add(256, 8, 0, 0, 0, 0, 0, 1);
         add(512, 8, 0, 0, 0, 0, 0, 1);
+        for (int wg : {256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 1, 1);
         add(256, 4, 1);
         add(512, 4, 1);
         add(1024, 4, 1);

@@ -637,8 +637,9 @@ def test_partition_tree_is_the_k256_partition(form):
 
 
 @pytest.mark.parametrize("form", ["plain", "db", "split"])
-@pytest.mark.parametrize("wg,npt", [(128, 4), (512, 4), (512, 8), (1024, 4)])
-def test_gather_sorted_storage(orc, form, wg, npt):
+@pytest.mark.parametrize("wg,npt,scan", [(128, 4, 0), (512, 4, 0), (512, 8, 0), (1024, 4, 0), (1024, 4, 1),
+                                         (256, 4, 1)])
+def test_gather_sorted_storage(orc, form, wg, npt, scan):
     """sort_gathers: every multi-row block has, at its own 64-aligned offset
     of the second copy, a permutation of its entries in column order, each
     index holding the column in its low 32 - ceil(log2 nnz_per_block) bits
@@ -651,13 +652,13 @@ def test_gather_sorted_storage(orc, form, wg, npt):
     A = long_row_csr(lens, 9000)
     x = np.random.default_rng(8).uniform(-1, 1, A.n)
     M = spx.from_csr(A, device=False)
-    tune = dict(wg_size=wg, nnz_per_block=wg * npt, sort_gathers=1)
+    tune = dict(wg_size=wg, nnz_per_block=wg * npt, sort_gathers=1, scan_reduce=scan)
     sh = 32 - int(np.ceil(np.log2(wg * npt)))
     if form == "plain":
         P, rq, cq = spx.plan_plain(M, tune=tune), np.arange(A.m), np.arange(A.n)
     else:
         P, rq, cq, _ = (spx.reorder_db if form == "db" else spx.split)(M, 4, 0, 2, tune=tune)
-    assert P.info()["sort_gathers"] == 1
+    assert P.info()["sort_gathers"] == 1 and P.info()["scan_reduce"] == scan
     check_schedule(P)
     if form == "split":
         ex = P.export_split()

@@ -67,7 +67,9 @@ TUNES = [None,
          dict(wg_size=512, sort_gathers=1),
          dict(wg_size=256, sort_gathers=1, xcd_remap=-1, reduce_iters=3),
          dict(wg_size=512, nnz_per_block=4096, sort_gathers=1),
-         dict(wg_size=1024, sort_gathers=1)]
+         dict(wg_size=1024, sort_gathers=1),
+         dict(wg_size=256, sort_gathers=1, scan_reduce=1, xcd_remap=-1),
+         dict(wg_size=1024, sort_gathers=1, scan_reduce=1)]
 SCAN_TUNES = [t for t in TUNES if t and t.get("scan_reduce")]
 SORTED_TUNES = [t for t in TUNES if t and t.get("sort_gathers")]
 
@@ -104,7 +106,7 @@ def test_reordered_c1_integer_exact(orc, form):
     A, x = integer_problem(gen_c1(), 9)
     y, rp, cp, part, P = run_reordered(A, x, form, 8)
     assert np.array_equal(y, orc.spmv(A, x)[rp])
-    for t in (SCAN_TUNES[1], SORTED_TUNES[1]):
+    for t in (SCAN_TUNES[1], SORTED_TUNES[1], SORTED_TUNES[-1]):
         y, rp, cp, part, P = run_reordered(A, x, form, 8, tune=t)
         assert np.array_equal(y, orc.spmv(A, x)[rp]), t
 
@@ -268,7 +270,7 @@ def test_rows_cut_into_segments(orc):
     x = gen_vectors(110, n)[0]
     ref, den = orc.spmv(A, x), orc.abs_rowsum(A, x)
     for t in (None, dict(wg_size=64), dict(wg_size=512), dict(blocks_per_tile=3), dict(wg_size=256, scan_reduce=1),
-              dict(wg_size=512, sort_gathers=1)):
+              dict(wg_size=512, sort_gathers=1), dict(wg_size=512, sort_gathers=1, scan_reduce=1)):
         M = spx.from_csr(A)
         P = spx.plan_plain(M, tune=t)
         assert P.info()["nlong_rows"] >= 4
