@@ -258,6 +258,18 @@ def schedule_name(tune):
     return name
 
 
+def kernel_name(tune):
+    """The kernel that runs a schedule (tune list as in tune_list)."""
+    wg, nb, bpt, win, tpg, wave, pipe, scan, srt = (list(tune) + [0] * 9)[:9]
+    if wave:
+        return "spmv_waves"
+    if pipe:
+        return "spmv_pipe"
+    if srt:
+        return "spmv_sorted_scan" if scan else "spmv_sorted"
+    return "spmv_scan" if scan else "spmv_blocks"
+
+
 def measured_traffic(form, nnz, sched, plan):
     """HBM bytes per launch of the SpMV kernel of this form from the committed
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a copy of
@@ -742,8 +754,7 @@ def main():
     out["roofline"] = {"bound": "hbm", "achieved": hb["kernel_GBs"], "peak": PEAK_HBM_GBS,
                        "unit": "GB/s", "frac": round(hb["kernel_GBs"] / PEAK_HBM_GBS, 4),
                        "traffic": measured_traffic(best, A.nnz, schedule_name(hb["tune"]), hb["plan_sha256"]),
-                       "kernel": f"{'spmv_waves' if hb['tune'][5] else 'spmv_blocks'} ({best}, "
-                                 f"{schedule_name(hb['tune'])})",
+                       "kernel": f"{kernel_name(hb['tune'])} ({best}, {schedule_name(hb['tune'])})",
                        "alg_bytes_per_launch": nb, "kernel_source_sha256": kernel_source_sha256()}
     if not args.no_stream:
         out["stream_read_GBs"] = round(stream_ceiling(spx, torch), 1)

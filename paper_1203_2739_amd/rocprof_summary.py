@@ -93,7 +93,7 @@ def traffic(out, form, filt, nnz, alg, plan, tune, sched, src_sha=None):
     args = f"--forms {form} --tune {tune} --no-cpu-baseline --no-stream"
     with open(path, "w") as o:
         o.write(f"""SpMV kernel ({form} form) on the n=10^6 irregular matrix (nnz={nnz}), K=64, schedule {sched}
-(the one bench.py's autotuning picked: threads x nonzeros per thread, w = wave blocks,
+(the one bench.py's autotuning picked: threads x nonzeros per thread, w = wave blocks, s = scan row sums, g = gather-sorted blocks, p = pipelined tiles,
 t = tiles per row group, W = LDS window entries).
 
 Commands (run from /tmp with TMPDIR=/tmp; R = repository root, OUT = output directory):

@@ -50,6 +50,9 @@ def test_schedule_names():
     assert bench.schedule_name([512, 2048, 1, -1, 0, 0, 0, 1]) == "512x4s"
     assert bench.schedule_name([512, 2048, 1, -1, 128, 0, 1, 0]) == "512x4pt128"
     assert bench.schedule_name([512, 2048, 1, -1, 0, 0, 0, 0, 1]) == "512x4g"
+    assert bench.kernel_name([1024, 4096, 1, -1, 0, 0, 0, 0, 1]) == "spmv_sorted"
+    assert bench.kernel_name([512, 2048, 1, -1, 0, 0, 0, 1, 1]) == "spmv_sorted_scan"
+    assert bench.kernel_name([256, 256, 4, -1, 0, 1]) == "spmv_waves"
 
 
 def test_plan_hash_sees_every_part_of_the_layout():
