@@ -126,7 +126,8 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    or 512 with 8; at most 2^(32 - ceil(log2
  *                    nnz_per_block)) columns (SPX_EUNSUPPORTED otherwise);
  *                    no tiles, windows, wave_blocks or pipeline; with
- *                    scan_reduce (wg_size 256, 512 or 1024, 4 per thread)
+ *                    scan_reduce (wg_size 256, 512 or 1024 with 4 per
+ *                    thread, 256 or 512 with 8)
  *                    the products go to their row-order slots and the rows
  *                    are summed by the scan, so that blocks are cut by
  *                    nonzeros and rows only; not for the precision mode.

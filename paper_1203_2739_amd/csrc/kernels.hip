@@ -731,11 +731,11 @@ __device__ __forceinline__ void scan_row_block(const SpmvArgsT<V, A> &a, const v
 
 // One gather-sorted block summed by the scan: the products of the sorted
 // loads go to their row-order slots in LDS (as in sorted_row_block), and
-// every thread then takes its 4 consecutive row-order products from there.
-template <int WG, bool SPLIT, class V, class A>
+// every thread then takes its NPT consecutive row-order products from there.
+template <int WG, int NPT, bool SPLIT, class V, class A>
 __device__ __forceinline__ void sorted_scan_block(const SpmvArgsT<V, A> &a, const v4i d, int32_t so, A *sprod,
                                                   int16_t *send, uint16_t *sowner, A *sws, int32_t *swf) {
-    constexpr int SH = pack_shift(WG * 4);
+    constexpr int SH = pack_shift(WG * NPT);
     constexpr int MASK = (1 << SH) - 1;
     const int tid = threadIdx.x;
     const v4i *__restrict__ c4 = reinterpret_cast<const v4i *>(a.scol);
@@ -744,26 +744,30 @@ __device__ __forceinline__ void sorted_scan_block(const SpmvArgsT<V, A> &a, cons
     const int32_t ngroups = ((d.w - d.z + 63) & ~63) >> 2;
     const int32_t rb = tid < nr ? a.slot_ptr[d.x + tid] : 0;
     const int32_t re = tid < nr ? a.slot_ptr[d.x + tid + 1] : 0;
-    if (tid < ngroups) {
-        const v4i cc = __builtin_nontemporal_load(&c4[(so >> 2) + tid]);
-        const auto vv = load4(a.sval, so + 4 * tid);
-        const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
-        A xv[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = c[j] != -1 ? a.x[c[j] & MASK] : A(0);
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid + u * WG;
+        if (gi < ngroups) {
+            const v4i cc = __builtin_nontemporal_load(&c4[(so >> 2) + gi]);
+            const auto vv = load4(a.sval, so + 4 * gi);
+            const int32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+            A xv[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (c[j] != -1) sprod[(uint32_t)c[j] >> SH] = vv.v[j] * xv[j];
+            for (int j = 0; j < 4; ++j) xv[j] = c[j] != -1 ? a.x[c[j] & MASK] : A(0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c[j] != -1) sprod[(uint32_t)c[j] >> SH] = vv.v[j] * xv[j];
+        }
     }
     mark_row_ends<SPLIT>(a, d, rb, re, send, sowner);
     __syncthreads();  // products in place, row ends recorded
-    A p[4];
+    A p[NPT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int32_t k = zb + 4 * tid + j;
-        p[j] = (k >= d.z && k < d.w) ? sprod[4 * tid + j] : A(0);
+    for (int j = 0; j < NPT; ++j) {
+        const int32_t k = zb + NPT * tid + j;
+        p[j] = (k >= d.z && k < d.w) ? sprod[NPT * tid + j] : A(0);
     }
-    scan_sum_rows<WG, 4, SPLIT>(a, d, p, send, sowner, sws, swf);
+    scan_sum_rows<WG, NPT, SPLIT>(a, d, p, send, sowner, sws, swf);
 }
 
 // One workgroup per block (XCD mapping as in spmv_blocks); multi-row blocks
@@ -783,18 +787,18 @@ __global__ __launch_bounds__(WG) void spmv_scan(SpmvArgsT<V, A> a) {
 
 // One workgroup per gather-sorted block summed by the scan (XCD mapping as
 // in spmv_blocks); long-slot segments from the stored order.
-template <int WG, bool SPLIT, class V, class A>
+template <int WG, int NPT, bool SPLIT, class V, class A>
 __global__ __launch_bounds__(WG) void spmv_sorted_scan(SpmvArgsT<V, A> a) {
-    __shared__ A sprod[4 * WG];
+    __shared__ A sprod[NPT * WG];
     __shared__ int16_t send[WG];
-    __shared__ uint16_t sowner[4 * WG];
+    __shared__ uint16_t sowner[NPT * WG];
     __shared__ A sws[WG / 64];
     __shared__ int32_t swf[WG / 64];
     const int id = unit_of(a, blockIdx.x);
     if (id < 0) return;
     const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
-    if (d.y >= 0) sorted_scan_block<WG, SPLIT>(a, d, a.sofs[id], sprod, send, sowner, sws, swf);
-    else long_row_segment<WG, 4, SPLIT, 0>(a, d, sws, sws, 0, 0);
+    if (d.y >= 0) sorted_scan_block<WG, NPT, SPLIT>(a, d, a.sofs[id], sprod, send, sowner, sws, swf);
+    else long_row_segment<WG, NPT, SPLIT, 0>(a, d, sws, sws, 0, 0);
 }
 
 // ------------------------------------------------------------------ batched
@@ -1169,14 +1173,14 @@ hipError_t launch_sorted(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_
 
 template <int WG, int NPT, int WMAX, class V, class A>
 hipError_t launch_sorted_scan(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
-    static_assert(WMAX == 0 && NPT == 4, "gather-sorted scan blocks: 4 nonzeros per thread, no window");
+    static_assert(WMAX == 0, "gather-sorted scan blocks take no window");
     if (a0.ntiles <= 0) return hipSuccess;
     SpmvArgsT<V, A> a = a0;
     const unsigned grid = grid_of_units(a);
     if (split)
-        hipLaunchKernelGGL((spmv_sorted_scan<WG, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((spmv_sorted_scan<WG, NPT, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
     else
-        hipLaunchKernelGGL((spmv_sorted_scan<WG, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
+        hipLaunchKernelGGL((spmv_sorted_scan<WG, NPT, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1218,6 +1222,8 @@ struct SortedScanTable {
         {256, 4, 0, launch_sorted_scan<256, 4, 0, double, double>},
         {512, 4, 0, launch_sorted_scan<512, 4, 0, double, double>},
         {1024, 4, 0, launch_sorted_scan<1024, 4, 0, double, double>},
+        {256, 8, 0, launch_sorted_scan<256, 8, 0, double, double>},
+        {512, 8, 0, launch_sorted_scan<512, 8, 0, double, double>},
     };
 };
 

@@ -46,6 +46,8 @@ const std::vector<spx_tune> &autotune_candidates() {
         add(256, 8, 0, 0, 0, 0, 0, 1);
         add(512, 8, 0, 0, 0, 0, 0, 1);
         for (int wg : {256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 1, 1);
+        add(256, 8, 0, 0, 0, 0, 1, 1);
+        add(512, 8, 0, 0, 0, 0, 1, 1);
         add(256, 4, 1);
         add(512, 4, 1);
         add(1024, 4, 1);

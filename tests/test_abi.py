@@ -638,7 +638,7 @@ def test_partition_tree_is_the_k256_partition(form):
 
 @pytest.mark.parametrize("form", ["plain", "db", "split"])
 @pytest.mark.parametrize("wg,npt,scan", [(128, 4, 0), (512, 4, 0), (512, 8, 0), (1024, 4, 0), (1024, 4, 1),
-                                         (256, 4, 1)])
+                                         (256, 4, 1), (512, 8, 1)])
 def test_gather_sorted_storage(orc, form, wg, npt, scan):
     """sort_gathers: every multi-row block has, at its own 64-aligned offset
     of the second copy, a permutation of its entries in column order, each

@@ -69,7 +69,8 @@ TUNES = [None,
          dict(wg_size=512, nnz_per_block=4096, sort_gathers=1),
          dict(wg_size=1024, sort_gathers=1),
          dict(wg_size=256, sort_gathers=1, scan_reduce=1, xcd_remap=-1),
-         dict(wg_size=1024, sort_gathers=1, scan_reduce=1)]
+         dict(wg_size=1024, sort_gathers=1, scan_reduce=1),
+         dict(wg_size=512, nnz_per_block=4096, sort_gathers=1, scan_reduce=1)]
 SCAN_TUNES = [t for t in TUNES if t and t.get("scan_reduce")]
 SORTED_TUNES = [t for t in TUNES if t and t.get("sort_gathers")]
 
