@@ -387,7 +387,8 @@ spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *str
  * spx_plan_export_lowp: the rounded values (float[nnz] or uint16_t[nnz]
  *   bfloat16 bit patterns) in the plan's storage order.
  * spx_spmv_lowp: y <- A_low x with binary32 device vectors x[n], y[m], in the
- *   plan's (reordered) space; untiled schedules only.  Each row is summed in
+ *   plan's (reordered) space; schedules without an LDS window, row blocks
+ *   untiled, not gather-sorted (SPX_EUNSUPPORTED otherwise).  Each row is summed in
  *   binary32 in a tree order, so against the exact sum of the rounded
  *   products a row of length m_i errs by at most about m_i 2^-24 times
  *   sum_j |a_ij x_j|.
@@ -399,7 +400,9 @@ spx_status spx_unpermute_y(spx_plan P, const double *y_hat, double *y, void *str
  *   (at most max_inner iterations), x <- x + ||r|| d, r <- b - A x.
  *   The host reads the inner residual every 8 iterations, so an inner
  *   solve may take up to 7 iterations past the first that meets inner_tol.
- *   SPX_PREC_F64 runs the inner CG in binary64 with the binary64 product.
+ *   SPX_PREC_F64 runs the inner CG in binary64 with the binary64 product
+ *   under any schedule; the other precisions need a schedule that
+ *   spx_spmv_lowp runs.
  *   Returns SPX_ENOTCONV (with stats filled and x the last iterate) if the
  *   tolerance was not reached.  Allocates its workspace on every call.
  */

@@ -244,7 +244,9 @@ spx_status spx_cg_ir(spx_plan P, int32_t precision, const double *b, double *x, 
         if (P->m != P->n) fail(SPX_EINVAL, "the matrix must be square");
         if (precision != SPX_PREC_F64) check_lowp_plan(*P, precision, true);
         if (!P->on_device) fail(SPX_ENODEVICE, "plan has no device copy");
-        if (!lowp_schedule_ok(P->tune))
+        // binary64 CG runs any schedule; the refined solves' inner products
+        // need one that the precision mode runs
+        if (precision != SPX_PREC_F64 && !lowp_schedule_ok(P->tune))
             fail(SPX_EUNSUPPORTED, "the solve runs schedules without an LDS window (row blocks untiled)");
         if (!(tol > 0) || !(inner_tol > 0) || max_outer < 1 || max_inner < 1)
             fail(SPX_EINVAL, "tol, inner_tol > 0 and max_outer, max_inner >= 1 required");

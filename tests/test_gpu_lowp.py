@@ -130,3 +130,22 @@ def test_cg_ir_rejects_reordered_plans():
     with pytest.raises(spx.SpxError) as e:
         spx.cg_ir(P, "f32", b, torch.zeros_like(b))
     assert e.value.code == -5
+
+
+def test_cg_schedules(orc):
+    """Binary64 CG runs under any schedule, gather-sorted blocks included;
+    the binary32 refined solve refuses a schedule the precision mode does
+    not run."""
+    import torch
+    A = gen_c3_spd(seed=5, n=8_000)
+    b = orc.spmv(A, np.ones(A.n))
+    M = spx.from_csr(A)
+    P = spx.plan_plain(M, tune=dict(wg_size=512, sort_gathers=1))
+    spx.plan_add_lowp(P, "f32")
+    xd = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    st = spx.cg_ir(P, "f64", dev(b), xd, tol=1e-10, max_inner=2000)
+    assert st["converged"]
+    assert np.linalg.norm(b - orc.spmv(A, host(xd))) <= 2e-10 * np.linalg.norm(b)
+    xd.zero_()
+    with pytest.raises(spx.SpxError):
+        spx.cg_ir(P, "f32", dev(b), xd, tol=1e-10)
