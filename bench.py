@@ -320,7 +320,7 @@ def time_calls(torch, fn, warmup, steps):
     return a.elapsed_time(b) / steps
 
 
-def main_precision(args, torch, spx):
+def main_precision(args, torch, spx, emit=True):
     """Precision mode on the SPD matrix A = offdiag(B + B^T) + diag(row sums + 1)
     built from the block generator at n = 5*10^5: product rates per stored
     precision, product errors against the binary64 oracle, and the refined CG
@@ -394,10 +394,12 @@ def main_precision(args, torch, spx):
                               for p in ("f32", "bf16")},
         **out,
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
 
 
-def main_batched(args, torch, spx):
+def main_batched(args, torch, spx, emit=True):
     """The uneven batch: 256 matrices (n log-uniform in [10^3, 2*10^5], mean
     degree U[5, 50], Zipf(2.2) rows) with 1, 8 or 32 right-hand sides each,
     run as one persistent launch replayed from a HIP graph with the
@@ -463,7 +465,30 @@ def main_batched(args, torch, spx):
         "bytes": inf["bytes"], "autotune": best,
         "sample_max_rel_err": worst, "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 2),
     }
-    print(json.dumps(line), flush=True)
+    if emit:
+        print(json.dumps(line), flush=True)
+    return line
+
+
+def extension_summaries(args, torch, spx):
+    """The precision and batched workloads, run after the main measurement
+    and reported in its line: their own metrics, rates and checks."""
+    p = main_precision(args, torch, spx, emit=False)
+    b = main_batched(args, torch, spx, emit=False)
+    return {
+        "precision": {"metric": p["metric"], "config": p["config"], "unit": "GB/s",
+                      "GBs": {k: v["GBs"] for k, v in p["products"].items()},
+                      "ms": {k: v["ms"] for k, v in p["products"].items()},
+                      "max_rel_err_vs_f64_oracle": {k: v["max_rel_err_vs_f64_oracle"]
+                                                    for k, v in p["products"].items()},
+                      "schedule": p["schedule"], "speedup_vs_f64_product": p["speedup_vs_f64_product"],
+                      "solve_seconds": {k: round(v["seconds"], 4) for k, v in p["solves"].items()},
+                      "solve_converged": {k: v["converged"] for k, v in p["solves"].items()},
+                      "speedup_vs_f64_cg": p["speedup_vs_f64_cg"]},
+        "batched": {k: b[k] for k in ("metric", "config", "value", "unit", "ms_per_step", "speedup_vs_plain",
+                                      "ms_plain_launches", "plain_launches", "bytes", "sample_max_rel_err",
+                                      "pct_of_peak")},
+    }
 
 
 def main_selector(args, torch, spx):
@@ -578,6 +603,8 @@ def main():
                          "scan_reduce,sort_gathers]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the precision and batched workloads that the default run reports beside the SpMV")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--cold", action="store_true",
                     help="also time 20 products per form, each after a 512 MB read that empties the caches")
@@ -767,6 +794,8 @@ def main():
         out["pct_of_stream_ceiling"] = round(100 * hb["GBs"] / out["stream_read_GBs"], 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, xs_host)
+    if not args.no_extensions:
+        out["extensions"] = extension_summaries(args, torch, spx)
     print(json.dumps(out), flush=True)
 
 

@@ -90,7 +90,7 @@ def traffic(out, form, filt, nnz, alg, plan, tune, sched, src_sha=None):
     fb, wb = f_kib * 1024 * ff, w_kib * 1024 * fw
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
                         f"spmv_c2_{form}_traffic.txt")
-    args = f"--forms {form} --tune {tune} --no-cpu-baseline --no-stream"
+    args = f"--forms {form} --tune {tune} --no-cpu-baseline --no-stream --no-extensions"
     with open(path, "w") as o:
         o.write(f"""SpMV kernel ({form} form) on the n=10^6 irregular matrix (nnz={nnz}), K=64, schedule {sched}
 (the one bench.py's autotuning picked: threads x nonzeros per thread, w = wave blocks, s = scan row sums, g = gather-sorted blocks, p = pipelined tiles,
