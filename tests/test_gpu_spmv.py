@@ -207,15 +207,16 @@ def test_edge_shapes(orc, shape, long_len):
 
 
 def test_empty_matrices(orc):
-    for m, n in [(0, 0), (0, 5), (5, 0), (7, 9)]:
+    for m, n in [(0, 0), (0, 5), (5, 0), (7, 9), (3000, 10)]:
         A = CSR(m, n, np.zeros(m + 1, np.int64), np.zeros(0, np.int32), np.zeros(0))
         M = spx.from_csr(A)
-        P = spx.plan_plain(M)
-        yd = torch.full((max(m, 1),), np.nan, dtype=torch.float64, device="cuda")
-        xd = torch.ones(max(n, 1), dtype=torch.float64, device="cuda")
-        spx.spmv(P, xd, yd)
-        if m:
-            assert np.all(host(yd)[:m] == 0.0)
+        for t in [None] + SCAN_TUNES[:1] + SORTED_TUNES[:1] + SORTED_TUNES[-1:]:
+            P = spx.plan_plain(M, tune=t)
+            yd = torch.full((max(m, 1),), np.nan, dtype=torch.float64, device="cuda")
+            xd = torch.ones(max(n, 1), dtype=torch.float64, device="cuda")
+            spx.spmv(P, xd, yd)
+            if m:
+                assert np.all(host(yd)[:m] == 0.0), t
         if m and n:
             P, rp, cp, _ = spx.split(M, 2, 0, 0)
             yd[:] = float("nan")
