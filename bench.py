@@ -491,6 +491,59 @@ def extension_summaries(args, torch, spx):
     }
 
 
+def main_locality(args, torch, spx):
+    """Temporal against spatial locality of the x accesses (Sec. 1, the
+    paper's claim that temporal locality matters more for irregular
+    matrices): four n x n matrices with 20 nonzeros per row whose columns are
+    uniform over x (random), scattered inside a window of 16,384 columns that
+    slides with the row (temporal only), one run of 20 consecutive columns at
+    a random place (spatial only), or that run at the diagonal (both).  Each
+    is timed with plain CSR under row blocks (512x4), gather-sorted blocks
+    (512x4) and the library's autotuned schedule (or the --tune schedule
+    alone)."""
+    from synth import LOCALITY_KINDS, gen_locality, gen_vectors
+    n = args.n
+    npool = min(max(args.steps + args.warmup, 3), 103)
+    xs = torch.from_numpy(gen_vectors(2000, n, npool)).cuda()
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for kind in LOCALITY_KINDS:
+        t = time.time()
+        L = gen_locality(kind, n=n)
+        P = spx.plan_plain(spx.from_csr(L))
+        nb = alg_bytes(L.m, L.n, L.nnz)
+        r = {"nnz": L.nnz, "bytes": nb}
+        if args.tune:
+            f = [int(v) for v in args.tune.split(",")]
+            keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group", "wave_blocks",
+                    "pipeline", "scan_reduce", "sort_gathers"]
+            scheds = {schedule_name(f): dict(zip(keys, f))}
+        else:
+            scheds = {"512x4": dict(wg_size=512), "512x4g": dict(wg_size=512, sort_gathers=1)}
+        for name, tune in scheds.items():
+            spx.plan_retune(P, tune)
+            _, kms = time_form(spx, torch, P, "plain", xs, y, args.warmup, args.steps)
+            r[name] = {"kernel_ms": round(kms, 5), "GBs": round(nb / (kms * 1e-3) / 1e9, 1)}
+        if not args.tune and not args.no_autotune:
+            best, _ = spx.plan_autotune(P, xs[0], y, reps=10)
+            _, kms = time_form(spx, torch, P, "plain", xs, y, args.warmup, args.steps)
+            r["autotuned"] = {"schedule": schedule_name(tune_list(best)), "kernel_ms": round(kms, 5),
+                              "GBs": round(nb / (kms * 1e-3) / 1e9, 1)}
+        log(f"{kind} ({time.time() - t:.0f} s): {json.dumps(r)}")
+        res[kind] = r
+    head = "autotuned" if "autotuned" in res["temporal"] else next(iter(scheds))
+    line = {
+        "metric": "SpMV GB/s by locality of the x accesses (random, temporal only, spatial only, both)",
+        "value": res["temporal"][head]["GBs"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["temporal"][head]["kernel_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"n={n}, 20 nonzeros per row; temporal window 16384 columns"},
+        "spatial_over_temporal": round(res["temporal"][head]["kernel_ms"] / res["spatial"][head]["kernel_ms"], 3),
+        "kinds": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main_selector(args, torch, spx):
     """Learned selector: every one of the 24 choices timed on matrices of the
     four families (n log-uniform in [n_lo, n_hi]); the network is trained on
@@ -608,7 +661,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--cold", action="store_true",
                     help="also time 20 products per form, each after a 512 MB read that empties the caches")
-    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched", "selector"],
+    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched", "selector", "locality"],
                     help="spmv: repeated products on the n=10^6 matrix (default); precision: "
                          "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
     ap.add_argument("--train", type=int, default=60, help="selector: training matrices")
@@ -650,6 +703,8 @@ def main():
         return main_batched(args, torch, spx)
     if args.workload == "selector":
         return main_selector(args, torch, spx)
+    if args.workload == "locality":
+        return main_locality(args, torch, spx)
     if args.only_stream:
         nbytes = 1 << 30
         src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()

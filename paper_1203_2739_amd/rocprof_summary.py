@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the SpMV kernels.
 
   python -m paper_1203_2739_amd.rocprof_summary stats  <kernel_stats.csv>
-  python -m paper_1203_2739_amd.rocprof_summary pmc    <counter_collection.csv> [name filter]
+  python -m paper_1203_2739_amd.rocprof_summary pmc    <counter_collection.csv> [name filter] [runs]
   python -m paper_1203_2739_amd.rocprof_summary traffic <out dir> <form> <kernel filter> <nnz> <alg bytes> <plan sha256> <tune> <schedule>
 
 ``traffic`` writes the summary that ``bench.py`` reads for roofline.traffic
@@ -14,7 +14,8 @@ layout only.
 
 ``stats`` lists kernels by total time with call count and mean duration.
 ``pmc`` lists, per kernel and grid size, the mean per-dispatch value of each
-collected counter (FETCH_SIZE and WRITE_SIZE are in KiB per dispatch).
+collected counter (FETCH_SIZE and WRITE_SIZE are in KiB per dispatch); with
+[runs], per consecutive run of the matching dispatches instead.
 """
 from __future__ import annotations
 
@@ -52,13 +53,28 @@ def stats(path: str):
               f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
 
 
-def pmc(path: str, filt: str = ""):
+def pmc(path: str, filt: str = "", groups: int = 0):
+    """Mean counters per (kernel, grid); with groups > 0, the matching
+    dispatches in dispatch order are cut into that many consecutive runs of
+    equal length (one per configuration a script ran in turn) and each run is
+    averaged on its own."""
     acc = defaultdict(lambda: defaultdict(list))
+    seq = defaultdict(lambda: defaultdict(float))
     for r in csv.DictReader(open(path)):
         k = r["Kernel_Name"]
         if filt and filt not in k:
             continue
         acc[(k, r.get("Grid_Size", ""))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        seq[int(r.get("Dispatch_Id", 0))][r["Counter_Name"]] += float(r["Counter_Value"])
+    if groups > 0:
+        ids = sorted(seq)
+        size = len(ids) // groups
+        for g in range(groups):
+            part = ids[g * size:(g + 1) * size]
+            names = sorted({c for i in part for c in seq[i]})
+            vals = [f"{c}={sum(seq[i][c] for i in part) / len(part):.1f}" for c in names]
+            print(f"run {g} (dispatches {part[0]}..{part[-1]}, n={len(part)}): " + ", ".join(vals))
+        return
     for (k, g), cs in sorted(acc.items(), key=lambda kv: kv[0]):
         parts = [f"{c}={sum(v) / len(v):.1f} (n={len(v)})" for c, v in sorted(cs.items())]
         print(f"{short(k)} grid={g}: " + ", ".join(parts))
@@ -137,4 +153,4 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
     else:
-        pmc(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
+        pmc(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "", int(sys.argv[4]) if len(sys.argv) > 4 else 0)

@@ -19,5 +19,7 @@ from .generators import (  # noqa: F401
     gen_vectors,
     gen_block_hidden,
     gen_banded_like,
+    gen_locality,
+    LOCALITY_KINDS,
     csr_sha256,
 )

@@ -436,3 +436,59 @@ def gen_banded_like(A: CSR) -> CSR:
     off = np.arange(A.nnz, dtype=np.int64) - np.repeat(A.rowptr[:-1].astype(np.int64), deg)
     cols = (np.repeat(start, deg) + off).astype(np.int32)
     return CSR(A.m, A.n, A.rowptr, cols, A.vals, {"banded_like": True})
+
+
+LOCALITY_KINDS = ("random", "temporal", "spatial", "band")
+
+
+def gen_locality(kind: str, seed: int = 7, n: int = 1_000_000, deg: int = 20, window: int = 16384) -> CSR:
+    """Square matrices of n rows with deg nonzeros each (values U[-1, 1]) that
+    separate the two localities of the x accesses (Sec. 1): "random" draws a
+    row's columns uniformly from all of x (neither locality); "temporal"
+    draws them, distinct and scattered, from a window of `window` columns
+    that slides with the row (row i: [i (n - window) / n, + window)), so
+    nearby rows reuse the same x entries but a row's own columns rarely share
+    a cache line; "spatial" gives each row one run of deg consecutive
+    columns at a uniform random start, so a row's reads share lines but no
+    entry is reused by nearby rows; "band" puts the run next to the diagonal
+    (both localities)."""
+    if kind not in LOCALITY_KINDS:
+        raise ValueError(f"kind must be one of {LOCALITY_KINDS}")
+    rng = _rng(seed)
+    rows = np.arange(n, dtype=np.int64)
+    if kind == "random":
+        cols = rng.integers(0, n, (n, deg), dtype=np.int64)
+        cols.sort(axis=1)
+        # redraw duplicates inside a row until every row has deg distinct columns
+        for _ in range(100):
+            dup = np.zeros_like(cols, dtype=bool)
+            dup[:, 1:] = cols[:, 1:] == cols[:, :-1]
+            if not dup.any():
+                break
+            cols[dup] = rng.integers(0, n, int(dup.sum()), dtype=np.int64)
+            cols.sort(axis=1)
+        assert not (cols[:, 1:] == cols[:, :-1]).any()
+    elif kind == "temporal":
+        lo = rows * (n - window) // n
+        # deg distinct offsets per row: a random permutation's first deg of window
+        # entries would be costly, so draw and redraw duplicates as above
+        off = rng.integers(0, window, (n, deg), dtype=np.int64)
+        off.sort(axis=1)
+        for _ in range(100):
+            dup = np.zeros_like(off, dtype=bool)
+            dup[:, 1:] = off[:, 1:] == off[:, :-1]
+            if not dup.any():
+                break
+            off[dup] = rng.integers(0, window, int(dup.sum()), dtype=np.int64)
+            off.sort(axis=1)
+        assert not (off[:, 1:] == off[:, :-1]).any()
+        cols = lo[:, None] + off
+    elif kind == "spatial":
+        start = rng.integers(0, n - deg + 1, n, dtype=np.int64)
+        cols = start[:, None] + np.arange(deg, dtype=np.int64)[None, :]
+    else:
+        start = np.clip(rows - deg // 2, 0, n - deg)
+        cols = start[:, None] + np.arange(deg, dtype=np.int64)[None, :]
+    rowptr = np.arange(n + 1, dtype=np.int64) * deg
+    vals = rng.uniform(-1.0, 1.0, n * deg)
+    return CSR(n, n, rowptr, cols.reshape(-1).astype(np.int32), vals, {"locality": kind, "window": window})

@@ -111,3 +111,35 @@ def test_cpu_baseline_legs_agree_and_report_cores():
     assert out["kind"] == "oracle" and out["cores"] == 1 and out["value"] > 0
     assert out["cpu_model"] and out["host_cpus"] >= 1
     assert out["all_cores"]["cores"] >= 1 and out["all_cores"]["value"] > 0
+
+
+def test_locality_matrices():
+    """The locality workload's matrices: 20 distinct sorted columns per row;
+    random spans all of x, temporal stays inside its sliding window and
+    reuses columns across nearby rows while a row's own columns are spread,
+    spatial and band are runs of 20 consecutive columns (band at the
+    diagonal)."""
+    from synth import LOCALITY_KINDS, gen_locality
+    n, deg, w = 50_000, 20, 4096
+    mats = {k: gen_locality(k, seed=3, n=n, deg=deg, window=w) for k in LOCALITY_KINDS}
+    rows = np.arange(n)
+    for k, A in mats.items():
+        assert A.m == A.n == n and A.nnz == n * deg
+        c = A.colidx.reshape(n, deg).astype(np.int64)
+        assert np.all(np.diff(c, axis=1) > 0) and c.min() >= 0 and c.max() < n, k
+    ct = mats["temporal"].colidx.reshape(n, deg).astype(np.int64)
+    lo = rows * (n - w) // n
+    assert np.all(ct >= lo[:, None]) and np.all(ct < (lo + w)[:, None])
+    # temporal: the 100 rows around any row read far fewer distinct columns
+    # than entries; spatial: a row's 20 entries fit 2 or 3 lines of 16 entries
+    blk = ct[1000:1100].reshape(-1)
+    assert np.unique(blk).size < 0.9 * blk.size
+    for k in ("spatial", "band"):
+        c = mats[k].colidx.reshape(n, deg).astype(np.int64)
+        assert np.all(c[:, -1] - c[:, 0] == deg - 1)
+        assert np.all(np.apply_along_axis(lambda r: np.unique(r >> 4).size, 1, c[:200]) <= 3)
+    cb = mats["band"].colidx.reshape(n, deg).astype(np.int64)
+    assert np.all(np.abs(cb[:, deg // 2] - rows) <= deg)
+    # spatial runs start anywhere: no reuse of columns between neighbouring rows
+    cs = mats["spatial"].colidx.reshape(n, deg).astype(np.int64)
+    assert np.mean(np.abs(cs[1:, 0] - cs[:-1, 0]) > deg) > 0.99
