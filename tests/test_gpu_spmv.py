@@ -377,3 +377,15 @@ def test_comparison_orderings_c1(orc, name):
     yi = torch.empty(A.m, dtype=torch.float64, device="cuda")
     spx.spmv(Pi, dev(xi[cp]), yi)
     assert np.array_equal(host(yi), orc.spmv(Ai, xi)[rp])
+
+
+@pytest.mark.parametrize("kind", ["random", "temporal", "spatial", "band"])
+def test_locality_matrices(orc, kind):
+    """The locality workload's patterns (n = 60,000) under row blocks,
+    gather-sorted blocks and scan blocks match the oracle."""
+    from synth import gen_locality
+    A = gen_locality(kind, seed=9, n=60_000, window=4096)
+    x = gen_vectors(112, A.n)[0]
+    ref, den = orc.spmv(A, x), orc.abs_rowsum(A, x)
+    for t in (dict(wg_size=512), dict(wg_size=1024, sort_gathers=1), dict(wg_size=256, scan_reduce=1)):
+        assert_close_rowwise(run_plain(A, x, t), ref, den, f"{kind} {t}")
