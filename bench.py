@@ -239,18 +239,19 @@ def tune_list(t):
     """A schedule dict as the bench line's tune list."""
     return [t.get("wg_size", 0), t.get("nnz_per_block", 0), t.get("blocks_per_tile", 1),
             t.get("window_entries", -1) or -1, t.get("tiles_per_group", 0), t.get("wave_blocks", 0),
-            t.get("pipeline", 0), t.get("scan_reduce", 0), t.get("sort_gathers", 0)]
+            t.get("pipeline", 0), t.get("scan_reduce", 0), t.get("sort_gathers", 0), t.get("compact_index", 0)]
 
 
 def schedule_name(tune):
     """Short name of a schedule [wg, nnz_per_block, blocks_per_tile, window,
-    tiles_per_group, wave_blocks, pipeline, scan_reduce, sort_gathers]:
-    threads x nonzeros per thread (per lane for wave blocks, marked w; s for
-    scan row sums, g for gather-sorted blocks, p for pipelined tiles), then
-    tiles per row group (t) and the LDS window (W) when used."""
-    wg, nb, _, win, tpg, wave, pipe, scan, srt = (list(tune) + [0] * 9)[:9]
+    tiles_per_group, wave_blocks, pipeline, scan_reduce, sort_gathers,
+    compact_index]: threads x nonzeros per thread (per lane for wave blocks,
+    marked w; s for scan row sums, g for gather-sorted blocks, c for 16-bit
+    indices, p for pipelined tiles), then tiles per row group (t) and the LDS
+    window (W) when used."""
+    wg, nb, _, win, tpg, wave, pipe, scan, srt, cpt = (list(tune) + [0] * 10)[:10]
     name = (f"{wg}x{nb // (64 if wave else wg)}" + ("w" if wave else "") + ("s" if scan else "")
-            + ("g" if srt else "") + ("p" if pipe else ""))
+            + ("g" if srt else "") + ("c" if cpt else "") + ("p" if pipe else ""))
     if tpg:
         name += f"t{tpg}"
     if win and win > 0:
@@ -260,7 +261,9 @@ def schedule_name(tune):
 
 def kernel_name(tune):
     """The kernel that runs a schedule (tune list as in tune_list)."""
-    wg, nb, bpt, win, tpg, wave, pipe, scan, srt = (list(tune) + [0] * 9)[:9]
+    wg, nb, bpt, win, tpg, wave, pipe, scan, srt, cpt = (list(tune) + [0] * 10)[:10]
+    if cpt:
+        return "spmv_compact"
     if wave:
         return "spmv_waves"
     if pipe:
@@ -516,7 +519,7 @@ def main_locality(args, torch, spx):
         if args.tune:
             f = [int(v) for v in args.tune.split(",")]
             keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group", "wave_blocks",
-                    "pipeline", "scan_reduce", "sort_gathers"]
+                    "pipeline", "scan_reduce", "sort_gathers", "compact_index"]
             scheds = {schedule_name(f): dict(zip(keys, f))}
         else:
             scheds = {"512x4": dict(wg_size=512), "512x4g": dict(wg_size=512, sort_gathers=1)}
@@ -653,7 +656,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tune", default="",
                     help="wg,nnz_per_block[,blocks_per_tile,window_entries,tiles_per_group,wave_blocks,pipeline,"
-                         "scan_reduce,sort_gathers]")
+                         "scan_reduce,sort_gathers,compact_index]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-extensions", action="store_true",
@@ -734,7 +737,7 @@ def main():
     if args.tune:
         f = [int(v) for v in args.tune.split(",")]
         keys = ["wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "tiles_per_group", "wave_blocks",
-                "pipeline", "scan_reduce", "sort_gathers"]
+                "pipeline", "scan_reduce", "sort_gathers", "compact_index"]
         tune = dict(zip(keys, f))
 
     results = {}
@@ -783,9 +786,14 @@ def main():
              "border_row_nnz": inf["border_row_nnz"], "bytes_matrix": inf["bytes_matrix"],
              "tune": [inf["wg_size"], inf["nnz_per_block"], inf["blocks_per_tile"],
                       inf["window_entries"], inf["tiles_per_group"], inf["wave_blocks"], inf["pipeline"],
-                      inf["scan_reduce"], inf["sort_gathers"]],
+                      inf["scan_reduce"], inf["sort_gathers"], inf["compact_index"]],
              "window_nnz": inf["window_nnz"],
              "plan_sha256": plan_key}
+        if inf["compact_index"]:
+            # 16-bit indices: the kernel has 2 bytes fewer to read per such nonzero
+            nb_c = nb - 2 * inf["nnz_compact"]
+            r.update({"nnz_compact": inf["nnz_compact"], "alg_bytes": nb_c,
+                      "kernel_GBs_alg": round(nb_c / (kern_ms * 1e-3) / 1e9, 1)})
         if args.cold:
             cold_ms = time_cold(spx, torch, P, form, xf, y)
             r["cold_ms_per_step"] = round(cold_ms, 5)
@@ -839,11 +847,13 @@ def main():
     }
     if "plain" in results:
         out["speedup_vs_plain"] = round(results["plain"]["ms_per_step"] / hb["ms_per_step"], 3)
-    out["roofline"] = {"bound": "hbm", "achieved": hb["kernel_GBs"], "peak": PEAK_HBM_GBS,
-                       "unit": "GB/s", "frac": round(hb["kernel_GBs"] / PEAK_HBM_GBS, 4),
+    # with 16-bit indices the algorithmic bytes are the ones that layout reads
+    ach = hb.get("kernel_GBs_alg", hb["kernel_GBs"])
+    out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                       "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
                        "traffic": measured_traffic(best, A.nnz, schedule_name(hb["tune"]), hb["plan_sha256"]),
                        "kernel": f"{kernel_name(hb['tune'])} ({best}, {schedule_name(hb['tune'])})",
-                       "alg_bytes_per_launch": nb, "kernel_source_sha256": kernel_source_sha256()}
+                       "alg_bytes_per_launch": hb.get("alg_bytes", nb), "kernel_source_sha256": kernel_source_sha256()}
     if not args.no_stream:
         out["stream_read_GBs"] = round(stream_ceiling(spx, torch), 1)
         out["pct_of_stream_ceiling"] = round(100 * hb["GBs"] / out["stream_read_GBs"], 2)

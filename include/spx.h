@@ -131,6 +131,13 @@ typedef struct spx_plan_s *spx_plan; /* a matrix in one of the forms, ready to m
  *                    the products go to their row-order slots and the rows
  *                    are summed by the scan, so that blocks are cut by
  *                    nonzeros and rows only; not for the precision mode.
+ *   compact_index    0 (default) or 1: a block whose columns lie within
+ *                    65,536 of its smallest column reads 16-bit offsets
+ *                    from that column (a second index copy, 2 bytes per
+ *                    nonzero instead of 4; Sec. 2.1 compresses indices for
+ *                    the same reason) and other blocks the 32-bit indices;
+ *                    binary64 workgroup row blocks only (wg_size 128, 256
+ *                    or 512, 4 per thread), not with the options above.
  * Only some (wg_size, nnz_per_block, window) combinations have a kernel;
  * others fail with SPX_EUNSUPPORTED.                                         */
 typedef struct spx_tune_s {
@@ -145,7 +152,7 @@ typedef struct spx_tune_s {
     int32_t pipeline;
     int32_t scan_reduce;
     int32_t sort_gathers;
-    int32_t reserved[1];
+    int32_t compact_index;
 } spx_tune;
 
 /* Plan summary.  The lambda sums are the right-hand sides of Theorem 1
@@ -176,6 +183,8 @@ typedef struct spx_plan_info_s {
     int32_t pipeline;         /* 1: pipelined tiles */
     int32_t scan_reduce;      /* 1: rows summed by a segmented scan per block */
     int32_t sort_gathers;     /* 1: blocks stored sorted by column for the x gathers */
+    int32_t compact_index;    /* 1: 16-bit block-local column indices where they fit */
+    int64_t nnz_compact;      /* nonzeros read through 16-bit indices (compact_index) */
 } spx_plan_info;
 
 const char *spx_last_error(void);
@@ -603,6 +612,11 @@ spx_status spx_select_exhaustive_trees(spx_mat A, const int32_t *tree_sb, const 
  *   padding: chunk k of a block holds
  *   sorted entry 64 k + 16 j + l at 64 k + 4 l + j) and vals[len];
  *   SPX_EUNSUPPORTED for other schedules.
+ * spx_plan_export_compact: the 16-bit indices of a plan tuned with
+ *   compact_index, colidx16[nnz] at the stored positions (offsets from the
+ *   block's cbase; zero where a block keeps 32-bit indices) and
+ *   cbase[nblocks] (-1 for such blocks and long-slot segments);
+ *   SPX_EUNSUPPORTED for other schedules.
  */
 spx_status spx_plan_export_csr(spx_plan P, int32_t *rowptr, int32_t *colidx, double *vals);
 spx_status spx_plan_export_split(spx_plan P, int32_t *leaf_slot_ptr, int32_t *slot_row,
@@ -611,6 +625,7 @@ spx_status spx_plan_export_parts(spx_plan P, int32_t *a, int32_t *b);
 spx_status spx_plan_export_perm(spx_plan P, int32_t *row_perm, int32_t *col_perm);
 spx_status spx_plan_export_sched(spx_plan P, int32_t *blk_desc, int32_t *tiles);
 spx_status spx_plan_export_gather_order(spx_plan P, int64_t *len, int32_t *ofs, uint32_t *colidx, double *vals);
+spx_status spx_plan_export_compact(spx_plan P, uint16_t *colidx16, int32_t *cbase);
 
 /* ----------------------------------------------------------------------
  * Measurement helpers.

@@ -36,7 +36,7 @@ class Tune(ctypes.Structure):
                 ("xcd_remap", ctypes.c_int32), ("reduce_iters", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
                 ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("sort_gathers", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("compact_index", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -53,7 +53,8 @@ class PlanInfo(ctypes.Structure):
                 ("partition_seconds", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("reduce_iters", ctypes.c_int32), ("nlong_rows", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("wave_blocks", ctypes.c_int32),
-                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("sort_gathers", ctypes.c_int32)]
+                ("pipeline", ctypes.c_int32), ("scan_reduce", ctypes.c_int32), ("sort_gathers", ctypes.c_int32),
+                ("compact_index", ctypes.c_int32), ("nnz_compact", ctypes.c_int64)]
 
 
 _VP = ctypes.c_void_p
@@ -100,6 +101,7 @@ _SIGS = {
     "spx_plan_export_perm": ([_VP, _VP, _VP], _I32),
     "spx_plan_export_sched": ([_VP, _VP, _VP], _I32),
     "spx_plan_export_gather_order": ([_VP, _VP, _VP, _VP, _VP], _I32),
+    "spx_plan_export_compact": ([_VP, _VP, _VP], _I32),
     "spx_stream_sink_len": ([_I64], _I64),
     "spx_stream_read": ([_VP, _I64, _VP, _VP], _I32),
     "spx_stream_copy": ([_VP, _VP, _I64, _VP], _I32),
@@ -389,6 +391,14 @@ class Plan:
         _check(lib().spx_plan_export_sched(self._h, _hp(bd), _hp(tl)))
         return bd[:4 * inf["nblocks"]].reshape(-1, 4), tl[:4 * inf["ntiles"]].reshape(-1, 4)
 
+    def export_compact(self):
+        """(colidx16 uint16[nnz], cbase int32[nblocks]) of a compact_index plan."""
+        inf = self.info()
+        c = np.empty(max(inf["nnz"], 1), np.uint16)
+        b = np.empty(max(inf["nblocks"], 1), np.int32)
+        _check(lib().spx_plan_export_compact(self._h, _hp(c), _hp(b)))
+        return c[:inf["nnz"]], b[:inf["nblocks"]]
+
     def export_gather_order(self):
         """(ofs[nblocks], colidx uint32[len], vals[len]) of the gather-sorted copy."""
         n = ctypes.c_int64()
@@ -457,7 +467,7 @@ def plan_retune(P: Plan, tune=None):
 
 
 _TUNE_FIELDS = ("wg_size", "nnz_per_block", "blocks_per_tile", "window_entries", "xcd_remap", "reduce_iters",
-                "tiles_per_group", "wave_blocks", "pipeline", "scan_reduce", "sort_gathers")
+                "tiles_per_group", "wave_blocks", "pipeline", "scan_reduce", "sort_gathers", "compact_index")
 
 
 def autotune_candidates():

@@ -65,6 +65,7 @@ Tune resolve_tune(const spx_tune *t, int form) {
         if (t->pipeline) r.pipeline = t->pipeline > 0 ? 1 : 0;
         if (t->scan_reduce) r.scan = t->scan_reduce > 0 ? 1 : 0;
         if (t->sort_gathers) r.sort_gathers = t->sort_gathers > 0 ? 1 : 0;
+        if (t->compact_index) r.compact_index = t->compact_index > 0 ? 1 : 0;
     }
     if (r.wg != 64 && r.wg != 128 && r.wg != 256 && r.wg != 512 && r.wg != 1024)
         fail(SPX_EINVAL, "wg_size must be 64, 128, 256, 512 or 1024");
@@ -79,6 +80,10 @@ Tune resolve_tune(const spx_tune *t, int form) {
     if (r.sort_gathers && (r.wave_blocks || r.pipeline || r.tiles_per_group > 0 || r.blocks_per_tile > 1 ||
                            (t && t->window_entries > 0)))
         fail(SPX_EINVAL, "sort_gathers runs one block per workgroup: no tiles, windows, wave blocks or pipeline");
+    if (r.compact_index && (r.sort_gathers || r.scan || r.wave_blocks || r.pipeline || r.tiles_per_group > 0 ||
+                            r.blocks_per_tile > 1 || (t && t->window_entries > 0)))
+        fail(SPX_EINVAL, "compact_index runs workgroup row blocks alone: no tiles, windows, wave blocks, pipeline, "
+                         "scan_reduce or sort_gathers");
     if (!r.wave_blocks && !r.pipeline && !r.scan && !r.sort_gathers && r.wg == 1024 &&
         (r.tiles_per_group == 0 || (t && t->window_entries <= 0)))
         fail(SPX_EUNSUPPORTED, "wg_size 1024 runs only scan blocks, gather-sorted blocks, wave blocks, pipelined "
@@ -184,6 +189,13 @@ void upload_schedule(spx_plan_s &P, void *stream) {
         P.d_vals_sorted.reset();
         P.d_sorted_ofs.reset();
     }
+    if (P.tune.compact_index) {
+        P.d_colidx16 = dev_upload(P.colidx16.data(), P.colidx16.size() * 2, kPadEntries * 2, stream);
+        P.d_blk_cbase = dev_upload(P.blk_cbase.data(), P.blk_cbase.size() * 4, 16, stream);
+    } else {
+        P.d_colidx16.reset();
+        P.d_blk_cbase.reset();
+    }
     P.d_tiles = dev_upload(P.tiles.data(), P.tiles.size() * 4, 16, stream);
     P.d_long_seg_ptr = dev_upload(P.long_seg_ptr.data(), P.long_seg_ptr.size() * 4, 16, stream);
     size_t nlong = P.long_seg_ptr.empty() ? 0 : P.long_seg_ptr.size() - 1;
@@ -262,6 +274,10 @@ hipError_t spx::run_product(spx_plan_s &P, const double *x, double *y, int32_t a
         a.scol = (const int32_t *)P.d_colidx_sorted->ptr;
         a.sval = (const double *)P.d_vals_sorted->ptr;
         a.sofs = (const int32_t *)P.d_sorted_ofs->ptr;
+    }
+    if (P.tune.compact_index) {
+        a.c16 = (const uint16_t *)P.d_colidx16->ptr;
+        a.cbase = (const int32_t *)P.d_blk_cbase->ptr;
     }
     a.x = x;
     a.y = y;
@@ -447,7 +463,8 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->sum_lambda_row = P->sum_lambda_row;
         info->border_row_nnz = P->border_row_nnz;
         info->cut_connectivity = P->cut;
-        info->bytes_matrix = 12 * P->nnz + 4 * (int64_t)P->slot_ptr.size() +
+        info->nnz_compact = P->nnz_compact;
+        info->bytes_matrix = 12 * P->nnz - 2 * P->nnz_compact + 4 * (int64_t)P->slot_ptr.size() +
                              4 * (int64_t)P->slot_row.size() + 4 * (int64_t)P->blk_desc.size() +
                              4 * (int64_t)P->tiles.size();
         info->bytes_window = P->window_bytes_fill;
@@ -461,6 +478,7 @@ spx_status spx_plan_info_get(spx_plan P, spx_plan_info *info) {
         info->pipeline = P->tune.pipeline;
         info->scan_reduce = P->tune.scan;
         info->sort_gathers = P->tune.sort_gathers;
+        info->compact_index = P->tune.compact_index;
     });
 }
 
@@ -579,6 +597,15 @@ spx_status spx_plan_export_gather_order(spx_plan P, int64_t *len, int32_t *ofs, 
         if (ofs) std::copy(P->sorted_ofs.begin(), P->sorted_ofs.end(), ofs);
         if (colidx) std::copy(P->colidx_sorted.begin(), P->colidx_sorted.end(), colidx);
         if (vals) std::copy(P->vals_sorted.begin(), P->vals_sorted.end(), vals);
+    });
+}
+
+spx_status spx_plan_export_compact(spx_plan P, uint16_t *colidx16, int32_t *cbase) {
+    return guarded([&] {
+        if (!P) fail(SPX_EINVAL, "NULL handle");
+        if (!P->tune.compact_index) fail(SPX_EUNSUPPORTED, "the plan is not tuned with compact_index");
+        if (colidx16) std::copy(P->colidx16.begin(), P->colidx16.end(), colidx16);
+        if (cbase) std::copy(P->blk_cbase.begin(), P->blk_cbase.end(), cbase);
     });
 }
 

@@ -32,6 +32,8 @@ struct SpmvArgsT {
     const int32_t *scol;          // gather-sorted copy (sort_gathers): packed indices, interleaved chunks
     const V *sval;                // its values
     const int32_t *sofs;          // its 64-aligned offset of every multi-row block
+    const uint16_t *c16;          // compact_index: 16-bit offsets from cbase[block], padded like colidx
+    const int32_t *cbase;         // smallest column of every block, -1 where the 32-bit indices serve
     const int32_t *long_seg_ptr;  // [nlong+1] partial-sum entries of each long slot
     double *partials;             // one per long-slot segment
     uint32_t *counters;           // one per long slot, zero between products

@@ -254,6 +254,50 @@ __device__ __forceinline__ void sorted_row_block(const SpmvArgsT<V, A> &a, const
     sum_rows<WG, SPLIT>(a, d, sprod, sptr, tid);
 }
 
+// A multi-row block read through 16-bit indices: the offsets from the
+// block's smallest column cb come four to a thread in one 8-byte load
+// (instead of 16 bytes of 32-bit indices); entries of the aligned start
+// before d.z and past d.w belong to other blocks, whose offsets are from
+// another base, so they gather x[cb] (a column of this block) and their
+// products are dropped, which keeps the four gathers unconditional.  Rows
+// are summed as in multi_row_block.
+template <int WG, int NPT, bool SPLIT, class V, class A>
+__device__ __forceinline__ void compact_row_block(const SpmvArgsT<V, A> &a, const v4i d, int32_t cb, A *sprod,
+                                                  int32_t *sptr) {
+    const int tid = threadIdx.x;
+    const v2u *__restrict__ c4 = reinterpret_cast<const v2u *>(a.c16);
+    const int32_t zb = d.z & ~3;
+    const int32_t nr = d.y - d.x;  // at most WG (schedule)
+    const int32_t G = (d.w - zb + 3) >> 2;
+    const int32_t rp0 = a.slot_ptr[d.x + min(tid, nr)];
+    const int32_t rp1 = (nr == WG && tid == 0) ? a.slot_ptr[d.x + WG] : 0;
+#pragma unroll
+    for (int u = 0; u < NPT / 4; ++u) {
+        const int gi = tid + u * WG;
+        if (gi < G) {
+            const v2u cc = __builtin_nontemporal_load(&c4[(zb >> 2) + gi]);
+            const auto vv = load4(a.vals, zb + 4 * gi);
+            const int32_t k0 = zb + 4 * gi;
+            const int32_t c[4] = {(int32_t)(cc.x & 0xFFFFu), (int32_t)(cc.x >> 16), (int32_t)(cc.y & 0xFFFFu),
+                                  (int32_t)(cc.y >> 16)};
+            A *sp = &sprod[4 * gi];
+            bool in[4];
+            A xv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                in[j] = k0 + j >= d.z && k0 + j < d.w;
+                xv[j] = a.x[cb + (in[j] ? c[j] : 0)];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sp[j] = in[j] ? vv.v[j] * xv[j] : A(0);
+        }
+    }
+    if (tid <= nr) sptr[tid] = rp0 - zb;
+    if (nr == WG && tid == 0) sptr[WG] = rp1 - zb;
+    __syncthreads();
+    sum_rows<WG, SPLIT>(a, d, sprod, sptr, tid);
+}
+
 // Partial sum number `seg` of long (or cut) slot number lr, which is slot
 // `slot`: stored directly when the slot has one partial, else combined by
 // the one that arrives last.
@@ -801,6 +845,25 @@ __global__ __launch_bounds__(WG) void spmv_sorted_scan(SpmvArgsT<V, A> a) {
     else long_row_segment<WG, NPT, SPLIT, 0>(a, d, sws, sws, 0, 0);
 }
 
+// One workgroup per block with 16-bit indices where the block has them
+// (XCD mapping as in spmv_blocks); other blocks read the 32-bit indices.
+template <int WG, int NPT, bool SPLIT, class V, class A>
+__global__ __launch_bounds__(WG) void spmv_compact(SpmvArgsT<V, A> a) {
+    __shared__ A sprod[NPT * WG];
+    __shared__ int32_t sptr[WG + 1];
+    __shared__ A swave[WG / 64];
+    const int id = unit_of(a, blockIdx.x);
+    if (id < 0) return;
+    const v4i d = reinterpret_cast<const v4i *>(a.blk_desc)[id];
+    if (d.y < 0) {
+        long_row_segment<WG, NPT, SPLIT, 0>(a, d, swave, swave, 0, 0);
+        return;
+    }
+    const int32_t cb = a.cbase[id];
+    if (cb >= 0) compact_row_block<WG, NPT, SPLIT>(a, d, cb, sprod, sptr);
+    else multi_row_block<WG, NPT, SPLIT, 0>(a, d, sprod, sptr, swave, 0, 0);
+}
+
 // ------------------------------------------------------------------ batched
 // One persistent launch over the blocks of many matrices.  Each workgroup
 // takes the next item from a queue counter (items are sorted by decreasing
@@ -1184,6 +1247,19 @@ hipError_t launch_sorted_scan(const SpmvArgsT<V, A> &a0, bool split, bool, hipSt
     return hipGetLastError();
 }
 
+template <int WG, int NPT, int WMAX, class V, class A>
+hipError_t launch_compact(const SpmvArgsT<V, A> &a0, bool split, bool, hipStream_t s) {
+    static_assert(WMAX == 0, "compact-index blocks take no window");
+    if (a0.ntiles <= 0) return hipSuccess;
+    SpmvArgsT<V, A> a = a0;
+    const unsigned grid = grid_of_units(a);
+    if (split)
+        hipLaunchKernelGGL((spmv_compact<WG, NPT, true, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    else
+        hipLaunchKernelGGL((spmv_compact<WG, NPT, false, V, A>), dim3(grid), dim3(WG), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class A>
 struct Variant {
     int wg, npt, wmax;
@@ -1213,6 +1289,15 @@ struct SortedTable {
         {1024, 4, 0, launch_sorted<1024, 4, 0, double, double>},
         {256, 8, 0, launch_sorted<256, 8, 0, double, double>},
         {512, 8, 0, launch_sorted<512, 8, 0, double, double>},
+    };
+};
+
+// compact-index kernels (binary64)
+struct CompactTable {
+    static constexpr Variant<double, double> v[] = {
+        {128, 4, 0, launch_compact<128, 4, 0, double, double>},
+        {256, 4, 0, launch_compact<256, 4, 0, double, double>},
+        {512, 4, 0, launch_compact<512, 4, 0, double, double>},
     };
 };
 
@@ -1409,6 +1494,7 @@ bool spmv_variant_exists(int wg, int npt, int window_entries, int *wmax_out, Kin
         case Kind::Scan: return find_in<ScanTable<double, double>>(wg, npt, window_entries, wmax_out);
         case Kind::Sorted: return find_in<SortedTable>(wg, npt, window_entries, wmax_out);
         case Kind::SortedScan: return find_in<SortedScanTable>(wg, npt, window_entries, wmax_out);
+        case Kind::Compact: return find_in<CompactTable>(wg, npt, window_entries, wmax_out);
         default: return find_variant<double, double>(wg, npt, window_entries, wmax_out);
     }
 }
@@ -1419,7 +1505,8 @@ bool spmv_lowp_variant_exists(int wg, int npt, Kind k) {
         case Kind::Waves: return find_wave_variant<float, float>(wg, npt, -1, nullptr);
         case Kind::Scan: return find_in<ScanTable<float, float>>(wg, npt, -1, nullptr);
         case Kind::Sorted:
-        case Kind::SortedScan: return false;
+        case Kind::SortedScan:
+        case Kind::Compact: return false;
         default: return find_variant<float, float>(wg, npt, -1, nullptr);
     }
 }
@@ -1432,6 +1519,7 @@ hipError_t launch_spmv(const SpmvArgs &a, int wg, int npt, int window_entries, b
         case Kind::Scan: return launch_in<ScanTable<double, double>>(a, wg, npt, window_entries, split, s);
         case Kind::Sorted: return launch_in<SortedTable>(a, wg, npt, window_entries, split, s);
         case Kind::SortedScan: return launch_in<SortedScanTable>(a, wg, npt, window_entries, split, s);
+        case Kind::Compact: return launch_in<CompactTable>(a, wg, npt, window_entries, split, s);
         default: return launch_any(a, wg, npt, window_entries, tiled, split, s);
     }
 }
@@ -1444,7 +1532,8 @@ hipError_t launch_lowp(const SpmvArgsT<V, float> &a, int wg, int npt, bool split
         case Kind::Waves: return launch_wave_any(a, wg, npt, -1, split, s);
         case Kind::Scan: return launch_in<ScanTable<V, float>>(a, wg, npt, -1, split, s);
         case Kind::Sorted:
-        case Kind::SortedScan: return hipErrorInvalidValue;
+        case Kind::SortedScan:
+        case Kind::Compact: return hipErrorInvalidValue;
         default: return launch_any(a, wg, npt, -1, false, split, s);
     }
 }

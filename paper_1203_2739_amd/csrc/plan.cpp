@@ -571,6 +571,37 @@ static void gather_sorted_storage(spx_plan_s &P) {
     });
 }
 
+// Compact indices (compact_index): every multi-row block whose columns lie
+// within 65,536 of its smallest column keeps 16-bit offsets from that column
+// (blk_cbase) at the stored positions of its nonzeros; other blocks keep
+// blk_cbase = -1 and the 32-bit indices.  Empty otherwise.
+static void compact_index_storage(spx_plan_s &P) {
+    P.colidx16.clear();
+    P.blk_cbase.clear();
+    P.nnz_compact = 0;
+    if (!P.tune.compact_index) return;
+    const int64_t nb = (int64_t)(P.blk_desc.size() / 4);
+    P.colidx16.assign(P.colidx.size(), 0);
+    P.blk_cbase.assign((size_t)nb, -1);
+    std::vector<int64_t> count((size_t)nb, 0);
+    parallel_for(nb, [&](int64_t lo, int64_t hi) {
+        for (int64_t b = lo; b < hi; ++b) {
+            const int32_t *d = &P.blk_desc[4 * (size_t)b];
+            if (d[1] < 0 || d[3] <= d[2]) continue;
+            int32_t cmin = P.colidx[d[2]], cmax = cmin;
+            for (int32_t z = d[2]; z < d[3]; ++z) {
+                cmin = std::min(cmin, P.colidx[z]);
+                cmax = std::max(cmax, P.colidx[z]);
+            }
+            if (cmax - cmin > 65535) continue;
+            P.blk_cbase[(size_t)b] = cmin;
+            for (int32_t z = d[2]; z < d[3]; ++z) P.colidx16[(size_t)z] = (uint16_t)(P.colidx[z] - cmin);
+            count[(size_t)b] = d[3] - d[2];
+        }
+    });
+    for (int64_t c : count) P.nnz_compact += c;
+}
+
 // Lanes the kernel gives to each row of a block of nr rows: the largest
 // power of two <= wg / nr, at most a wave.
 static int32_t lanes_per_row(int32_t wg, int32_t nr) {
@@ -730,6 +761,7 @@ void build_schedule(spx_plan_s &P) {
     if (T.tiles_per_group > 0) group_tiles(P, P.xcd_blk_ptr, T.tiles_per_group, T.window_entries);
     group_ptr(true, P.xcd_tile_ptr);
     gather_sorted_storage(P);
+    compact_index_storage(P);
 }
 
 }  // namespace spx

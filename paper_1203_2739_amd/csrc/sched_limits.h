@@ -17,9 +17,9 @@ constexpr int kReduceIters = 64;
 // g of the MI355X, and the plans order columns by the groups that read them.
 constexpr int kXcdGroups = 8;
 // Kernel that runs a schedule: row blocks, wave blocks, pipelined tiles, row
-// blocks summed by a segmented scan, row blocks stored sorted by column, or
-// both of the last two.
-enum class Kind : int { Blocks = 0, Waves = 1, Pipe = 2, Scan = 3, Sorted = 4, SortedScan = 5 };
+// blocks summed by a segmented scan, row blocks stored sorted by column,
+// both of the last two, or row blocks with 16-bit block-local indices.
+enum class Kind : int { Blocks = 0, Waves = 1, Pipe = 2, Scan = 3, Sorted = 4, SortedScan = 5, Compact = 6 };
 // Gather-sorted storage: a column index keeps the nonzero's offset in row
 // order from its block's aligned start (below nt, the block's capacity) in
 // its upper bits; the column takes the low pack_shift(nt) bits, so columns

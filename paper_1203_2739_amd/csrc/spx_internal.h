@@ -86,7 +86,7 @@ DevPtr dev_upload(const void *host, size_t bytes, size_t pad_bytes, void *stream
 struct Tune {
     int32_t wg = kDefaultWG, nnz_per_block = kDefaultNpt * kDefaultWG, blocks_per_tile = 1, window_entries = -1;
     int32_t xcd_remap = 1, reduce_iters = kReduceIters, tiles_per_group = 0, wave_blocks = 0, pipeline = 0;
-    int32_t scan = 0, sort_gathers = 0;
+    int32_t scan = 0, sort_gathers = 0, compact_index = 0;
 };
 Tune resolve_tune(const spx_tune *t, int form);
 inline bool tiled(const Tune &t) {
@@ -100,6 +100,7 @@ inline Kind kind_of(const Tune &t) {
            : t.scan && t.sort_gathers ? Kind::SortedScan
            : t.scan        ? Kind::Scan
            : t.sort_gathers ? Kind::Sorted
+           : t.compact_index ? Kind::Compact
                             : Kind::Blocks;
 }
 
@@ -140,13 +141,19 @@ struct spx_plan_s {
     std::vector<uint32_t> colidx_sorted;
     std::vector<double> vals_sorted;
     std::vector<int32_t> sorted_ofs;
+    // compact_index: 16-bit column offsets from blk_cbase[b] (the smallest
+    // column of block b, or -1 when its columns span 65,536 or more, or for
+    // a long-slot segment), at the stored positions
+    std::vector<uint16_t> colidx16;
+    std::vector<int32_t> blk_cbase;
+    int64_t nnz_compact = 0;
     std::vector<float> vals32;                  // precision mode: values rounded to binary32
     std::vector<uint16_t> vals16;               // precision mode: binary32 values rounded to bfloat16
     int64_t window_nnz = 0, window_bytes_fill = 0;
     // device copies
     spx::DevPtr d_slot_ptr, d_slot_row, d_colidx, d_vals, d_row_perm, d_col_perm;
     spx::DevPtr d_blk_desc, d_tiles, d_long_seg_ptr, d_partials, d_counters;
-    spx::DevPtr d_colidx_sorted, d_vals_sorted, d_sorted_ofs;
+    spx::DevPtr d_colidx_sorted, d_vals_sorted, d_sorted_ofs, d_colidx16, d_blk_cbase;
     spx::DevPtr d_vals32, d_vals16;
     // statistics
     int64_t sum_lambda_col = 0, sum_lambda_row = 0, border_row_nnz = 0, cut = 0;

@@ -48,6 +48,10 @@ const std::vector<spx_tune> &autotune_candidates() {
         for (int wg : {256, 512, 1024}) add(wg, 4, 0, 0, 0, 0, 1, 1);
         add(256, 8, 0, 0, 0, 0, 1, 1);
         add(512, 8, 0, 0, 0, 0, 1, 1);
+        for (int wg : {128, 256, 512}) {
+            add(wg, 4);
+            v.back().compact_index = 1;
+        }
         add(256, 4, 1);
         add(512, 4, 1);
         add(1024, 4, 1);
@@ -167,6 +171,7 @@ spx_status spx_plan_autotune(spx_plan P, int32_t precision, const void *x, void 
             chosen->pipeline = P->tune.pipeline;
             chosen->scan_reduce = P->tune.scan;
             chosen->sort_gathers = P->tune.sort_gathers;
+            chosen->compact_index = P->tune.compact_index;
         }
         if (ms) *ms = best_ms;
     });

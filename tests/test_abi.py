@@ -725,3 +725,59 @@ def test_gather_sorted_limits():
     P = spx.plan_plain(M)
     with pytest.raises(spx.SpxError):
         P.export_gather_order()
+
+
+@pytest.mark.parametrize("form", ["plain", "db", "split"])
+def test_compact_indices(orc, form):
+    """compact_index: a multi-row block whose columns lie within 65,536 of
+    its smallest column has cbase = that column and 16-bit offsets at its
+    stored positions that give back every column; other blocks and long-slot
+    segments have cbase = -1; nnz_compact counts the nonzeros of the compact
+    blocks and bytes_matrix drops 2 bytes for each.  A banded matrix is
+    compact everywhere."""
+    rng = np.random.default_rng(12)
+    R = long_row_csr([0, 3, 1, 1021, 5, 2045, 7000, 7] + list(rng.integers(0, 60, 3000)), 200_000)
+    # the first 1500 short rows read columns near 60 i: their blocks are compact
+    cols, rp = [], [0]
+    for i in range(R.m):
+        c = R.colidx[R.rowptr[i]:R.rowptr[i + 1]]
+        if 8 <= i < 1508:
+            c = np.sort(rng.choice(np.arange(60 * i, 60 * i + 200), c.size, replace=False))
+        cols.append(c)
+        rp.append(rp[-1] + c.size)
+    A = CSR(R.m, R.n, np.array(rp), np.concatenate(cols).astype(np.int32), R.vals)
+    M = spx.from_csr(A, device=False)
+    tune = dict(wg_size=256, compact_index=1)
+    if form == "plain":
+        P = spx.plan_plain(M, tune=tune)
+    else:
+        P = (spx.reorder_db if form == "db" else spx.split)(M, 4, 0, 2, tune=tune)[0]
+    check_schedule(P)
+    inf = P.info()
+    ci = P.export_split()["colidx"] if form == "split" else P.export_csr()[1]
+    c16, cb = P.export_compact()
+    bd, _ = P.export_sched()
+    total = 0
+    for b, (s_lo, s_hi, z0, z1) in enumerate(bd):
+        cols = ci[z0:z1].astype(np.int64)
+        fits = s_hi >= 0 and z1 > z0 and int(cols.max() - cols.min()) <= 65535
+        if not fits:
+            assert cb[b] == -1
+            continue
+        assert cb[b] == cols.min()
+        assert np.array_equal(cb[b] + c16[z0:z1].astype(np.int64), cols)
+        total += z1 - z0
+    assert inf["nnz_compact"] == total
+    if form == "plain":
+        assert 0 < total < A.nnz
+        assert inf["bytes_matrix"] == spx.plan_plain(M, tune=dict(wg_size=256)).info()["bytes_matrix"] - 2 * total
+    from synth import gen_locality
+    B = gen_locality("band", n=20_000)
+    PB = spx.plan_plain(spx.from_csr(B, device=False), tune=tune)
+    assert PB.info()["nnz_compact"] == B.nnz
+    with pytest.raises(spx.SpxError):
+        spx.plan_plain(M).export_compact()
+    for bad in (dict(compact_index=1, scan_reduce=1), dict(compact_index=1, sort_gathers=1),
+                dict(compact_index=1, blocks_per_tile=4), dict(compact_index=1, wg_size=1024)):
+        with pytest.raises(spx.SpxError):
+            spx.plan_plain(M, tune=bad)

@@ -53,6 +53,8 @@ def test_schedule_names():
     assert bench.kernel_name([1024, 4096, 1, -1, 0, 0, 0, 0, 1]) == "spmv_sorted"
     assert bench.kernel_name([512, 2048, 1, -1, 0, 0, 0, 1, 1]) == "spmv_sorted_scan"
     assert bench.kernel_name([256, 256, 4, -1, 0, 1]) == "spmv_waves"
+    assert bench.schedule_name([256, 1024, 1, -1, 0, 0, 0, 0, 0, 1]) == "256x4c"
+    assert bench.kernel_name([256, 1024, 1, -1, 0, 0, 0, 0, 0, 1]) == "spmv_compact"
 
 
 def test_plan_hash_sees_every_part_of_the_layout():

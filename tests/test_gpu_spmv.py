@@ -70,7 +70,9 @@ TUNES = [None,
          dict(wg_size=1024, sort_gathers=1),
          dict(wg_size=256, sort_gathers=1, scan_reduce=1, xcd_remap=-1),
          dict(wg_size=1024, sort_gathers=1, scan_reduce=1),
-         dict(wg_size=512, nnz_per_block=4096, sort_gathers=1, scan_reduce=1)]
+         dict(wg_size=512, nnz_per_block=4096, sort_gathers=1, scan_reduce=1),
+         dict(wg_size=256, compact_index=1),
+         dict(wg_size=512, compact_index=1, xcd_remap=-1, reduce_iters=5)]
 SCAN_TUNES = [t for t in TUNES if t and t.get("scan_reduce")]
 SORTED_TUNES = [t for t in TUNES if t and t.get("sort_gathers")]
 
@@ -387,5 +389,10 @@ def test_locality_matrices(orc, kind):
     A = gen_locality(kind, seed=9, n=60_000, window=4096)
     x = gen_vectors(112, A.n)[0]
     ref, den = orc.spmv(A, x), orc.abs_rowsum(A, x)
-    for t in (dict(wg_size=512), dict(wg_size=1024, sort_gathers=1), dict(wg_size=256, scan_reduce=1)):
+    for t in (dict(wg_size=512), dict(wg_size=1024, sort_gathers=1), dict(wg_size=256, scan_reduce=1),
+              dict(wg_size=256, compact_index=1)):
         assert_close_rowwise(run_plain(A, x, t), ref, den, f"{kind} {t}")
+    # banded rows: every block reads 16-bit indices, integer data exact
+    if kind == "band":
+        Ai, xi = integer_problem(A, 21)
+        assert np.array_equal(run_plain(Ai, xi, dict(wg_size=512, compact_index=1)), orc.spmv(Ai, xi))
