@@ -105,7 +105,8 @@ def test_full_size_precision_products(orc, spd):
     per-entry bound of the sum order (its rows reach about 10^4 nonzeros, so
     gamma of the row length, not 1e-12, bounds it), the low precisions within
     the binary32 summation bound of the oracle's binary32 product of the same
-    rounded values.  Gather-sorted schedules run binary64 only."""
+    rounded values.  Gather-sorted and 16-bit-index schedules run binary64
+    only."""
     A, P = spd
     x = gen_vectors(3000, A.n, 1)[0]
     x32 = x.astype(np.float32)
@@ -125,7 +126,7 @@ def test_full_size_precision_products(orc, spd):
         spx.spmv(P, dev(x), y)
         yh = host(y)
         assert np.all(np.abs(yh - ref64) <= g64 * bound64), f"f64 {tune}"
-        if tune.get("sort_gathers"):
+        if tune.get("sort_gathers") or tune.get("compact_index"):
             with pytest.raises(spx.SpxError):
                 spx.spmv_lowp(P, "f32", dev(x32), torch.empty(A.m, dtype=torch.float32, device="cuda"))
             continue
