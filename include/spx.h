@@ -553,7 +553,7 @@ spx_status spx_mlp_loss_grad_noalloc(const float *theta, const float *X, const i
  * spx_plan_for_choice: the plan of choice c for A (partitioning at K = 256
  *   and coarsening for the reordered forms); row_perm[m] / col_perm[n]
  *   (host, may be NULL) receive its permutations (identity for plain).
- * spx_select_exhaustive: the fallback and the judge of the network's
+ * spx_select_exhaustive: the fallback and the yardstick of the network's
  *   regret: every choice is built and timed over `reps` products (two
  *   warm-up products first) of x (device, n binary64) into y (device, m,
  *   overwritten; split products include zeroing their shared rows) on

@@ -1,6 +1,6 @@
 // Learned choice of the product form: matrix features (host), the C
 // interface of the selector network's kernels, the 24 choices, selection by
-// the network and the exhaustive timing that is its fallback and judge.
+// the network and the exhaustive timing that is its fallback and yardstick.
 #include <hip/hip_runtime.h>
 
 #include <chrono>

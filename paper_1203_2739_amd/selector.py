@@ -3,7 +3,7 @@
 The 24 choices (6 schedules of plain CSR, and the SB, DB and split forms of
 Sections 3 and 4 at K = 8 .. 256) live in the library (spx_choice_info), as
 do the exhaustive timing of every choice (spx_select_exhaustive: the label,
-the fallback and the judge of the regret t(chosen) / t(best) - 1) and the
+the fallback and the measure of the regret t(chosen) / t(best) - 1) and the
 selection itself (spx_select / spx_select_features: features, normalisation,
 network forward, argmax).  This module holds what is training: the
 normalisation statistics of the training set, the label tolerance, and the
