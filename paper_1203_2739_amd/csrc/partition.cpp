@@ -31,6 +31,7 @@
 #include <future>
 #include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "spx_internal.h"
 
@@ -556,61 +557,112 @@ void absorb_nets(const Hypergraph &H, int64_t maxw, int64_t heavy_maxw, std::vec
     }
 }
 
-// Contract clusters into a coarse hypergraph.  Nets reduced to one cluster
-// vanish, nets spanning more than kCoarseNetCap clusters are left out of the
-// coarse levels (they are cut by nearly every bisection and only slow the
-// coarse search down; the finest level keeps them), and nets with identical
-// pin sets are merged by adding their costs.
-void contract(const Hypergraph &H, const std::vector<int32_t> &cmap, int32_t nc, Hypergraph &C) {
-    C.nv = nc;
-    C.vw.assign(nc, 0);
-    for (int32_t v = 0; v < H.nv; ++v) C.vw[cmap[v]] += H.vw[v];
+// The nets [n0, n1) of H as clusters: each net's distinct clusters in
+// ascending order with their hash, or nothing when fewer than two or more
+// than kCoarseNetCap remain.  A net's result depends on that net alone.
+struct ReducedNets {
+    std::vector<int64_t> off;  // net n0 + i holds pins[off[i], off[i + 1])
+    std::vector<int32_t> pins;
+    std::vector<uint64_t> hash;
+};
+
+void reduce_nets(const Hypergraph &H, const std::vector<int32_t> &cmap, int32_t nc, int32_t n0, int32_t n1,
+                 ReducedNets &R) {
     std::vector<int32_t> mark(nc, -1);
-    C.xpins.clear();
-    C.pins.clear();
-    C.nc.clear();
-    C.nrow.clear();
-    C.xpins.push_back(0);
     std::vector<int32_t> buf;
-    // open-addressing table of net hashes -> coarse net id
-    size_t cap = 1;
-    while (cap < 2 * (size_t)H.nn + 16) cap <<= 1;
-    std::vector<int32_t> table(cap, -1);
-    std::vector<uint64_t> nhash;
-    for (int32_t n = 0; n < H.nn; ++n) {
+    R.off.assign((size_t)(n1 - n0) + 1, 0);
+    R.hash.assign((size_t)(n1 - n0), 0);
+    R.pins.clear();
+    for (int32_t n = n0; n < n1; ++n) {
         buf.clear();
         for (int64_t p = H.xpins[n]; p < H.xpins[n + 1]; ++p) {
             int32_t c = cmap[H.pins[p]];
             if (mark[c] != n) { mark[c] = n; buf.push_back(c); }
         }
-        if (buf.size() < 2 || (int64_t)buf.size() > kCoarseNetCap) continue;
-        std::sort(buf.begin(), buf.end());
-        uint64_t h = 1469598103934665603ull ^ buf.size();
-        for (int32_t c : buf) h = (h ^ (uint64_t)c) * 1099511628211ull;
-        uint8_t row = H.nrow.empty() ? 0 : H.nrow[n];
-        h ^= row;
-        size_t slot = (size_t)(h ^ (h >> 29)) & (cap - 1);
-        int32_t found = -1;
-        while (table[slot] >= 0) {
-            int32_t e = table[slot];
-            if (nhash[e] == h && C.nrow[e] == row &&
-                (size_t)(C.xpins[e + 1] - C.xpins[e]) == buf.size() &&
-                std::equal(buf.begin(), buf.end(), C.pins.begin() + C.xpins[e])) {
-                found = e;
-                break;
+        if (buf.size() >= 2 && (int64_t)buf.size() <= kCoarseNetCap) {
+            std::sort(buf.begin(), buf.end());
+            uint64_t h = 1469598103934665603ull ^ buf.size();
+            for (int32_t c : buf) h = (h ^ (uint64_t)c) * 1099511628211ull;
+            h ^= H.nrow.empty() ? 0 : H.nrow[n];
+            R.hash[n - n0] = h;
+            R.pins.insert(R.pins.end(), buf.begin(), buf.end());
+        }
+        R.off[n - n0 + 1] = (int64_t)R.pins.size();
+    }
+}
+
+// Contract clusters into a coarse hypergraph.  Nets reduced to one cluster
+// vanish, nets spanning more than kCoarseNetCap clusters are left out of the
+// coarse levels (they are cut by nearly every bisection and only slow the
+// coarse search down; the finest level keeps them), and nets with identical
+// pin sets are merged by adding their costs.  Large hypergraphs reduce their
+// nets on several threads; the merge then walks the nets in order, so the
+// result does not depend on the thread count.
+void contract(const Hypergraph &H, const std::vector<int32_t> &cmap, int32_t nc, Hypergraph &C) {
+    C.nv = nc;
+    C.vw.assign(nc, 0);
+    for (int32_t v = 0; v < H.nv; ++v) C.vw[cmap[v]] += H.vw[v];
+    // one thread per 2^20 pins, at most the partitioner's thread count
+    int32_t T = (int32_t)std::min<size_t>(H.pins.size() >> 20, (size_t)std::max<int32_t>(1, num_threads()));
+    T = std::max<int32_t>(1, std::min<int32_t>(T, H.nn));
+    // chunks of nets holding about equal numbers of pins
+    std::vector<int32_t> cut(T + 1, H.nn);
+    cut[0] = 0;
+    for (int32_t t = 1; t < T; ++t) {
+        int64_t want = (int64_t)((double)H.pins.size() * t / T);
+        cut[t] = (int32_t)(std::lower_bound(H.xpins.begin(), H.xpins.begin() + H.nn, want) - H.xpins.begin());
+        cut[t] = std::max(cut[t], cut[t - 1]);
+    }
+    std::vector<ReducedNets> R(T);
+    if (T == 1) {
+        reduce_nets(H, cmap, nc, 0, H.nn, R[0]);
+    } else {
+        std::vector<std::thread> th;
+        for (int32_t t = 0; t < T; ++t)
+            th.emplace_back([&, t] { reduce_nets(H, cmap, nc, cut[t], cut[t + 1], R[t]); });
+        for (auto &x : th) x.join();
+    }
+    C.xpins.clear();
+    C.pins.clear();
+    C.nc.clear();
+    C.nrow.clear();
+    C.xpins.push_back(0);
+    // open-addressing table of net hashes -> coarse net id
+    size_t cap = 1;
+    while (cap < 2 * (size_t)H.nn + 16) cap <<= 1;
+    std::vector<int32_t> table(cap, -1);
+    std::vector<uint64_t> nhash;
+    for (int32_t t = 0; t < T; ++t) {
+        const ReducedNets &Q = R[t];
+        for (int32_t n = cut[t]; n < cut[t + 1]; ++n) {
+            size_t i = (size_t)(n - cut[t]);
+            int64_t len = Q.off[i + 1] - Q.off[i];
+            if (len == 0) continue;
+            const int32_t *b = Q.pins.data() + Q.off[i];
+            uint64_t h = Q.hash[i];
+            uint8_t row = H.nrow.empty() ? 0 : H.nrow[n];
+            size_t slot = (size_t)(h ^ (h >> 29)) & (cap - 1);
+            int32_t found = -1;
+            while (table[slot] >= 0) {
+                int32_t e = table[slot];
+                if (nhash[e] == h && C.nrow[e] == row && C.xpins[e + 1] - C.xpins[e] == len &&
+                    std::equal(b, b + len, C.pins.begin() + C.xpins[e])) {
+                    found = e;
+                    break;
+                }
+                slot = (slot + 1) & (cap - 1);
             }
-            slot = (slot + 1) & (cap - 1);
+            if (found >= 0) {
+                C.nc[found] += H.nc[n];
+                continue;
+            }
+            table[slot] = (int32_t)C.nc.size();
+            nhash.push_back(h);
+            C.pins.insert(C.pins.end(), b, b + len);
+            C.xpins.push_back((int64_t)C.pins.size());
+            C.nc.push_back(H.nc[n]);
+            C.nrow.push_back(row);
         }
-        if (found >= 0) {
-            C.nc[found] += H.nc[n];
-            continue;
-        }
-        table[slot] = (int32_t)C.nc.size();
-        nhash.push_back(h);
-        C.pins.insert(C.pins.end(), buf.begin(), buf.end());
-        C.xpins.push_back((int64_t)C.pins.size());
-        C.nc.push_back(H.nc[n]);
-        C.nrow.push_back(row);
     }
     C.nn = (int32_t)C.nc.size();
     C.build_vertex_side();
@@ -821,7 +873,7 @@ struct Ctx {
     std::vector<Leaf> leaves;
     std::vector<int32_t> removed;  // eRCN: nonzeros whose row went to R_B
     std::atomic<int64_t> cut{0};
-    std::atomic<int32_t> active{1};
+    std::atomic<int32_t> active{1};  // threads working (not waiting), this one included
 };
 
 // Column-net hypergraph of a subset of rows (vertices = rows, nets = the
@@ -1061,16 +1113,22 @@ void recurse(Ctx &C, Sub S, int32_t K, int32_t part, uint64_t path, int32_t dept
         C.leaves.push_back(Leaf{part, path, depth, std::move(keep.gid)});
         return;
     }
+    // the first half goes to another thread when one is free, this thread
+    // works on the second half and gives up its slot only while it waits
     std::vector<std::future<void>> futs;
     if (leafmode) {
         uint64_t bit = depth < 63 ? (1ull << (63 - depth)) : 0;
         spawn_or_run(C, std::move(out[0]), 1, part, path, depth + 1, true, futs);
-        spawn_or_run(C, std::move(out[1]), 1, part, path | bit, depth + 1, true, futs);
+        recurse(C, std::move(out[1]), 1, part, path | bit, depth + 1, true);
     } else {
         spawn_or_run(C, std::move(out[0]), K0, part, 0, depth + 1, false, futs);
-        spawn_or_run(C, std::move(out[1]), K1, part + K0, 0, depth + 1, false, futs);
+        recurse(C, std::move(out[1]), K1, part + K0, 0, depth + 1, false);
     }
-    for (auto &f : futs) f.get();
+    if (!futs.empty()) {
+        C.active--;
+        for (auto &f : futs) f.get();
+        C.active++;
+    }
 }
 
 }  // namespace

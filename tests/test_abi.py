@@ -266,6 +266,25 @@ def test_determinism_across_threads_and_runs():
         assert outs[i] == outs[3 + i] == outs[6 + i] == outs[9 + i]
 
 
+def test_determinism_when_contraction_runs_on_threads():
+    # 1.2 M nonzeros: the nonzero-vertex hypergraphs of DB and the split hold
+    # 2.4 M pins, enough for the coarsening to reduce nets on two threads
+    A = gen_uniform_zipf(23, 60000, 1_200_000, 400)
+    M = spx.from_csr(A, device=False)
+    outs = {}
+    try:
+        for threads in (1, 8):
+            spx.set_num_threads(threads)
+            for fn in (spx.reorder_db, spx.split):
+                P, rp, cp, pp = fn(M, 8, 0, 5)
+                outs.setdefault(fn.__name__, []).append(
+                    (rp.tobytes(), cp.tobytes(), pp.tobytes(), *[x.tobytes() for x in P.export_parts()]))
+    finally:
+        spx.set_num_threads(8)
+    for name, o in outs.items():
+        assert o[0] == o[1], name
+
+
 def test_seed_changes_partition():
     A = gen_uniform_zipf(22, 2000, 20000, 100)
     M = spx.from_csr(A, device=False)
