@@ -596,14 +596,15 @@ void reduce_nets(const Hypergraph &H, const std::vector<int32_t> &cmap, int32_t 
 // coarse levels (they are cut by nearly every bisection and only slow the
 // coarse search down; the finest level keeps them), and nets with identical
 // pin sets are merged by adding their costs.  Large hypergraphs reduce their
-// nets on several threads; the merge then walks the nets in order, so the
-// result does not depend on the thread count.
-void contract(const Hypergraph &H, const std::vector<int32_t> &cmap, int32_t nc, Hypergraph &C) {
+// nets on up to `threads` threads; the merge then walks the nets in order, so
+// the result does not depend on the thread count.
+void contract(const Hypergraph &H, const std::vector<int32_t> &cmap, int32_t nc, Hypergraph &C,
+              int32_t threads) {
     C.nv = nc;
     C.vw.assign(nc, 0);
     for (int32_t v = 0; v < H.nv; ++v) C.vw[cmap[v]] += H.vw[v];
-    // one thread per 2^20 pins, at most the partitioner's thread count
-    int32_t T = (int32_t)std::min<size_t>(H.pins.size() >> 20, (size_t)std::max<int32_t>(1, num_threads()));
+    // one thread per 2^20 pins, at most `threads`
+    int32_t T = (int32_t)std::min<size_t>(H.pins.size() >> 20, (size_t)std::max<int32_t>(1, threads));
     T = std::max<int32_t>(1, std::min<int32_t>(T, H.nn));
     // chunks of nets holding about equal numbers of pins
     std::vector<int32_t> cut(T + 1, H.nn);
@@ -707,7 +708,7 @@ static double now_s() {
 }
 
 int64_t bisect(const Hypergraph &H, double frac0, double eps, uint64_t seed,
-               std::vector<uint8_t> &side) {
+               std::vector<uint8_t> &side, int32_t threads) {
     side.assign(H.nv, 0);
     if (H.nv <= 1) return 0;
     double tb = now_s(), tm = 0, tc = 0, tf = 0;
@@ -739,7 +740,7 @@ int64_t bisect(const Hypergraph &H, double frac0, double eps, uint64_t seed,
         if (nc > (int32_t)(0.95 * cur->nv)) break;
         auto C = std::make_unique<Hypergraph>();
         t1 = now_s();
-        contract(*cur, cmap, nc, *C);
+        contract(*cur, cmap, nc, *C, threads);
         tc += now_s() - t1;
         // stop once the pins stop shrinking and the level is small enough
         // for the initial bisection: further levels only cost time
@@ -1073,7 +1074,9 @@ void recurse(Ctx &C, Sub S, int32_t K, int32_t part, uint64_t path, int32_t dept
     uint64_t sseed = mix(mix(C.seed, (uint64_t)part * 1315423911ull + (uint64_t)K),
                          path * 2654435761ull + (uint64_t)depth + (leafmode ? 77 : 0));
     std::vector<uint8_t> side;
-    int64_t c = bisect(S.H, frac0, C.eps, sseed, side);
+    // this thread and the free slots
+    const int32_t spare = std::max<int32_t>(1, num_threads() - C.active.load() + 1);
+    int64_t c = bisect(S.H, frac0, C.eps, sseed, side, spare);
     if (!leafmode && C.model == Model::ERowColumnNet) {
         int64_t c0 = c;
         auto rows_cut = [&](int64_t &nnzc) {

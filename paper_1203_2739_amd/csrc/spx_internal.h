@@ -35,9 +35,10 @@ struct Hypergraph {
 };
 
 // One bisection: side[v] in {0, 1}; part 0 gets about frac0 of the weight.
-// Returns the cutsize (sum of costs of cut nets).
+// Returns the cutsize (sum of costs of cut nets).  `threads` bounds the
+// threads its contraction may use; the result does not depend on it.
 int64_t bisect(const Hypergraph &H, double frac0, double eps, uint64_t seed,
-               std::vector<uint8_t> &side);
+               std::vector<uint8_t> &side, int32_t threads = 1);
 
 // Matrix in CSR (host).
 struct CsrHost {
