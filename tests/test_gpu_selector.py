@@ -1,6 +1,7 @@
 """Selector network kernels against the binary64 oracle (forward, loss,
-gradient, Adam), training on the GPU, and the learned choice on measured
-timings against the best single fixed choice."""
+gradient, Adam), training on the GPU, and the exhaustive timing of the 24
+choices.  The held-out study of the learned choice is in
+test_study_selector.py."""
 import numpy as np
 import pytest
 
@@ -71,35 +72,6 @@ def test_training_fits_a_teacher(orc):
     spx.mlp_forward(theta, Xd, logits)
     acc = np.mean(host(logits).argmax(axis=1) == labels)
     assert curve[-1] < 0.5 * curve[0] and acc > 0.85, (curve[0], curve[-1], acc)
-
-
-@pytest.mark.timeout(900)
-def test_selector_gains_on_held_out_matrices():
-    """End to end on matrices of the four families: every choice timed by the
-    library (spx_select_exhaustive), the network trained on 16 matrices and
-    judged on 8 others it never saw, choosing through spx_select.  Its mean
-    held-out regret must not exceed that of the best fixed choice (picked on
-    the training matrices) by more than 0.03, nor that of plain CSR."""
-    from paper_1203_2739_amd import selector
-    from synth import gen_family
-    fams = ("F1", "F2", "F3", "F4")
-    sizes = [12000, 20000, 30000, 45000, 16000, 26000]
-    mats = [gen_family(f, 300 + 10 * s + k, sizes[s]) for s in range(6) for k, f in enumerate(fams)]
-    T = np.stack([selector.measure(A, seed=i, reps=5)[0] for i, A in enumerate(mats)])
-    assert np.all(T > 0)
-    F = selector.feature_matrix(mats)
-    tr, te = np.arange(16), np.arange(16, 24)
-    norm = selector.Normalizer(F[tr])
-    theta, settings, _ = selector.fit(F[tr], T[tr], norm, epochs=200, check_every=40, lrs=(3e-3,))
-    chosen = np.array([spx.select(spx.from_csr(mats[i], device=False), theta, norm.mu, norm.sd)[0] for i in te])
-    assert np.array_equal(chosen, selector.predict(theta, F[te], norm))
-    fixed = selector.best_fixed(T[tr])
-    r_net = selector.regret(T[te], chosen).mean()
-    r_fix = selector.regret(T[te], np.full(te.size, fixed)).mean()
-    r_plain = selector.regret(T[te], np.zeros(te.size, int)).mean()
-    print(f"held-out mean regret: network {r_net:.3f}, best fixed {selector.choice_name(fixed)} {r_fix:.3f}, "
-          f"plain {r_plain:.3f}; settings {settings}")
-    assert r_net <= r_fix + 0.03 and r_net <= r_plain + 1e-9, (r_net, r_fix, r_plain)
 
 
 def test_exhaustive_timing_from_given_trees():
