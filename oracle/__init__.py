@@ -238,7 +238,7 @@ def canonical_rowcol(A, r2p, r2leaf, K, nleaves=None):
     r2leaf[i] the leaf of a part row (leaves numbered part-major).
 
     Rows: by part (border last), then by leaf, then by original index.
-    Columns, judged over the non-border rows that touch them: a column touched
+    Columns, classified by the non-border rows that touch them: a column touched
     by one leaf goes with that leaf, a column touched by several leaves of one
     part goes after that part's leaf columns, and every other column (touched
     by several parts, or by none) goes to the column border C_B at the end.

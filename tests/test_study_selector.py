@@ -1,4 +1,4 @@
-"""The learned choice on measured timings, judged on matrices it never saw.
+"""The learned choice on measured timings, evaluated on matrices it never saw.
 
 A statistical end-to-end study rather than a parity check, so it sits in a
 file of its own that is collected after the parity tests."""
