@@ -639,6 +639,91 @@ def main_selector(args, torch, spx):
     print(json.dumps(line), flush=True)
 
 
+def gather_requests(P, line_entries=16, max_nnz=None):
+    """Model of the L1 -> L2 requests of a plan's x gathers: distinct cache
+    lines (line_entries binary64 entries each; 16 for 128-byte lines) per
+    gather instruction of 16 lanes (a quarter wave) and of 64 lanes (a wave),
+    over the multi-row blocks of the plan's schedule, per gathered nonzero.
+    Row order follows spmv_blocks: thread t of a block loads the 4
+    consecutive entries from the aligned start zb + 4 t (+ 4 WG per further
+    round) and the j-th gather of its lanes reads the j-th of them; the
+    entries of the first aligned group that precede the block are gathered
+    too.  Gather-sorted order follows spmv_sorted: the block's own entries
+    sorted by column, the j-th gather of a quarter wave reading 16
+    consecutive sorted entries and a wave covering four such runs, 64
+    entries apart.  Long-row segments are left out.  Returns a dict of the
+    four ratios and the counted nonzeros.  Host only."""
+    rowptr, col, _ = P.export_csr()
+    bd, _ = P.export_sched()
+    inf = P.info()
+    wg, npt = inf["wg_size"], inf["nnz_per_block"] // max(inf["wg_size"], 1)
+    line = col.astype(np.int64) // line_entries
+    req = {"row16": 0, "row64": 0, "sorted16": 0, "sorted64": 0}
+    cnt = {"row": 0, "sorted": 0}
+
+    def distinct(L, group):
+        # L: (instructions, lanes) line ids, -1 for lanes without an entry
+        L = np.sort(L.reshape(-1, group), axis=1)
+        new = np.ones(L.shape, bool)
+        new[:, 1:] = L[:, 1:] != L[:, :-1]
+        return int(np.count_nonzero(new & (L >= 0)))
+
+    for s0, s1, z0, z1 in bd:
+        if s1 < 0 or z1 <= z0:
+            continue
+        zb = z0 & ~3
+        # row order: entry zb + 4 g + j for 16-byte group g = u WG + t
+        ng = (z1 - zb + 3) // 4
+        G = np.full(npt // 4 * wg * 4, -1, np.int64)
+        G[:z1 - zb] = line[zb:z1]
+        G = G.reshape(npt // 4, wg // 64, 64, 4)      # round, wave, lane, j
+        R = G.transpose(0, 1, 3, 2)                     # instruction (round, wave, j) x lane
+        req["row16"] += distinct(R, 16)
+        req["row64"] += distinct(R, 64)
+        cnt["row"] += z1 - zb
+        # gather-sorted order: chunks of 64 sorted entries, quarter q of a
+        # wave reading chunk 4 w + q, its j-th gather entries 16 j .. 16 j + 15
+        S = np.sort(line[z0:z1])
+        nc = (S.size + 63) // 64
+        nw = (nc + 3) // 4
+        C = np.full(nw * 4 * 64, -1, np.int64)
+        C[:S.size] = S
+        C = C.reshape(nw, 4, 4, 16)                     # wave, chunk (quarter), j, lane
+        Q = C.transpose(0, 2, 1, 3)                     # instruction (wave, j) x (quarter, lane)
+        req["sorted16"] += distinct(Q, 16)
+        req["sorted64"] += distinct(Q, 64)
+        cnt["sorted"] += S.size
+        if max_nnz is not None and cnt["sorted"] >= max_nnz:
+            break
+    out = {k: round(float(v) / max(int(cnt["row" if k.startswith("row") else "sorted"]), 1), 4)
+           for k, v in req.items()}
+    out["nnz_counted"] = int(cnt["sorted"])
+    return out
+
+
+def main_gather_model(args, spx):
+    """Modeled gather requests per nonzero of the DB form (K = 64) of the
+    n = 10^6 matrix in row order and in gather-sorted order, for the
+    workgroup row blocks of 2048 and 4096 entries (the latter as the
+    gather-sorted kernel cuts them) and the scan's fuller blocks of 4096
+    entries; host only, no GPU."""
+    A = load_c2(args.n)
+    M = spx.from_csr(A, device=False)
+    P, _, _, _ = spx.reorder_db(M, args.K, 0, args.seed, tune=dict(wg_size=512, nnz_per_block=2048))
+    rows = []
+    for tune in (dict(wg_size=512, nnz_per_block=2048), dict(wg_size=1024, nnz_per_block=4096, sort_gathers=1),
+                 dict(wg_size=1024, nnz_per_block=4096, scan_reduce=1)):
+        spx.plan_retune(P, tune)
+        r = gather_requests(P, max_nnz=args.model_nnz)
+        r["schedule"] = schedule_name(tune_list(tune))
+        rows.append(r)
+        log(f"gather model {r}")
+    line = {"workload": "gather request model", "form": "db", "K": args.K, "n": args.n, "line_bytes": 128,
+            "rows": rows}
+    print(json.dumps(line))
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -664,7 +749,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--cold", action="store_true",
                     help="also time 20 products per form, each after a 512 MB read that empties the caches")
-    ap.add_argument("--workload", default="spmv", choices=["spmv", "precision", "batched", "selector", "locality"],
+    ap.add_argument("--workload", default="spmv",
+                    choices=["spmv", "precision", "batched", "selector", "locality", "gather_model"],
                     help="spmv: repeated products on the n=10^6 matrix (default); precision: "
                          "binary32/bfloat16 products and refined CG on the n=5*10^5 SPD matrix")
     ap.add_argument("--train", type=int, default=60, help="selector: training matrices")
@@ -682,6 +768,8 @@ def main():
     ap.add_argument("--trees", default="",
                     help="selector: take the partitions from this folder (written by --save-trees) instead of "
                          "partitioning during the measurement")
+    ap.add_argument("--model-nnz", type=int, default=4_000_000,
+                    help="gather_model: nonzeros of the first blocks counted")
     ap.add_argument("--only-stream", action="store_true",
                     help="run only the 1 GiB stream read and copy kernels (counter calibration)")
     args = ap.parse_args()
@@ -695,6 +783,9 @@ def main():
     import paper_1203_2739_amd as spx
     from synth import gen_vectors
 
+    if args.workload == "gather_model":
+        spx.set_num_threads(min(16, os.cpu_count() or 1))
+        return main_gather_model(args, spx)  # host only
     if args.workload == "selector" and args.save_trees:
         spx.set_num_threads(min(16, os.cpu_count() or 1))
         return main_selector(args, torch, spx)  # host partitions only

@@ -145,3 +145,31 @@ def test_locality_matrices():
     # spatial runs start anywhere: no reuse of columns between neighbouring rows
     cs = mats["spatial"].colidx.reshape(n, deg).astype(np.int64)
     assert np.mean(np.abs(cs[1:, 0] - cs[:-1, 0]) > deg) > 0.99
+
+
+def test_gather_request_model_on_a_hand_counted_block():
+    """32 rows of 64 nonzeros, all on columns 0..63 (four 128-byte lines of
+    x); the 8 row groups give 8 blocks of 4 rows (256 entries) at 512 x 4.
+    Row order: the j-th gather of quarter wave q reads columns 4 m + j of
+    row q (m < 16), four lines; the four quarters read the same four lines,
+    so a wave instruction needs 4 and a quarter 4: 0.25 and 0.0625 requests
+    per nonzero.  Sorted order: every column four times; 16 consecutive
+    sorted entries cover columns 4 a .. 4 a + 3, one line, and the four
+    runs of a wave instruction (columns 16 q + 4 j ..) four lines: 0.0625
+    both ways."""
+    import bench
+    import paper_1203_2739_amd as spx
+    m = 32
+    rowptr = np.arange(0, 64 * m + 1, 64, dtype=np.int32)
+    colidx = np.tile(np.arange(64, dtype=np.int32), m)
+    M = spx.csr_create_host(m, 64, rowptr, colidx, np.ones(64 * m))
+    P = spx.plan_plain(M, tune=dict(wg_size=512, nnz_per_block=2048))
+    bd, _ = P.export_sched()
+    assert bd.shape[0] == 8 and np.all(bd[:, 1] - bd[:, 0] == 4)
+    r = bench.gather_requests(P)
+    assert r["nnz_counted"] == 64 * m
+    assert (r["row16"], r["row64"], r["sorted16"], r["sorted64"]) == (0.25, 0.0625, 0.0625, 0.0625)
+    # one request per nonzero when every entry has a line of its own
+    M2 = spx.csr_create_host(m, 64 * 16, rowptr, (colidx * 16).astype(np.int32), np.ones(64 * m))
+    r2 = bench.gather_requests(spx.plan_plain(M2, tune=dict(wg_size=512, nnz_per_block=2048)))
+    assert (r2["row16"], r2["row64"]) == (1.0, 0.25)
