@@ -701,6 +701,34 @@ def gather_requests(P, line_entries=16, max_nnz=None):
     return out
 
 
+def block_fill(P):
+    """Share of a schedule's load slots that its blocks fill: the entries
+    every block (or long-row segment) loads from its aligned start, over the
+    blocks' capacity (nnz_per_block each).  Host only."""
+    bd, _ = P.export_sched()
+    cap = P.info()["nnz_per_block"]
+    load = (bd[:, 3].astype(np.int64) - (bd[:, 2] & ~3)).sum()
+    return round(float(load) / max(bd.shape[0] * cap, 1), 4)
+
+
+def reduction_chain(P):
+    """Median over the multi-row blocks of a lane-group schedule of the
+    dependent LDS reads of its longest row: ceil(length / lanes), a row
+    being summed by 2^floor(log2(WG / rows)) lanes, at most 64.  Host only."""
+    bd, _ = P.export_sched()
+    rp = P.export_csr()[0].astype(np.int64)
+    wg = P.info()["wg_size"]
+    chain = []
+    for s0, s1, _, _ in bd[bd[:, 1] >= 0]:
+        nr = int(s1 - s0)
+        longest = int((rp[s0 + 1:s1 + 1] - rp[s0:s1]).max())
+        lanes = 1
+        while lanes * 2 <= wg // nr and lanes < 64:
+            lanes *= 2
+        chain.append(-(-longest // lanes))
+    return float(np.median(chain)) if chain else 0.0
+
+
 def main_gather_model(args, spx):
     """Modeled gather requests per nonzero of the DB form (K = 64) of the
     n = 10^6 matrix in row order and in gather-sorted order, for the
@@ -718,8 +746,14 @@ def main_gather_model(args, spx):
         r["schedule"] = schedule_name(tune_list(tune))
         rows.append(r)
         log(f"gather model {r}")
+    # how full the blocks of plain CSR are with and without the scan's rule
+    fill = {}
+    for tune in (dict(wg_size=512, nnz_per_block=2048), dict(wg_size=512, nnz_per_block=2048, scan_reduce=1)):
+        fill[schedule_name(tune_list(tune))] = block_fill(spx.plan_plain(M, tune=tune))
+    chain = reduction_chain(spx.plan_plain(M, tune=dict(wg_size=512, nnz_per_block=2048)))
+    log(f"plain CSR block fill {fill}, median reduction chain at 512x4 {chain}")
     line = {"workload": "gather request model", "form": "db", "K": args.K, "n": args.n, "line_bytes": 128,
-            "rows": rows}
+            "rows": rows, "plain_block_fill": fill, "plain_median_reduction_chain": chain}
     print(json.dumps(line))
     return line
 

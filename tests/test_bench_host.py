@@ -169,6 +169,10 @@ def test_gather_request_model_on_a_hand_counted_block():
     r = bench.gather_requests(P)
     assert r["nnz_counted"] == 64 * m
     assert (r["row16"], r["row64"], r["sorted16"], r["sorted64"]) == (0.25, 0.0625, 0.0625, 0.0625)
+    assert bench.block_fill(P) == 256 / 2048
+    # 4 rows of 64 in a block of 512 threads: 128 lanes a row, capped at 64,
+    # so one read of the row's partial sums
+    assert bench.reduction_chain(P) == 1.0
     # one request per nonzero when every entry has a line of its own
     M2 = spx.csr_create_host(m, 64 * 16, rowptr, (colidx * 16).astype(np.int32), np.ones(64 * m))
     r2 = bench.gather_requests(spx.plan_plain(M2, tune=dict(wg_size=512, nnz_per_block=2048)))
