@@ -639,6 +639,16 @@ def main_selector(args, torch, spx):
     print(json.dumps(line), flush=True)
 
 
+def stored_rows(P):
+    """(row pointers over the stored rows, their column indices) of any plan:
+    the reordered CSR, or for the split the per-leaf slots."""
+    if P.info()["form_name"] == "split":
+        S = P.export_split()
+        return S["slot_ptr"], S["colidx"]
+    rp, col, _ = P.export_csr()
+    return rp, col
+
+
 def gather_requests(P, line_entries=16, max_nnz=None):
     """Model of the L1 -> L2 requests of a plan's x gathers: distinct cache
     lines (line_entries binary64 entries each; 16 for 128-byte lines) per
@@ -653,7 +663,7 @@ def gather_requests(P, line_entries=16, max_nnz=None):
     consecutive sorted entries and a wave covering four such runs, 64
     entries apart.  Long-row segments are left out.  Returns a dict of the
     four ratios and the counted nonzeros.  Host only."""
-    rowptr, col, _ = P.export_csr()
+    _, col = stored_rows(P)
     bd, _ = P.export_sched()
     inf = P.info()
     wg, npt = inf["wg_size"], inf["nnz_per_block"] // max(inf["wg_size"], 1)
@@ -716,7 +726,7 @@ def reduction_chain(P):
     dependent LDS reads of its longest row: ceil(length / lanes), a row
     being summed by 2^floor(log2(WG / rows)) lanes, at most 64.  Host only."""
     bd, _ = P.export_sched()
-    rp = P.export_csr()[0].astype(np.int64)
+    rp = stored_rows(P)[0].astype(np.int64)
     wg = P.info()["wg_size"]
     chain = []
     for s0, s1, _, _ in bd[bd[:, 1] >= 0]:
@@ -734,7 +744,8 @@ def main_gather_model(args, spx):
     n = 10^6 matrix in row order and in gather-sorted order, for the
     workgroup row blocks of 2048 and 4096 entries (the latter as the
     gather-sorted kernel cuts them) and the scan's fuller blocks of 4096
-    entries; host only, no GPU."""
+    entries, and of the split at 1024 x 4 gather-sorted; block fill and
+    reduction chain of plain CSR; host only, no GPU."""
     A = load_c2(args.n)
     M = spx.from_csr(A, device=False)
     P, _, _, _ = spx.reorder_db(M, args.K, 0, args.seed, tune=dict(wg_size=512, nnz_per_block=2048))
@@ -744,15 +755,24 @@ def main_gather_model(args, spx):
         spx.plan_retune(P, tune)
         r = gather_requests(P, max_nnz=args.model_nnz)
         r["schedule"] = schedule_name(tune_list(tune))
+        r["form"] = "db"
         rows.append(r)
         log(f"gather model {r}")
+    # the split (128 KB leaves) under the schedule its autotuning keeps
+    tune = dict(wg_size=1024, nnz_per_block=4096, sort_gathers=1)
+    P, _, _, _ = spx.split(M, args.K, args.window_bytes, args.seed, tune=tune)
+    r = gather_requests(P, max_nnz=args.model_nnz)
+    r["schedule"] = schedule_name(tune_list(tune))
+    r["form"] = "split"
+    rows.append(r)
+    log(f"gather model {r}")
     # how full the blocks of plain CSR are with and without the scan's rule
     fill = {}
     for tune in (dict(wg_size=512, nnz_per_block=2048), dict(wg_size=512, nnz_per_block=2048, scan_reduce=1)):
         fill[schedule_name(tune_list(tune))] = block_fill(spx.plan_plain(M, tune=tune))
     chain = reduction_chain(spx.plan_plain(M, tune=dict(wg_size=512, nnz_per_block=2048)))
     log(f"plain CSR block fill {fill}, median reduction chain at 512x4 {chain}")
-    line = {"workload": "gather request model", "form": "db", "K": args.K, "n": args.n, "line_bytes": 128,
+    line = {"workload": "gather request model", "K": args.K, "n": args.n, "line_bytes": 128,
             "rows": rows, "plain_block_fill": fill, "plain_median_reduction_chain": chain}
     print(json.dumps(line))
     return line

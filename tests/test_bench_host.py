@@ -173,6 +173,11 @@ def test_gather_request_model_on_a_hand_counted_block():
     # 4 rows of 64 in a block of 512 threads: 128 lanes a row, capped at 64,
     # so one read of the row's partial sums
     assert bench.reduction_chain(P) == 1.0
+    # the split's per-leaf storage is read through its slots
+    Ps, _, _, _ = spx.split(M, 2, 0, 0, tune=dict(wg_size=512, nnz_per_block=2048))
+    rs = bench.gather_requests(Ps)
+    assert rs["nnz_counted"] == 64 * m and 0 < rs["sorted64"] <= rs["row16"] <= 1
+    assert bench.reduction_chain(Ps) >= 1
     # one request per nonzero when every entry has a line of its own
     M2 = spx.csr_create_host(m, 64 * 16, rowptr, (colidx * 16).astype(np.int32), np.ones(64 * m))
     r2 = bench.gather_requests(spx.plan_plain(M2, tune=dict(wg_size=512, nnz_per_block=2048)))
