@@ -591,11 +591,13 @@ spx_status spx_select_exhaustive_trees(spx_mat A, const int32_t *tree_sb, const 
  * Inspection (host arrays, caller-allocated; any pointer may be NULL).
  *
  * spx_plan_export_csr: the stored matrix of a plain/SB/DB plan in CSR:
- *   rowptr[m+1], colidx[nnz], vals[nnz] (A itself for plain, A_hat else).
+ *   rowptr[m+1], colidx[nnz], vals[nnz] (A itself for plain, A_hat else);
+ *   SPX_EUNSUPPORTED for a split plan.
  * spx_plan_export_split: the per-leaf GCSR storage of a split plan in
  *   reordered coordinates (GCSR = CSR plus the list of non-empty rows,
  *   Section 5.2): leaf_slot_ptr[nleaves+1], slot_row[nslots],
- *   slot_ptr[nslots+1], colidx[nnz], vals[nnz].
+ *   slot_ptr[nslots+1], colidx[nnz], vals[nnz]; SPX_EUNSUPPORTED for the
+ *   other forms.
  * spx_plan_export_parts: the partition itself.  SB/DB: r2p[m] (part of each
  *   original row, K for R_B) and r2leaf[m] (leaf, -1 for R_B).  Split:
  *   nz_part[nnz] and nz_leaf[nnz] in A's CSR order.

@@ -800,3 +800,16 @@ def test_compact_indices(orc, form):
                 dict(compact_index=1, blocks_per_tile=4), dict(compact_index=1, wg_size=1024)):
         with pytest.raises(spx.SpxError):
             spx.plan_plain(M, tune=bad)
+
+
+def test_exports_refuse_the_other_storage():
+    """A split plan stores per-leaf GCSR and has no CSR export; a plain plan
+    has no split export; a plan without the gather-sorted or 16-bit copy
+    has neither export (SPX_EUNSUPPORTED, -5)."""
+    M = spx.from_csr(small_csr(), device=False)
+    Ps, _, _, _ = spx.split(M, 2)
+    Pp = spx.plan_plain(M)
+    for call in (Ps.export_csr, Pp.export_split, Pp.export_gather_order, Pp.export_compact):
+        with pytest.raises(spx.SpxError) as e:
+            call()
+        assert e.value.code == -5, call
