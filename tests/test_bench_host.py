@@ -182,3 +182,20 @@ def test_gather_request_model_on_a_hand_counted_block():
     M2 = spx.csr_create_host(m, 64 * 16, rowptr, (colidx * 16).astype(np.int32), np.ones(64 * m))
     r2 = bench.gather_requests(spx.plan_plain(M2, tune=dict(wg_size=512, nnz_per_block=2048)))
     assert (r2["row16"], r2["row64"]) == (1.0, 0.25)
+
+
+def test_gather_model_workload_runs_on_the_host():
+    """bench.py --workload gather_model needs no GPU: at n = 20,000 it prints
+    one JSON line with the DB rows, the split row and the block measures,
+    every sorted figure at most its row-order one."""
+    import json
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "gather_model", "--n", "20000",
+                        "--model-nnz", "100000"], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert [(x["form"], x["schedule"]) for x in line["rows"]] == [
+        ("db", "512x4"), ("db", "1024x4g"), ("db", "1024x4s"), ("split", "1024x4g")]
+    for x in line["rows"]:
+        assert 0 < x["sorted64"] <= x["sorted16"] <= x["row16"] <= 1 and x["row64"] <= x["row16"]
+    assert 0 < line["plain_block_fill"]["512x4"] < line["plain_block_fill"]["512x4s"] <= 1
+    assert line["plain_median_reduction_chain"] >= 1
